@@ -1,0 +1,26 @@
+"""CPU FP64 oracle for the RGF hot path -- TEST INFRASTRUCTURE ONLY.
+
+Plain, slow, obviously correct NumPy code written from the paper's statement of
+the NEGF problem (Eqs. 1-8).  It shares no code with the HIP path and never
+imports it.  Only the tests, the smoke check and the CPU-baseline leg of the
+benchmark may import it; the product path must never route through it.
+
+Parity status of each function is stated in its docstring ("pinned by ..." or
+"parity unpinned").
+"""
+from .negf_oracle import (  # noqa: F401
+    fermi,
+    norm1,
+    sancho_rubio,
+    lead_selfenergy,
+    lead_lesser,
+    rgf,
+    dense,
+    scba_selfenergy,
+    solve_points,
+    lead_tables,
+    scba,
+    observables,
+    dense_grad,
+    density_objective,
+)

@@ -1,0 +1,367 @@
+"""Pins of the CPU oracle against what mathematics and the paper fix.
+
+Each test ties one oracle function to something other than itself: the plain
+dense definition of Eqs. (1)-(2), closed forms of simple leads, Landauer
+transmission of ordered strips, exact identities (spectral, eta-sink current,
+equilibrium detailed balance, elastic current conservation), reciprocity,
+finite differences, and the paper's printed sizes.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from synth import make_workload, random_tiny, strip_workload
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _leads(wl, ik, E, **kw):
+    z = E + 1j * wl.eta
+    sL, itL, cL = O.lead_selfenergy(wl.lead_h00[ik], wl.lead_h01_L, wl.lead_tau_L, z, **kw)
+    sR, itR, cR = O.lead_selfenergy(wl.lead_h00[ik], wl.lead_h01_R, wl.lead_tau_R, z, **kw)
+    assert cL and cR
+    return sL, sR
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(b)), 1e-300))
+
+
+# --------------------------------------------------------------------------
+# RGF vs the plain dense definition (Eqs. 1-2)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("nb,N,up,seed", [(1, 1, None, 0), (3, 1, None, 1), (5, 2, None, 2),
+                                          (6, 5, None, 3), (8, 4, 2, 4), (12, 6, 4, 5)])
+def test_rgf_matches_dense_inversion(nb, N, up, seed):
+    wl = random_tiny(nb, N, n_e=3, seed=seed, up_block=up, eta=1e-3)
+    rng = np.random.default_rng(seed)
+    hd, hu, _ = wl.sample_blocks(0, 0)
+    v = [rng.uniform(0, 0.3, nb) for _ in range(N)]
+    scatR = [rng.normal(size=nb) * 0.02 - 0.02j * rng.uniform(size=nb) for _ in range(N)]
+    scatL = [0.03j * rng.uniform(size=nb) for _ in range(N)]
+    for E in wl.energy:
+        sL, sR = _leads(wl, 0, E)
+        r = O.rgf(hd, hu, E, wl.eta, sL, sR, 0.8, 0.3, v=v, scatR=scatR, scatL=scatL, transmission=True)
+        d = O.dense(hd, hu, E, wl.eta, sL, sR, 0.8, 0.3, v=v, scatR=scatR, scatL=scatL)
+        for key in ("GR", "GL", "GG"):
+            assert _rel(r[key], d[key]) < 1e-12, key
+        if N > 1:
+            assert _rel(r["bond"], d["bond"]) < 1e-11
+        assert abs(r["T"] - d["T"]) <= 1e-12 * max(1.0, abs(d["T"]))
+
+
+def test_rgf_matches_dense_on_strip_workload():
+    wl = make_workload("C1", n_e=32)
+    hd, hu, _ = wl.sample_blocks(0, 0)
+    for E in wl.energy[::3]:
+        sL, sR = _leads(wl, 0, E)
+        fL, fR = O.fermi(E, wl.mu_L, wl.kT), O.fermi(E, wl.mu_R, wl.kT)
+        r = O.rgf(hd, hu, E, wl.eta, sL, sR, fL, fR, transmission=True)
+        d = O.dense(hd, hu, E, wl.eta, sL, sR, fL, fR)
+        assert _rel(r["GR"], d["GR"]) < 1e-10
+        assert abs(r["T"] - d["T"]) < 1e-9
+
+
+# --------------------------------------------------------------------------
+# Sancho-Rubio vs closed forms
+# --------------------------------------------------------------------------
+
+def _chain_sigma(x, t):
+    """Self-energy t^2 g_s of a semi-infinite 1-D chain: (x - sqrt(x^2-4t^2))/2,
+    the root with |sigma| < |t| (decaying / retarded branch)."""
+    s = np.sqrt(x * x - 4 * t * t + 0j)
+    r1, r2 = (x - s) / 2, (x + s) / 2
+    return r1 if abs(r1) < abs(r2) else r2
+
+
+@pytest.mark.parametrize("E", [-2.7, -1.3, -0.2, 0.0, 0.9, 1.99 - 0.5, 2.6])
+def test_sancho_rubio_1d_chain_closed_form(E):
+    t, eps, eta = -1.0, 0.1, 1e-6
+    z = E + 1j * eta
+    h = np.array([[eps]], dtype=complex)
+    sig, it, conv = O.lead_selfenergy(h, np.array([[t]], dtype=complex), np.array([[t]], dtype=complex), z)
+    assert conv
+    ref = _chain_sigma(z - eps, t)
+    assert abs(sig[0, 0] - ref) < 1e-10 * max(1, abs(ref))
+    assert sig[0, 0].imag <= 0
+
+
+def test_sancho_rubio_strip_closed_form():
+    W, t, eta = 8, -1.0, 1e-6
+    wl = strip_workload(width=W, disorder=0.0, eta=eta)
+    m = np.arange(1, W + 1)
+    eps_m = 2 * t * np.cos(m * np.pi / (W + 1))
+    U = np.sqrt(2.0 / (W + 1)) * np.sin(np.outer(np.arange(1, W + 1), m) * np.pi / (W + 1))
+    for E in np.linspace(-3.9, 3.9, 23):
+        if np.min(np.abs(np.abs(E - eps_m) - 2)) < 1e-3:
+            continue
+        z = E + 1j * eta
+        sL, sR = _leads(wl, 0, E)
+        ref = U @ np.diag([_chain_sigma(z - e, t) for e in eps_m]) @ U.T
+        assert np.max(np.abs(sL - ref)) < 1e-10
+        assert np.max(np.abs(sR - ref)) < 1e-10
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_sancho_rubio_surface_dyson_fixed_point(seed):
+    wl = random_tiny(6, 2, n_e=3, seed=seed, eta=1e-4)
+    for E in wl.energy:
+        z = E + 1j * wl.eta
+        for h01 in (wl.lead_h01_L, wl.lead_h01_R):
+            gs, it, conv = O.sancho_rubio(wl.lead_h00[0], h01, z)
+            assert conv
+            rhs = np.linalg.inv(z * np.eye(6) - wl.lead_h00[0] - h01 @ gs @ h01.conj().T)
+            assert np.max(np.abs(gs - rhs)) < 1e-8 * np.max(np.abs(gs))  # conditioning ~ 1/eta
+            sig = wl.lead_tau_L @ gs @ wl.lead_tau_L.conj().T
+            gam = 1j * (sig - sig.conj().T)
+            assert np.min(np.linalg.eigvalsh(gam)) > -1e-10
+
+
+def test_sancho_rubio_flags_iteration_cap():
+    wl = random_tiny(4, 2, n_e=1, seed=3, eta=1e-6)
+    _, it, conv = O.sancho_rubio(wl.lead_h00[0], wl.lead_h01_R, wl.energy[0] + 1e-6j, max_iter=1)
+    assert it == 1 and not conv
+
+
+# --------------------------------------------------------------------------
+# Transmission: integer steps of ordered strips (Landauer)
+# --------------------------------------------------------------------------
+
+def test_ordered_strip_integer_transmission():
+    W, t = 8, -1.0
+    # eta -> 0 limit: the O(eta N / v) absorption of the device eta is < 1e-6 here
+    wl = strip_workload(width=W, disorder=0.0, n_slab=20, eta=1e-9)
+    hd, hu, _ = wl.sample_blocks(0, 0)
+    eps_m = 2 * t * np.cos(np.arange(1, W + 1) * np.pi / (W + 1))
+    checked = 0
+    for E in wl.energy:
+        dist = np.min(np.abs(np.abs(E - eps_m) - 2 * abs(t)))
+        if dist < 0.05:
+            continue
+        sL, sR = _leads(wl, 0, E, max_iter=200)
+        r = O.rgf(hd, hu, E, wl.eta, sL, sR, 1.0, 0.0, transmission=True)
+        n_open = int(np.sum(np.abs(E - eps_m) < 2 * abs(t)))
+        assert abs(r["T"] - n_open) < 1e-5, (E, r["T"], n_open)
+        checked += 1
+    assert checked > 150
+
+
+def test_bond_current_equals_landauer():
+    """Ballistic, eta -> 0: every bond current equals T (f_L - f_R)."""
+    wl = random_tiny(4, 6, n_e=3, seed=2, eta=1e-9)
+    hd, hu, _ = wl.sample_blocks(0, 0)
+    for E in wl.energy:
+        sL, sR = _leads(wl, 0, E, max_iter=200)
+        r = O.rgf(hd, hu, E, wl.eta, sL, sR, 0.9, 0.2, transmission=True)
+        assert np.max(np.abs(r["bond"] - r["T"] * 0.7)) < 1e-6 * max(r["T"], 1e-3)
+
+
+def test_eta_sink_current_identity():
+    """Exact at any eta: j_{i-1} - j_i = 2 eta Tr(-i G^<_ii) (current lost into the
+    eta contact of slab i)."""
+    wl = random_tiny(5, 7, n_e=3, seed=6, eta=2e-2)
+    hd, hu, _ = wl.sample_blocks(0, 0)
+    for E in wl.energy:
+        sL, sR = _leads(wl, 0, E)
+        r = O.rgf(hd, hu, E, wl.eta, sL, sR, 0.95, 0.1)
+        j = r["bond"]
+        for i in range(1, 6):
+            sink = 2 * wl.eta * np.real(np.trace(-1j * r["GL"][i]))
+            assert abs((j[i - 1] - j[i]) - sink) < 1e-12 * max(1, np.max(np.abs(j)))
+
+
+def test_spectral_identity_via_lesser_recursion():
+    """With every contact filled (f = 1, including eta and scattering),
+    Sigma^< = i Gamma_total and the lesser recursion must return
+    G^< = i A = -(G - G^dagger) blockwise, i.e. G^> = 0."""
+    wl = random_tiny(6, 5, n_e=3, seed=7, eta=1e-3)
+    rng = np.random.default_rng(7)
+    hd, hu, _ = wl.sample_blocks(0, 0)
+    scatR = [rng.normal(size=6) * 0.02 - 0.05j * rng.uniform(size=6) for _ in range(5)]
+    scatL = [-2j * np.imag(s) for s in scatR]     # i * Gamma_scat, Gamma = -2 Im Sigma^R
+    for E in wl.energy:
+        sL, sR = _leads(wl, 0, E)
+        r = O.rgf(hd, hu, E, wl.eta, sL, sR, 1.0, 1.0, scatR=scatR, scatL=scatL, eta_fill=1.0)
+        A = -(r["GR"] - np.conj(np.transpose(r["GR"], (0, 2, 1))))
+        assert _rel(r["GL"], A) < 1e-12
+        assert np.max(np.abs(r["GG"])) < 1e-11 * np.max(np.abs(r["GR"]))
+
+
+def test_reciprocity_k_minus_k():
+    """Real-symmetric couplings, no magnetic field: G(-k) = G(k)^T blockwise;
+    at k = 0 and k = pi, G = G^T."""
+    wl = make_workload("C2", n_slab=3, n_e=2, n_k=4, n_z=2, n_y=2)
+    pts = [(0, ik, ie) for ik in range(4) for ie in range(2)]
+    res = O.solve_points(wl, pts)
+    R = {(p[1], p[2]): r for p, r in zip(pts, res)}
+    for ie in range(2):
+        for k, mk in ((1, 3), (0, 0), (2, 2)):
+            a = R[(k, ie)]["GR"]
+            b = np.transpose(R[(mk, ie)]["GR"], (0, 2, 1))
+            assert _rel(a, b) < 1e-10
+
+
+# --------------------------------------------------------------------------
+# Scattering self-energies (Eqs. 4-6) and SCBA
+# --------------------------------------------------------------------------
+
+def _tiny_scba_workload(seed, n_e, shift, D, M, n_k=2):
+    wl = random_tiny(4, 4, n_e=n_e, seed=seed, eta=1e-3, complex_h=False, n_k=n_k)
+    wl.energy = np.linspace(-1.0, 1.0, n_e)
+    wl.w_e = np.full(n_e, wl.energy[1] - wl.energy[0])
+    # k-dependent device and lead blocks, still Hermitian
+    rng = np.random.default_rng(seed + 100)
+    y = rng.normal(size=(4, 4)) * 0.1
+    for ik, k in enumerate(2 * np.pi * np.arange(n_k) / n_k):
+        wl.h_diag[ik] = wl.h_diag[0].real + np.exp(1j * k) * y + np.exp(-1j * k) * y.T
+        wl.lead_h00[ik] = wl.lead_h00[0].real + np.exp(1j * k) * y + np.exp(-1j * k) * y.T
+    wl.kpts = 2 * np.pi * np.arange(n_k) / n_k
+    wl.D_ac, wl.M_op, wl.shift = D, M, shift
+    wl.kT = 0.05
+    wl.n_bose = 1.0 / np.expm1(shift * (wl.energy[1] - wl.energy[0]) / wl.kT) if shift else 0.0
+    return wl
+
+
+def test_kms_equilibrium_every_scba_iterate():
+    """mu_L = mu_R, lead T = phonon T, eta contact filled: G^< = -f (G^R - G^A)
+    holds at every SCBA iterate (detailed balance of each +-hw group, including
+    the groups dropped at the grid ends)."""
+    wl = _tiny_scba_workload(seed=11, n_e=9, shift=2, D=0.05, M=0.08)
+    wl.mu_L = wl.mu_R = 0.1
+    leads = O.lead_tables(wl)
+    pts = [(0, ik, ie) for ik in range(wl.n_k) for ie in range(wl.n_e)]
+    scatR = np.zeros((wl.n_e, 4, 4), dtype=complex)
+    scatL = np.zeros_like(scatR)
+    for it in range(4):
+        res = O.solve_points(wl, pts, leads, scatR, scatL, eta_fill=wl.mu_L)
+        for (s, ik, ie), r in zip(pts, res):
+            f = O.fermi(wl.energy[ie], wl.mu_L, wl.kT)
+            A = r["GR"] - np.conj(np.transpose(r["GR"], (0, 2, 1)))
+            # roundoff scales with |A| (not with f |A|, which is tiny above mu)
+            assert np.max(np.abs(r["GL"] + f * A)) < 1e-10 * np.max(np.abs(A)), (it, ik, ie)
+        GRd = np.array([np.diagonal(r["GR"], axis1=1, axis2=2) for r in res]).reshape(wl.n_k, wl.n_e, 4, 4)
+        GLd = np.array([np.diagonal(r["GL"], axis1=1, axis2=2) for r in res]).reshape(wl.n_k, wl.n_e, 4, 4)
+        scatR, scatL = O.scba_selfenergy(GRd, GLd, wl.w_k, wl.D_ac, wl.M_op, wl.shift, wl.n_bose)
+        assert np.max(np.abs(scatL)) > 0
+
+
+def test_optical_selfenergy_detailed_balance_identity():
+    """Per group, f(E) (1 + n0 - f(E - hw)) = n0 f(E - hw) (and its +hw mirror)."""
+    kT, hw = 0.025852, 0.06
+    n0 = 1.0 / np.expm1(hw / kT)
+    for E in np.linspace(-0.3, 0.3, 13):
+        f, fm, fp = (O.fermi(x, 0.0, kT) for x in (E, E - hw, E + hw))
+        assert abs(f * (1 + n0 - fm) - n0 * fm) < 1e-15
+        assert abs(f * (n0 + fp) - (1 + n0) * fp) < 1e-15
+
+
+def test_elastic_scattering_conserves_current():
+    """Acoustic (elastic, local) scattering at SCBA convergence: per energy the
+    k-summed current divergence equals only the eta-sink loss."""
+    # Undamped SCBA is a contraction only when D |G| is small; eta = 0.05 keeps it so.
+    wl = _tiny_scba_workload(seed=12, n_e=3, shift=0, D=0.05, M=0.0)
+    wl.eta = 0.05
+    wl.mu_L, wl.mu_R = 0.3, -0.3
+    out = O.scba(wl, 200, eta_fill=None, tol=1e-13)
+    assert out["hist"][-1] < 1e-12
+    res = out["res"]
+    for ie in range(wl.n_e):
+        div = np.zeros(2)
+        for ik in range(wl.n_k):
+            r = res[ik * wl.n_e + ie]
+            j = r["bond"]
+            for i in range(1, 3):       # interior slabs of the 4-slab device
+                sink = 2 * wl.eta * np.real(np.trace(-1j * r["GL"][i]))
+                div[i - 1] += wl.w_k[ik] * ((j[i - 1] - j[i]) - sink)
+        jmax = max(abs(res[ik * wl.n_e + ie]["bond"]).max() for ik in range(wl.n_k))
+        assert np.max(np.abs(div)) < 1e-10 * max(jmax, 1e-12)
+
+
+def test_scattering_changes_current():
+    """The paper's Fig. 2 claim in its weakest form: phonon scattering changes
+    the current relative to the ballistic solution."""
+    wl = _tiny_scba_workload(seed=13, n_e=7, shift=2, D=0.05, M=0.05)
+    out = O.scba(wl, 3)
+    b0 = O.solve_points(wl, [(0, 0, 3)])[0]["bond"]
+    b1 = out["res"][3]["bond"]
+    assert np.max(np.abs(b1 - b0)) > 1e-6 * np.max(np.abs(b0))
+
+
+# --------------------------------------------------------------------------
+# Observables (Eqs. 7-8)
+# --------------------------------------------------------------------------
+
+def test_density_sum_rule():
+    """With every contact filled, Im G^< = A and sum_E w_E A_oo / 2pi -> 1 per
+    orbital: the total density is g_s x (number of orbitals), up to the
+    Lorentzian tails outside the energy window."""
+    wl = random_tiny(3, 3, n_e=1, seed=21, eta=0.02)
+    E = np.arange(-12.0, 12.0, 0.004)
+    hd, hu, _ = wl.sample_blocks(0, 0)
+    tot = np.zeros((3, 3))
+    for e in E:
+        sL, sR = _leads(wl, 0, e)
+        r = O.rgf(hd, hu, e, wl.eta, sL, sR, 1.0, 1.0, eta_fill=1.0)
+        tot += np.imag(np.diagonal(r["GL"], axis1=1, axis2=2))
+    wl.energy = np.array([0.0])
+    wl.w_e = np.array([0.004])
+    n, _, _ = O.observables(wl, [(0, 0, 0)], [1j * tot],
+                            [np.zeros(2)], g_s=2.0)
+    assert abs(n.sum() - 2.0 * 9) < 2.0 * 9 * 2e-3
+
+
+def test_current_observable_matches_landauer_integral():
+    wl = random_tiny(4, 5, n_e=6, seed=22, eta=1e-9)
+    wl.mu_L, wl.mu_R = 0.5, -0.5
+    pts = [(0, 0, ie) for ie in range(wl.n_e)]
+    leads = O.lead_tables(wl, max_iter=200)
+    res = O.solve_points(wl, pts, leads, transmission=True)
+    GLd = [np.diagonal(r["GL"], axis1=1, axis2=2) for r in res]
+    n, J, jE = O.observables(wl, pts, GLd, [r["bond"] for r in res])
+    ref = sum(wl.g_s * wl.w_e[ie] * r["T"] * (O.fermi(wl.energy[ie], 0.5, wl.kT) - O.fermi(wl.energy[ie], -0.5, wl.kT))
+              for ie, r in enumerate(res))
+    assert np.max(np.abs(J[:4] - ref)) < 1e-6 * abs(ref)
+
+
+# --------------------------------------------------------------------------
+# Differentiation: dense VJP vs finite differences
+# --------------------------------------------------------------------------
+
+def test_dense_grad_matches_finite_differences():
+    wl = make_workload("C5", n_slab=4, n_e=2, n_z=1, n_y=2)
+    wl.eta = 1e-3
+    pts = [(0, 0, ie) for ie in range(wl.n_e)]
+    leads = O.lead_tables(wl)
+    rng = np.random.default_rng(5)
+    w = rng.normal(size=(wl.total_slabs, wl.atoms_per_slab))
+    v = wl.v_onsite.copy()
+    g = O.dense_grad(wl, w, v, pts, leads)
+    h = 1e-5
+    for (s, a) in [(0, 0), (1, 1), (3, 0), (2, 1)]:
+        vp, vm = v.copy(), v.copy()
+        vp[s, a * 10:(a + 1) * 10] += h
+        vm[s, a * 10:(a + 1) * 10] -= h
+        fd = (O.density_objective(wl, w, vp, pts, leads) - O.density_objective(wl, w, vm, pts, leads)) / (2 * h)
+        assert abs(fd - g[s, a]) < 1e-6 * np.max(np.abs(g)) + 1e-12
+
+
+# --------------------------------------------------------------------------
+# The paper's printed sizes
+# --------------------------------------------------------------------------
+
+def test_memory_model_matches_paper():
+    """One stored set of 200 diagonal blocks of 1200^2 complex doubles is the
+    paper's ~4.5 GB per (E,k) tuple; 24000 atoms x 10 orbitals = rank 240000."""
+    with open(os.path.join(GOLDEN, "paper_sizes.json")) as fh:
+        g = json.load(fh)
+    n_slab = g["atoms"] // (g["block_rows_6x10"] // g["orbitals_per_atom"])
+    assert n_slab == 200
+    assert g["atoms"] * g["orbitals_per_atom"] == g["matrix_rank"]
+    gb = n_slab * g["block_rows_6x10"] ** 2 * 16 / 1e9
+    assert abs(gb - g["memory_per_ek_tuple_GB_6x10"]) / g["memory_per_ek_tuple_GB_6x10"] < 0.03
+    wl_b = 12 * 10 * 10
+    assert wl_b == g["block_rows_6x10"]
