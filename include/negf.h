@@ -1,0 +1,234 @@
+/*
+ * negf.h -- C ABI of the MI355X (gfx950) recursive Green's function library.
+ *
+ * The library solves, for many independent (sample, k, E) points, the
+ * block-tridiagonal NEGF system of the paper's Eqs. (1)-(3):
+ *
+ *     G^R(k,E) = (E + i eta - H(k) - V - Sigma^R_lead - Sigma^R_scat)^-1      (Eq. 1)
+ *     G^<(k,E) = G^R Sigma^< G^R^dagger                                       (Eq. 2)
+ *
+ * by recursive Green's functions (RGF) over the slabs of the device, with
+ * ordered semi-infinite leads (Sancho-Rubio decimation), the acoustic and
+ * optical phonon self-energies of Eqs. (4)-(6) and the density and current
+ * of Eqs. (7)-(8).
+ *
+ * Conventions
+ * -----------
+ * - Complex numbers are interleaved {re, im} (torch.complex128 layout).
+ *   Matrices are dense, row-major, contiguous, nb x nb.
+ * - Unless stated otherwise every array pointer is a DEVICE pointer owned by
+ *   the caller; the library never frees caller memory and keeps no pointer to
+ *   it beyond the bound system (negf_bind).  Energies are in eV.
+ * - Every call is asynchronous on the caller's HIP stream (passed as void*,
+ *   NULL = default stream).  A context must not be used from two streams at
+ *   once.
+ * - Return codes: 0 = OK; < 0 = error detected on the host, nothing was
+ *   launched; > 0 = warning (results written).  Faults met inside kernels
+ *   (singular or non-finite pivots) set bits in a device status word that
+ *   negf_sync_status() returns and clears.
+ * - The hot calls (negf_rgf_forward / negf_rgf_backward /
+ *   negf_scba_selfenergy / negf_observables) allocate nothing and issue no
+ *   host<->device copies, so a caller may capture them into a HIP graph.
+ */
+#ifndef NEGF_H
+#define NEGF_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct negf_ctx negf_ctx;
+typedef struct { double re, im; } negf_c128;
+
+enum {
+    NEGF_OK = 0,
+    NEGF_EINVAL = -1,     /* bad argument */
+    NEGF_ESHAPE = -2,     /* sizes exceed the context configuration */
+    NEGF_ENOMEM = -3,     /* device allocation failed (negf_create / negf_bind only) */
+    NEGF_EHIP = -4,       /* a HIP runtime call failed */
+    NEGF_ESTATE = -5,     /* call order violated (e.g. no bound system) */
+    NEGF_WNOCONV = 1,     /* Sancho-Rubio hit max_iter for some point */
+    NEGF_WSINGULAR = 2,   /* a block inverse met an exactly zero pivot */
+    NEGF_WNONFINITE = 3,  /* a block inverse met a non-finite pivot */
+    NEGF_WFALLBACK = 4    /* mixed precision redid some block inverses in FP64 */
+};
+
+enum { NEGF_FP64 = 0, NEGF_MIXED = 1 };   /* negf_config.precision */
+
+/* negf_rgf_forward flags */
+enum { NEGF_WANT_TRANSMISSION = 1 };
+
+typedef struct {
+    int nb;           /* orbitals per slab (block size), >= 1 */
+    int n_slab_max;   /* largest slab count of any sample that will be bound */
+    int capacity;     /* points per negf_rgf_forward/backward call and per lead batch */
+    int precision;    /* NEGF_FP64, or NEGF_MIXED: FP32 MFMA block algebra with one
+                         FP64-residual Newton-Schulz step per block inverse */
+} negf_config;
+
+/* Create a context and allocate its device workspace (the only allocation of
+ * the hot path): two stores of capacity * n_slab_max blocks for the
+ * left-connected g^R and g^< plus per-point temporaries.
+ * Errors: NEGF_EINVAL (bad sizes), NEGF_ENOMEM. */
+int negf_create(const negf_config* cfg, negf_ctx** out);
+void negf_destroy(negf_ctx* ctx);
+
+/* Bytes of device workspace the context holds. */
+long long negf_workspace_bytes(const negf_ctx* ctx);
+
+/* Return and clear the device status word (synchronises `stream`).
+ * Returns NEGF_OK, or the warning code of the most severe bit set. */
+int negf_sync_status(negf_ctx* ctx, void* stream);
+const char* negf_error_string(int status);
+
+/*
+ * The block-tridiagonal device (Eq. 1).  Samples (alloy realisations) are
+ * concatenated along the slab axis; sample s owns global slabs
+ * [slab_offset[s], slab_offset[s+1]).
+ */
+typedef struct {
+    int nb;                          /* must equal negf_config.nb */
+    int n_samples;
+    const long long* slab_offset;    /* HOST [n_samples+1] */
+    int n_k, n_e;
+    const negf_c128* h_diag;         /* [n_k][total_slabs][nb][nb]  H_ii(k) (Hermitian) */
+    const negf_c128* h_up;           /* [n_kup][total_slabs][nb][nb] H_{i,i+1}; entry of a
+                                        sample's last slab unused.  H_{i+1,i} = H_{i,i+1}^dagger */
+    long long h_up_k_stride;         /* elements between k-points in h_up; 0 = shared by all k */
+    int up_block;                    /* H_{i,i+1} is block-diagonal with up_block x up_block
+                                        blocks (up_block divides nb, up_block <= 48); only
+                                        those blocks are read */
+    const double* v_onsite;          /* [total_slabs][nb] potential energy added to diag(H),
+                                        or NULL */
+    const double* energy;            /* [n_e] */
+    double eta;                      /* z = E + i eta in every diagonal block and in the leads */
+    double mu_L, mu_R, kT;           /* lead Fermi functions for Sigma^<_lead = i f Gamma */
+    int eta_fill;                    /* 0: the device eta is an empty sink; 1: filled with
+                                        f(E; mu_L, kT), Sigma^<_eta = 2 i eta f  (equilibrium) */
+} negf_system;
+
+/* Bind a system and a point set.  `points` is a HOST array [n_points][3] of
+ * (sample, ik, ie).  Uploads the descriptors (synchronously, so never inside a
+ * graph capture); the device pointers inside `sys` must stay valid while bound.
+ * Points should be ordered longest sample first: batched launches then cover
+ * only the active prefix of a range.
+ * Errors: NEGF_EINVAL, NEGF_ESHAPE (nb mismatch, n_slab > n_slab_max), NEGF_ENOMEM. */
+int negf_bind(negf_ctx* ctx, const negf_system* sys, int n_points, const int* points);
+
+/*
+ * Retarded self-energies of the two ordered semi-infinite leads (Eq. 3,
+ * Sigma_lead), by Sancho-Rubio decimation in complex FP64 (always FP64).
+ *   h00  [n_k][nb][nb]  principal-layer Hamiltonian of the lead
+ *   h01  [n_k][nb][nb]  coupling from a lead layer to the next layer deeper in the lead
+ *   tau  [n_k][nb][nb]  coupling from the device edge slab to the lead surface layer
+ *   energy [n_e] (device); z = E + i eta.
+ * Out: sigma [n_k][n_e][nb][nb] = tau g_s tau^dagger; iters [n_k][n_e] (device int,
+ * may be NULL) decimation steps used.  Stops per point when
+ * ||alpha||_1 + ||beta||_1 < tol ||h01||_1 or at max_iter.  Processes the grid in
+ * batches of `capacity` points and synchronises `stream` once per decimation step.
+ * Returns NEGF_WNOCONV if any point hit max_iter.  Errors: NEGF_EINVAL. */
+int negf_lead_selfenergy(negf_ctx* ctx, void* stream, int n_k,
+                         const negf_c128* h00, const negf_c128* h01, const negf_c128* tau,
+                         int n_e, const double* energy, double eta, double tol, int max_iter,
+                         negf_c128* sigma, int* iters);
+
+/*
+ * Forward (left-connected) RGF sweep over bound points [p0, p0+np), np <= capacity:
+ *   g_i   = (A_ii - H_{i,i-1} g_{i-1} H_{i-1,i})^-1                         (Eq. 1)
+ *   g^<_i = g_i (Sigma^<_i + H_{i,i-1} g^<_{i-1} H_{i-1,i}) g_i^dagger     (Eq. 2)
+ * with A_ii = (E + i eta) I - H_ii - diag(V_i) - diag(Sigma^R_scat,i) - Sigma_L (i=0)
+ * - Sigma_R (i=N-1) and Sigma^<_i = diag(Sigma^<_scat,i) + lead terms i f Gamma.
+ *   sigma_L, sigma_R  [n_k][n_e][nb][nb] lead self-energies (negf_lead_selfenergy)
+ *   scat_R, scat_L    [n_e][total_slabs][nb] orbital-diagonal scattering
+ *                     self-energies (Eqs. 4-6), or NULL (ballistic)
+ *   flags             NEGF_WANT_TRANSMISSION keeps the left-column chain G_{N,1}.
+ * g and g^< stay in the context for negf_rgf_backward.  Errors: NEGF_ESTATE,
+ * NEGF_EINVAL, NEGF_ESHAPE. */
+int negf_rgf_forward(negf_ctx* ctx, void* stream, int p0, int np,
+                     const negf_c128* sigma_L, const negf_c128* sigma_R,
+                     const negf_c128* scat_R, const negf_c128* scat_L, int flags);
+
+/*
+ * Backward sweep for the same points (after negf_rgf_forward):
+ *   G_ii   = g_i + g_i H_{i,i+1} G_{i+1,i+1} H_{i+1,i} g_i
+ *   G^<_ii = g^<_i + L G^<_{i+1} L^dagger + T - T^dagger,  L = g_i H_{i,i+1},
+ *            T = L G_{i+1} H_{i+1,i} g^<_i
+ *   G^>_ii = G^<_ii + G_ii - G_ii^dagger   (no greater-than recursion, Eq. 6 remark)
+ *   j_i    = 2 Re Tr[H_{i,i+1} G^<_{i+1,i}]  bond current (units e/h per spin, Eq. 8)
+ * Outputs (each may be NULL), indexed by bound point p:
+ *   GR, GL, GG   full_blocks = 0: [p][slab_stride][nb] orbital diagonals,
+ *                full_blocks = 1: [p][slab_stride][nb][nb] diagonal blocks
+ *   bond_j       [p][slab_stride] (entry i = bond i -> i+1, i < N_p - 1)
+ *   transmission [p] Caroli T = Tr[Gamma_R G_{N1} Gamma_L G_{N1}^dagger]
+ *                (requires NEGF_WANT_TRANSMISSION in the forward call)
+ * slab_stride >= the longest bound sample.  Errors: NEGF_ESTATE, NEGF_EINVAL. */
+int negf_rgf_backward(negf_ctx* ctx, void* stream, int p0, int np,
+                      negf_c128* GR, negf_c128* GL, negf_c128* GG, int full_blocks,
+                      int slab_stride, double* bond_j, double* transmission);
+
+/*
+ * Scattering self-energies of Eqs. (4)-(6) for a bound single-sample system
+ * whose points are the full grid in (ik, ie) order (p = ik * n_e + ie):
+ *   acoustic: Sigma^{R,<} = D_ac <G^{R,<}(E)>_k
+ *   optical:  Sigma^<  = M_op <(1+n0) G^<(E+hw) + n0 G^<(E-hw)>_k
+ *             Sigma^R  = M_op <(1+n0) G^R(E-hw) + n0 G^R(E+hw)
+ *                              + G^<(E-hw)/2 - G^<(E+hw)/2>_k
+ * with hw = `shift` energy-grid steps and <.>_k = sum_k w_k (.).  A (E-hw) or
+ * (E+hw) group that falls off the grid is dropped from both Sigma^R and Sigma^<.
+ *   GR, GL   [n_k][n_e][slab_stride][nb] orbital diagonals (negf_rgf_backward)
+ *   w_k      [n_k] (device)
+ *   sig_R, sig_L  [n_e][N][nb], updated in place
+ *   rel_change    device double[1]: ||Sigma_new - Sigma_old||_F / ||Sigma_new||_F, or NULL
+ * Errors: NEGF_ESTATE (not a single-sample full grid), NEGF_EINVAL. */
+int negf_scba_selfenergy(negf_ctx* ctx, void* stream,
+                         const negf_c128* GR, const negf_c128* GL, int slab_stride,
+                         const double* w_k, double D_ac, double M_op, int shift, double n_bose,
+                         negf_c128* sig_R, negf_c128* sig_L, double* rel_change);
+
+/*
+ * Observables of Eqs. (7)-(8) over the whole bound point set, summed in a
+ * fixed order (deterministic, no floating-point atomics):
+ *   n[s_glob][a] = g_s sum_p w_e[ie] w_k[ik] (1/2pi) sum_{o in atom a} Im G^<_oo
+ *   J[s_glob]    = g_s sum_p w_e[ie] w_k[ik] j_i                         (units e/h)
+ *   j_E[sample][ie][i] = g_s sum_{p at ie} w_k[ik] j_i        (spectral current, or NULL)
+ * Atoms are consecutive groups of orbs_per_atom orbitals of a slab.
+ *   GL [p][slab_stride][nb], bond_j [p][slab_stride] (negf_rgf_backward layout)
+ *   n  [total_slabs][nb / orbs_per_atom], J [total_slabs], j_E [n_samples][n_e][slab_stride]
+ * Errors: NEGF_ESTATE, NEGF_EINVAL. */
+int negf_observables(negf_ctx* ctx, void* stream, const negf_c128* GL, const double* bond_j,
+                     int slab_stride, const double* w_e, const double* w_k, double g_s,
+                     int orbs_per_atom, double* n, double* J, double* j_E);
+
+/*
+ * The two dense block kernels of every slab step, exposed on their own (the
+ * zgemm / zgesv of the paper's Sec. "System and environment"), batched over
+ * `batch` independent n x n matrices (row-major, contiguous, [batch][n][n]).
+ *   dtype 0: complex128 operands, FP64 matrix-core arithmetic;
+ *   dtype 1: complex64 operands (interleaved float pairs), FP32 matrix cores.
+ * negf_zgemm_batched: C = op(A) op(B), op = 0 none, 1 conjugate transpose.
+ * negf_zinv_batched:  Ainv = A^-1 by Gauss-Jordan with partial pivoting; A is
+ *   overwritten (used as workspace).  Requires n <= nb and batch <= capacity of
+ *   the context; a zero or non-finite pivot sets the device status word.
+ * Errors: NEGF_EINVAL, NEGF_ESHAPE.
+ */
+int negf_zgemm_batched(negf_ctx* ctx, void* stream, int n, int batch, int opa, int opb,
+                       const void* A, const void* B, void* C, int dtype);
+int negf_zinv_batched(negf_ctx* ctx, void* stream, int n, int batch, void* A, void* Ainv, int dtype);
+
+/* Mixed-precision diagnostics of the last forward sweeps since the previous call:
+ * number of block inverses redone in FP64 and the largest Newton-Schulz
+ * residual ||I - A X0||_max seen (host outputs; synchronises `stream`). */
+int negf_mixed_stats(negf_ctx* ctx, void* stream, long long* n_fallback, double* max_residual);
+
+/* Kernel timing of the dominant kernel family (the batched complex GEMM):
+ * enable = 1 records a HIP event pair around every GEMM launch on the launch
+ * stream; negf_gemm_timing returns the launch count, summed kernel milliseconds
+ * and summed algorithmic flops (8 n^3 per point per launch) since enabling.
+ * Synchronises `stream`. */
+int negf_gemm_timing_enable(negf_ctx* ctx, int enable);
+int negf_gemm_timing(negf_ctx* ctx, void* stream, long long* launches, double* ms, double* flops);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NEGF_H */

@@ -84,10 +84,42 @@ def sancho_rubio(h00, h01, z, tol=1e-14, max_iter=100):
     return inv(z * eye - eps_s), it, converged
 
 
-def lead_selfenergy(h00, h01, tau, z, tol=1e-14, max_iter=100):
+def sancho_rubio_alt(h00, h01, z, tol=1e-14, max_iter=100):
+    """The same decimation with every triple product associated the other way,
+    a(g b) instead of (a g) b, and the inverse taken by an LU solve.  Used only
+    to measure how far two correct FP64 evaluations of one point can drift
+    apart (its conditioning; ~1/eta for propagating lead modes), which sets the
+    per-point parity tolerance of the GPU tests."""
+    n = h00.shape[0]
+    eye = np.eye(n)
+    eps_s = h00.astype(np.complex128).copy()
+    eps = eps_s.copy()
+    alpha = h01.astype(np.complex128).copy()
+    beta = dag(alpha)
+    ref = norm1(h01)
+    it = 0
+    converged = False
+    while it < max_iter:
+        it += 1
+        g = np.linalg.solve(z * eye - eps, eye)
+        agb = alpha @ (g @ beta)
+        bga = beta @ (g @ alpha)
+        eps_s = eps_s + agb
+        eps = eps + agb + bga
+        alpha = alpha @ (g @ alpha)
+        beta = beta @ (g @ beta)
+        if norm1(alpha) + norm1(beta) < tol * ref:
+            converged = True
+            break
+    return np.linalg.solve(z * eye - eps_s, eye), it, converged
+
+
+def lead_selfenergy(h00, h01, tau, z, tol=1e-14, max_iter=100, variant=None):
     """Retarded lead self-energy Sigma = tau g_s tau^dagger (tau: device edge
-    slab -> lead surface layer).  Returns (Sigma, iterations, converged)."""
-    gs, it, conv = sancho_rubio(h00, h01, z, tol, max_iter)
+    slab -> lead surface layer).  Returns (Sigma, iterations, converged).
+    variant="alt" uses ``sancho_rubio_alt`` (reproducibility estimate only)."""
+    sr = sancho_rubio_alt if variant == "alt" else sancho_rubio
+    gs, it, conv = sr(h00, h01, z, tol, max_iter)
     return tau @ gs @ dag(tau), it, conv
 
 
@@ -281,7 +313,7 @@ def scba_selfenergy(GRd, GLd, w_k, D_ac, M_op, shift, n_bose):
 # Drivers over many points
 # ---------------------------------------------------------------------------
 
-def lead_tables(wl, tol=1e-14, max_iter=100, ks=None, es=None):
+def lead_tables(wl, tol=1e-14, max_iter=100, ks=None, es=None, variant=None):
     """Sigma_L, Sigma_R for the (k, E) grid (or the listed subsets)."""
     ks = range(wl.n_k) if ks is None else ks
     es = range(wl.n_e) if es is None else es
@@ -289,17 +321,18 @@ def lead_tables(wl, tol=1e-14, max_iter=100, ks=None, es=None):
     for ik in ks:
         for ie in es:
             z = wl.energy[ie] + 1j * wl.eta
-            sL, itL, cL = lead_selfenergy(wl.lead_h00[ik], wl.lead_h01_L, wl.lead_tau_L, z, tol, max_iter)
-            sR, itR, cR = lead_selfenergy(wl.lead_h00[ik], wl.lead_h01_R, wl.lead_tau_R, z, tol, max_iter)
+            sL, itL, cL = lead_selfenergy(wl.lead_h00[ik], wl.lead_h01_L, wl.lead_tau_L, z, tol, max_iter, variant)
+            sR, itR, cR = lead_selfenergy(wl.lead_h00[ik], wl.lead_h01_R, wl.lead_tau_R, z, tol, max_iter, variant)
             out[(ik, ie)] = (sL, sR, itL, itR)
     return out
 
 
-def solve_points(wl, points, leads=None, scatR=None, scatL=None, transmission=False, eta_fill=None):
+def solve_points(wl, points, leads=None, scatR=None, scatL=None, transmission=False, eta_fill=None,
+                 variant=None):
     """RGF for a list of (sample, ik, ie) points.  scatR/scatL: [n_e, total_slabs, b]."""
     if leads is None:
         leads = lead_tables(wl, ks=sorted({int(p[1]) for p in points}),
-                            es=sorted({int(p[2]) for p in points}))
+                            es=sorted({int(p[2]) for p in points}), variant=variant)
     res = []
     for s, ik, ie in points:
         hd, hu, v = wl.sample_blocks(int(s), int(ik))

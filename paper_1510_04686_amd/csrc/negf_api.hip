@@ -1,0 +1,760 @@
+// C ABI of the RGF library: context, binding, and the host-side schedule of
+// the batched kernels (one launch per operation per slab step, covering every
+// point of the batch).
+#include "negf_kernels.hpp"
+#include "negf.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <utility>
+#include <vector>
+
+using namespace negf;
+
+namespace {
+
+constexpr int NTMP = 15;
+constexpr int NBMAX_INV = 16;
+constexpr int EV_POOL = 2048;
+
+struct TimedLaunch {
+    hipEvent_t a, b;
+    double flops;
+};
+
+}  // namespace
+
+struct negf_ctx {
+    negf_config cfg{};
+    int nb = 0, nsm = 0, cap = 0, prec = 0;
+    int sdt = DT_C128;            // store element type
+    size_t ce = 16;               // bytes per store element
+    std::vector<void*> allocs;
+    void* gst = nullptr;          // [cap][nsm][nb][nb]  left-connected g^R
+    void* glst = nullptr;         // [cap][nsm][nb][nb]  left-connected g^<
+    double2* tmp[NTMP] = {};
+    void* invE = nullptr;
+    void* invP = nullptr;
+    int* rowsrc = nullptr;
+    int* piv = nullptr;
+    int* coldst = nullptr;
+    double* bond_partial = nullptr;
+    int* sr_flags = nullptr;
+    int* sr_iters = nullptr;
+    double* sr_ref = nullptr;
+    int* d_count = nullptr;
+    int* status = nullptr;
+    double* ns_res = nullptr;     // [cap] mixed-precision residual per point
+    int* ns_flag = nullptr;       // [cap] fallback flag per point
+    int* ns_count = nullptr;      // device fallback counter
+    double* ns_max = nullptr;     // device: per-point max residual history (max)
+    int* h_pinned = nullptr;      // host pinned scratch
+    long long ws_bytes = 0;
+
+    // bound system
+    bool bound = false;
+    negf_system sys{};
+    std::vector<long long> soff_h;
+    std::vector<int4> desc_h;
+    int n_points = 0;
+    bool is_grid = false;
+    std::vector<void*> bound_allocs;
+    int4* desc_d = nullptr;
+    long long* soff_d = nullptr;
+    int* slab_sample_d = nullptr;
+    int* csr_off_d = nullptr;
+    int* csr_pts_d = nullptr;
+    double* orb_tmp_d = nullptr;
+    double* scba_partial_d = nullptr;
+    double* trans_d = nullptr;
+
+    // forward state
+    bool fwd_done = false;
+    int fwd_p0 = -1, fwd_np = 0, fwd_flags = 0;
+
+    // timing of the GEMM family
+    bool timing = false;
+    std::vector<TimedLaunch> pending;
+    std::vector<hipEvent_t> ev_free;
+    long long t_launches = 0;
+    double t_ms = 0.0, t_flops = 0.0;
+
+    ~negf_ctx() {
+        for (auto& t : pending) { hipEventDestroy(t.a); hipEventDestroy(t.b); }
+        for (auto e : ev_free) hipEventDestroy(e);
+        for (void* p : bound_allocs) hipFree(p);
+        for (void* p : allocs) hipFree(p);
+        if (h_pinned) hipHostFree(h_pinned);
+    }
+};
+
+namespace {
+
+template <typename T>
+bool dev_alloc(negf_ctx* c, T** p, size_t bytes, std::vector<void*>& list) {
+    if (bytes == 0) bytes = 16;
+    void* q = nullptr;
+    if (hipMalloc(&q, bytes) != hipSuccess) { hipGetLastError(); return false; }
+    list.push_back(q);
+    c->ws_bytes += (long long)bytes;
+    *p = reinterpret_cast<T*>(q);
+    return true;
+}
+
+hipError_t drain_timing(negf_ctx* c) {
+    for (auto& t : c->pending) {
+        hipError_t e = hipEventSynchronize(t.b);
+        if (e != hipSuccess) return e;
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, t.a, t.b);
+        c->t_ms += ms;
+        c->t_flops += t.flops;
+        c->t_launches += 1;
+        c->ev_free.push_back(t.a);
+        c->ev_free.push_back(t.b);
+    }
+    c->pending.clear();
+    return hipSuccess;
+}
+
+hipEvent_t get_event(negf_ctx* c) {
+    if (c->ev_free.empty()) {
+        hipEvent_t e;
+        hipEventCreate(&e);
+        return e;
+    }
+    hipEvent_t e = c->ev_free.back();
+    c->ev_free.pop_back();
+    return e;
+}
+
+// Batched GEMM with optional timing.  `active` = number of points that do work.
+hipError_t run_gemm(negf_ctx* c, hipStream_t s, GemmTypes ty, int opa, int opb, int epi, const GemmArgs& g,
+                    long long active) {
+    if (g.np <= 0 || active <= 0) return hipSuccess;
+    if (!c->timing) return gemm_launch(s, ty, opa, opb, epi, g);
+    if ((int)c->pending.size() >= EV_POOL) {
+        hipError_t e = drain_timing(c);
+        if (e != hipSuccess) return e;
+    }
+    TimedLaunch t{get_event(c), get_event(c), 8.0 * (double)g.n * g.n * g.n * (double)active};
+    hipEventRecord(t.a, s);
+    hipError_t e = gemm_launch(s, ty, opa, opb, epi, g);
+    hipEventRecord(t.b, s);
+    c->pending.push_back(t);
+    return e;
+}
+
+GemmArgs gargs(int n, int np, const Active& act) {
+    GemmArgs g{};
+    g.n = n;
+    g.np = np;
+    g.act = act;
+    return g;
+}
+
+void* slot(const negf_ctx* c, void* store, int slab) {
+    return static_cast<char*>(store) + (size_t)slab * c->nb * c->nb * c->ce;
+}
+
+long long store_stride(const negf_ctx* c) { return (long long)c->nsm * c->nb * c->nb; }
+
+// Active point counts and grid extents over [p0, p0+np) for predicate mode at step.
+void extent(const negf_ctx* c, int p0, int np, int mode, int step, int* hi, long long* cnt) {
+    int h = 0;
+    long long k = 0;
+    for (int q = 0; q < np; ++q) {
+        int ns = c->desc_h[p0 + q].w;
+        bool a = (mode == PRED_FWD) ? (step < ns) : (mode == PRED_BWD) ? (step < ns - 1)
+               : (mode == PRED_INIT) ? (step == ns - 1) : true;
+        if (a) { h = q + 1; ++k; }
+    }
+    *hi = h;
+    *cnt = k;
+}
+
+SandArgs sand_base(const negf_ctx* c, int p0, const Active& act, int np) {
+    SandArgs a{};
+    const negf_system& S = c->sys;
+    a.hup = reinterpret_cast<const double2*>(S.h_up);
+    a.hup_k = S.h_up_k_stride;
+    a.ub = S.up_block;
+    a.tile = sandwich_tile(S.up_block);
+    a.hdiag = reinterpret_cast<const double2*>(S.h_diag);
+    a.hdiag_k = c->soff_h.back() * (long long)c->nb * c->nb;
+    a.v = S.v_onsite;
+    a.total = c->soff_h.back();
+    a.n_e = S.n_e;
+    a.energy = S.energy;
+    a.eta = S.eta;
+    a.muL = S.mu_L;
+    a.muR = S.mu_R;
+    a.kT = S.kT;
+    a.eta_fill = S.eta_fill;
+    a.n = c->nb;
+    a.np = np;
+    a.act = act;
+    a.ps = PointSet{c->desc_d, c->soff_d, p0};
+    a.sign = 1.0;
+    return a;
+}
+
+InvWork invwork(negf_ctx* c, void* partner) {
+    return InvWork{partner, c->invE, c->invP, c->rowsrc, c->piv, c->coldst, c->status};
+}
+
+__global__ void fill_int_kernel(int* p, int v, int n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void copy_d_kernel(const double* a, double* b, int n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+// Mixed precision: per-point max |R_ij| of the refinement residual; flags a
+// fallback when it exceeds `thr`.
+__global__ __launch_bounds__(256) void ns_check_kernel(const double2* R, long long sR, int n, int np, Active act,
+                                                       double thr, double* res, int* flag, int* count, double* histmax,
+                                                       int* status) {
+    const int q = blockIdx.x;
+    if (q >= np) return;
+    __shared__ double red[256];
+    double m = 0.0;
+    bool on = act(q);
+    if (on) {
+        const double2* X = R + q * sR;
+        for (long long i = threadIdx.x; i < (long long)n * n; i += 256) {
+            double2 v = X[i];
+            double a = fmax(fabs(v.x), fabs(v.y));
+            if (!(a <= m)) m = (a == a) ? a : INFINITY;
+        }
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double r = on ? red[0] : 0.0;
+        res[q] = r;
+        int f = (on && !(r <= thr)) ? 1 : 0;
+        flag[q] = f;
+        if (f) { atomicAdd(count, 1); raise_status(status, ST_FALLBACK); }
+        if (on && r > histmax[q]) histmax[q] = r;
+    }
+}
+
+__global__ void zero_d_kernel(double* p, int n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+const char* negf_error_string(int st) {
+    switch (st) {
+        case NEGF_OK: return "ok";
+        case NEGF_EINVAL: return "invalid argument";
+        case NEGF_ESHAPE: return "sizes exceed the context configuration";
+        case NEGF_ENOMEM: return "device allocation failed";
+        case NEGF_EHIP: return "HIP runtime error";
+        case NEGF_ESTATE: return "call order violated (no bound system or no forward sweep)";
+        case NEGF_WNOCONV: return "Sancho-Rubio decimation hit max_iter for some point";
+        case NEGF_WSINGULAR: return "a block inverse met an exactly zero pivot";
+        case NEGF_WNONFINITE: return "a block inverse met a non-finite pivot";
+        case NEGF_WFALLBACK: return "mixed precision redid some block inverses in FP64";
+        default: return "unknown status";
+    }
+}
+
+int negf_create(const negf_config* cfg, negf_ctx** out) {
+    if (!cfg || !out) return NEGF_EINVAL;
+    *out = nullptr;
+    if (cfg->nb < 1 || cfg->n_slab_max < 1 || cfg->capacity < 1) return NEGF_EINVAL;
+    if (cfg->precision != NEGF_FP64 && cfg->precision != NEGF_MIXED) return NEGF_EINVAL;
+    negf_ctx* c = new (std::nothrow) negf_ctx();
+    if (!c) return NEGF_ENOMEM;
+    c->cfg = *cfg;
+    c->nb = cfg->nb;
+    c->nsm = cfg->n_slab_max;
+    c->cap = cfg->capacity;
+    c->prec = cfg->precision;
+    c->sdt = (c->prec == NEGF_MIXED) ? DT_C64 : DT_C128;
+    c->ce = (c->prec == NEGF_MIXED) ? 8 : 16;
+    const size_t nn = (size_t)c->nb * c->nb;
+    const size_t cap = (size_t)c->cap;
+    bool ok = dev_alloc(c, &c->gst, cap * c->nsm * nn * c->ce, c->allocs) &&
+              dev_alloc(c, &c->glst, cap * c->nsm * nn * c->ce, c->allocs);
+    for (int i = 0; ok && i < NTMP; ++i) ok = dev_alloc(c, &c->tmp[i], cap * nn * sizeof(double2), c->allocs);
+    ok = ok && dev_alloc(c, &c->invE, cap * c->nb * NBMAX_INV * sizeof(double2), c->allocs) &&
+         dev_alloc(c, &c->invP, cap * c->nb * NBMAX_INV * sizeof(double2), c->allocs) &&
+         dev_alloc(c, &c->rowsrc, cap * c->nb * sizeof(int), c->allocs) &&
+         dev_alloc(c, &c->piv, cap * c->nb * sizeof(int), c->allocs) &&
+         dev_alloc(c, &c->coldst, cap * c->nb * sizeof(int), c->allocs) &&
+         dev_alloc(c, &c->bond_partial, cap * 8 * sizeof(double), c->allocs) &&
+         dev_alloc(c, &c->sr_flags, cap * sizeof(int), c->allocs) &&
+         dev_alloc(c, &c->sr_iters, cap * sizeof(int), c->allocs) &&
+         dev_alloc(c, &c->sr_ref, cap * sizeof(double), c->allocs) &&
+         dev_alloc(c, &c->d_count, 4 * sizeof(int), c->allocs) &&
+         dev_alloc(c, &c->status, 4 * sizeof(int), c->allocs) &&
+         dev_alloc(c, &c->ns_res, cap * sizeof(double), c->allocs) &&
+         dev_alloc(c, &c->ns_flag, cap * sizeof(int), c->allocs) &&
+         dev_alloc(c, &c->ns_count, 4 * sizeof(int), c->allocs) &&
+         dev_alloc(c, &c->ns_max, cap * sizeof(double), c->allocs);
+    if (ok && hipHostMalloc((void**)&c->h_pinned, 64) != hipSuccess) { c->h_pinned = nullptr; ok = false; }
+    if (!ok) { delete c; return NEGF_ENOMEM; }
+    if (inverse_init() != hipSuccess || sandwich_init() != hipSuccess) { delete c; return NEGF_EHIP; }
+    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, 0, c->status, 0, 4);
+    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, 0, c->ns_count, 0, 4);
+    hipLaunchKernelGGL(zero_d_kernel, dim3((c->cap + 255) / 256), dim3(256), 0, 0, c->ns_max, c->cap);
+    if (hipDeviceSynchronize() != hipSuccess) { delete c; return NEGF_EHIP; }
+    *out = c;
+    return NEGF_OK;
+}
+
+void negf_destroy(negf_ctx* c) { delete c; }
+
+long long negf_workspace_bytes(const negf_ctx* c) { return c ? c->ws_bytes : 0; }
+
+int negf_sync_status(negf_ctx* c, void* stream) {
+    if (!c) return NEGF_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    NEGF_HIP_CHECK(hipMemcpyAsync(c->h_pinned, c->status, sizeof(int), hipMemcpyDeviceToHost, s));
+    NEGF_HIP_CHECK(hipStreamSynchronize(s));
+    int st = c->h_pinned[0];
+    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, s, c->status, 0, 1);
+    NEGF_HIP_CHECK(hipGetLastError());
+    if (st & ST_NONFINITE) return NEGF_WNONFINITE;
+    if (st & ST_SINGULAR) return NEGF_WSINGULAR;
+    if (st & ST_FALLBACK) return NEGF_WFALLBACK;
+    return NEGF_OK;
+}
+
+int negf_bind(negf_ctx* c, const negf_system* S, int n_points, const int* points) {
+    if (!c || !S || !points || n_points < 1) return NEGF_EINVAL;
+    if (S->nb != c->nb) return NEGF_ESHAPE;
+    if (S->n_samples < 1 || !S->slab_offset || S->n_k < 1 || S->n_e < 1) return NEGF_EINVAL;
+    if (!S->h_diag || !S->h_up || !S->energy) return NEGF_EINVAL;
+    if (S->up_block < 1 || S->up_block > 48 || S->nb % S->up_block != 0) return NEGF_EINVAL;
+    if (!(S->kT > 0) || !(S->eta >= 0)) return NEGF_EINVAL;
+    if (S->h_up_k_stride < 0) return NEGF_EINVAL;
+    std::vector<long long> soff(S->slab_offset, S->slab_offset + S->n_samples + 1);
+    if (soff[0] != 0) return NEGF_EINVAL;
+    for (int s = 0; s < S->n_samples; ++s) {
+        long long ns = soff[s + 1] - soff[s];
+        if (ns < 1) return NEGF_EINVAL;
+        if (ns > c->nsm) return NEGF_ESHAPE;
+    }
+    std::vector<int4> desc(n_points);
+    for (int p = 0; p < n_points; ++p) {
+        int s = points[3 * p], k = points[3 * p + 1], e = points[3 * p + 2];
+        if (s < 0 || s >= S->n_samples || k < 0 || k >= S->n_k || e < 0 || e >= S->n_e) return NEGF_EINVAL;
+        desc[p] = make_int4(s, k, e, (int)(soff[s + 1] - soff[s]));
+    }
+    for (void* p : c->bound_allocs) hipFree(p);
+    c->bound_allocs.clear();
+    c->bound = false;
+    c->fwd_done = false;
+    const long long total = soff.back();
+    // slab -> sample map, (sample, ie) -> points CSR
+    std::vector<int> slab_sample(total);
+    for (int s = 0; s < S->n_samples; ++s)
+        for (long long i = soff[s]; i < soff[s + 1]; ++i) slab_sample[i] = s;
+    const long long nkey = (long long)S->n_samples * S->n_e;
+    std::vector<int> csr_off(nkey + 1, 0), csr_pts(n_points);
+    for (int p = 0; p < n_points; ++p) csr_off[(long long)desc[p].x * S->n_e + desc[p].z + 1]++;
+    for (long long k = 0; k < nkey; ++k) csr_off[k + 1] += csr_off[k];
+    {
+        std::vector<int> fill(csr_off.begin(), csr_off.end() - 1);
+        for (int p = 0; p < n_points; ++p) csr_pts[fill[(long long)desc[p].x * S->n_e + desc[p].z]++] = p;
+    }
+    bool grid = (S->n_samples == 1 && (long long)n_points == (long long)S->n_k * S->n_e);
+    for (int p = 0; grid && p < n_points; ++p)
+        grid = desc[p].y == p / S->n_e && desc[p].z == p % S->n_e;
+    bool ok = dev_alloc(c, &c->desc_d, n_points * sizeof(int4), c->bound_allocs) &&
+              dev_alloc(c, &c->soff_d, soff.size() * sizeof(long long), c->bound_allocs) &&
+              dev_alloc(c, &c->slab_sample_d, total * sizeof(int), c->bound_allocs) &&
+              dev_alloc(c, &c->csr_off_d, csr_off.size() * sizeof(int), c->bound_allocs) &&
+              dev_alloc(c, &c->csr_pts_d, n_points * sizeof(int), c->bound_allocs) &&
+              dev_alloc(c, &c->orb_tmp_d, total * c->nb * sizeof(double), c->bound_allocs) &&
+              dev_alloc(c, &c->trans_d, n_points * sizeof(double), c->bound_allocs);
+    if (ok && grid) {
+        long long nblk = ((long long)S->n_e * total * c->nb + 255) / 256;
+        ok = dev_alloc(c, &c->scba_partial_d, nblk * 2 * sizeof(double), c->bound_allocs);
+    }
+    if (!ok) return NEGF_ENOMEM;
+    NEGF_HIP_CHECK(hipMemcpy(c->desc_d, desc.data(), n_points * sizeof(int4), hipMemcpyHostToDevice));
+    NEGF_HIP_CHECK(hipMemcpy(c->soff_d, soff.data(), soff.size() * sizeof(long long), hipMemcpyHostToDevice));
+    NEGF_HIP_CHECK(hipMemcpy(c->slab_sample_d, slab_sample.data(), total * sizeof(int), hipMemcpyHostToDevice));
+    NEGF_HIP_CHECK(hipMemcpy(c->csr_off_d, csr_off.data(), csr_off.size() * sizeof(int), hipMemcpyHostToDevice));
+    NEGF_HIP_CHECK(hipMemcpy(c->csr_pts_d, csr_pts.data(), n_points * sizeof(int), hipMemcpyHostToDevice));
+    c->sys = *S;
+    c->sys.slab_offset = nullptr;   // host copy kept in soff_h
+    c->soff_h = soff;
+    c->desc_h = desc;
+    c->n_points = n_points;
+    c->is_grid = grid;
+    c->bound = true;
+    return NEGF_OK;
+}
+
+int negf_lead_selfenergy(negf_ctx* c, void* stream, int n_k, const negf_c128* h00, const negf_c128* h01,
+                         const negf_c128* tau, int n_e, const double* energy, double eta, double tol,
+                         int max_iter, negf_c128* sigma, int* iters) {
+    if (!c || !h00 || !h01 || !tau || !energy || !sigma) return NEGF_EINVAL;
+    if (n_k < 1 || n_e < 1 || max_iter < 1 || !(tol > 0) || !(eta >= 0)) return NEGF_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const int n = c->nb;
+    const long long nn = (long long)n * n;
+    const long long total = (long long)n_k * n_e;
+    const GemmTypes T64{DT_C128, DT_C128, DT_C128, DT_C128};
+    bool noconv = false;
+    for (long long f0 = 0; f0 < total; f0 += c->cap) {
+        const int cnt = (int)std::min<long long>(c->cap, total - f0);
+        SrArgs a{};
+        a.h00 = reinterpret_cast<const double2*>(h00);
+        a.h01 = reinterpret_cast<const double2*>(h01);
+        a.tauin = reinterpret_cast<const double2*>(tau);
+        a.eps_s = c->tmp[0]; a.eps = c->tmp[1]; a.alpha = c->tmp[2]; a.beta = c->tmp[3]; a.tau = c->tmp[13];
+        a.flags = c->sr_flags; a.iters = c->sr_iters; a.ref = c->sr_ref; a.count = c->d_count;
+        a.energy = energy; a.eta = eta; a.tol = tol; a.f0 = f0; a.n = n; a.n_e = n_e; a.np = cnt;
+        NEGF_HIP_CHECK(sr_launch_init(s, a));
+        double2 *al = c->tmp[2], *be = c->tmp[3], *al2 = c->tmp[6], *be2 = c->tmp[7];
+        double2 *g = c->tmp[8], *X1 = c->tmp[9], *X2 = c->tmp[10], *M = c->tmp[11];
+        long long active = cnt;
+        for (int it = 1; it <= max_iter && active > 0; ++it) {
+            Active act{c->desc_d, 0, 0, PRED_FLAG, c->sr_flags};
+            NEGF_HIP_CHECK(sr_launch_zminus(s, a, a.eps, M, act));
+            NEGF_HIP_CHECK(inverse_launch(s, DT_C128, M, nn, g, nn, n, cnt, act, invwork(c, c->tmp[12])));
+            GemmArgs G = gargs(n, cnt, act);
+            G.A = al; G.sA = nn; G.B = g; G.sB = nn; G.C = X1; G.sC = nn;
+            NEGF_HIP_CHECK(run_gemm(c, s, T64, OP_N, OP_N, EPI_STORE, G, active));
+            G.A = be; G.C = X2;
+            NEGF_HIP_CHECK(run_gemm(c, s, T64, OP_N, OP_N, EPI_STORE, G, active));
+            // eps_s += X1 beta ; eps += X1 beta
+            G.A = X1; G.B = be; G.C = a.eps_s; G.C2 = a.eps; G.sC2 = nn;
+            NEGF_HIP_CHECK(run_gemm(c, s, T64, OP_N, OP_N, EPI_DUAL, G, active));
+            // eps += X2 alpha
+            G.A = X2; G.B = al; G.C = a.eps; G.D = a.eps; G.sD = nn;
+            NEGF_HIP_CHECK(run_gemm(c, s, T64, OP_N, OP_N, EPI_ADD, G, active));
+            // alpha' = X1 alpha ; beta' = X2 beta
+            G.A = X1; G.B = al; G.C = al2;
+            NEGF_HIP_CHECK(run_gemm(c, s, T64, OP_N, OP_N, EPI_STORE, G, active));
+            G.A = X2; G.B = be; G.C = be2;
+            NEGF_HIP_CHECK(run_gemm(c, s, T64, OP_N, OP_N, EPI_STORE, G, active));
+            std::swap(al, al2);
+            std::swap(be, be2);
+            hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, s, c->d_count, 0, 1);
+            NEGF_HIP_CHECK(sr_launch_check(s, a, al, be, it));
+            NEGF_HIP_CHECK(hipMemcpyAsync(c->h_pinned, c->d_count, sizeof(int), hipMemcpyDeviceToHost, s));
+            NEGF_HIP_CHECK(hipStreamSynchronize(s));
+            active = c->h_pinned[0];
+        }
+        if (active > 0) noconv = true;
+        // g_s = (z - eps_s)^-1 ; Sigma = tau g_s tau^dagger
+        Active all{c->desc_d, 0, 0, PRED_ALL, nullptr};
+        NEGF_HIP_CHECK(sr_launch_zminus(s, a, a.eps_s, M, all));
+        NEGF_HIP_CHECK(inverse_launch(s, DT_C128, M, nn, g, nn, n, cnt, all, invwork(c, c->tmp[12])));
+        GemmArgs G = gargs(n, cnt, all);
+        G.A = a.tau; G.sA = nn; G.B = g; G.sB = nn; G.C = X1; G.sC = nn;
+        NEGF_HIP_CHECK(run_gemm(c, s, T64, OP_N, OP_N, EPI_STORE, G, cnt));
+        G.A = X1; G.B = a.tau; G.C = reinterpret_cast<double2*>(sigma) + f0 * nn;
+        NEGF_HIP_CHECK(run_gemm(c, s, T64, OP_N, OP_C, EPI_STORE, G, cnt));
+        if (iters) NEGF_HIP_CHECK(sr_launch_iters(s, a, iters));
+    }
+    return noconv ? NEGF_WNOCONV : NEGF_OK;
+}
+
+int negf_rgf_forward(negf_ctx* c, void* stream, int p0, int np, const negf_c128* sigma_L,
+                     const negf_c128* sigma_R, const negf_c128* scat_R, const negf_c128* scat_L, int flags) {
+    if (!c) return NEGF_EINVAL;
+    if (!c->bound) return NEGF_ESTATE;
+    if (!sigma_L || !sigma_R || p0 < 0 || np < 1 || p0 + np > c->n_points) return NEGF_EINVAL;
+    if (np > c->cap) return NEGF_ESHAPE;
+    if ((scat_R == nullptr) != (scat_L == nullptr)) return NEGF_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const int n = c->nb;
+    const long long nn = (long long)n * n;
+    const long long sst = store_stride(c);
+    const bool mixed = c->prec == NEGF_MIXED;
+    const int sdt = c->sdt;
+    const GemmTypes TS{sdt, sdt, sdt, sdt};
+    int maxN = 0;
+    for (int q = 0; q < np; ++q) maxN = std::max(maxN, c->desc_h[p0 + q].w);
+    const bool wantT = (flags & NEGF_WANT_TRANSMISSION) != 0;
+    const double2* sL = reinterpret_cast<const double2*>(sigma_L);
+    const double2* sR = reinterpret_cast<const double2*>(sigma_R);
+    for (int i = 0; i < maxN; ++i) {
+        int hi;
+        long long cnt;
+        extent(c, p0, np, PRED_FWD, i, &hi, &cnt);
+        Active act{c->desc_d, p0, i, PRED_FWD, nullptr};
+        // M = A_ii - H_{i,i-1} g_{i-1} H_{i-1,i}   (FP64 assembly)
+        SandArgs sa = sand_base(c, p0, act, hi);
+        sa.sigL = sL; sa.sigR = sR;
+        sa.X = (i > 0) ? slot(c, c->gst, i - 1) : nullptr; sa.sX = sst;
+        sa.uslab = i - 1; sa.opL = 2; sa.opR = 1; sa.sign = -1.0;
+        sa.O = c->tmp[0]; sa.sO = nn; sa.mode = 1; sa.slab = i;
+        sa.scat = reinterpret_cast<const double2*>(scat_R);
+        NEGF_HIP_CHECK(sandwich_launch(s, sdt, DT_C128, sa));
+        if (!mixed) {
+            NEGF_HIP_CHECK(inverse_launch(s, DT_C128, c->tmp[0], nn, slot(c, c->gst, i), sst, n, hi, act,
+                                          invwork(c, c->tmp[3])));
+        } else {
+            // X0 = M^-1 in FP32, R = I - M X0 in FP64, X1 = X0 + X0 R in FP32.
+            Active all{c->desc_d, p0, i, PRED_FWD, nullptr};
+            NEGF_HIP_CHECK(copy_launch(s, DT_C128, DT_C64, c->tmp[0], nn, c->tmp[4], nn, nn, hi, act));
+            NEGF_HIP_CHECK(inverse_launch(s, DT_C64, c->tmp[4], nn, c->tmp[2], nn, n, hi, act,
+                                          invwork(c, c->tmp[3])));
+            GemmArgs G = gargs(n, hi, act);
+            G.A = c->tmp[0]; G.sA = nn; G.B = c->tmp[2]; G.sB = nn; G.C = c->tmp[1]; G.sC = nn;
+            NEGF_HIP_CHECK(run_gemm(c, s, GemmTypes{DT_C128, DT_C64, DT_C128, DT_C128}, OP_N, OP_N, EPI_IMINUS, G, cnt));
+            hipLaunchKernelGGL(ns_check_kernel, dim3(hi), dim3(256), 0, s, c->tmp[1], nn, n, hi, all, 1e-2,
+                               c->ns_res, c->ns_flag, c->ns_count, c->ns_max, c->status);
+            NEGF_HIP_CHECK(hipGetLastError());
+            G.A = c->tmp[2]; G.B = c->tmp[1]; G.D = c->tmp[2]; G.sD = nn; G.C = slot(c, c->gst, i); G.sC = sst;
+            NEGF_HIP_CHECK(run_gemm(c, s, GemmTypes{DT_C64, DT_C128, DT_C64, DT_C64}, OP_N, OP_N, EPI_ADD, G, cnt));
+            // FP64 fallback for flagged points (M is still in tmp[0]).
+            Active fb{c->desc_d, p0, i, PRED_FLAG, c->ns_flag};
+            NEGF_HIP_CHECK(inverse_launch(s, DT_C128, c->tmp[0], nn, c->tmp[1], nn, n, hi, fb, invwork(c, c->tmp[3])));
+            NEGF_HIP_CHECK(copy_launch(s, DT_C128, DT_C64, c->tmp[1], nn, slot(c, c->gst, i), sst, nn, hi, fb));
+        }
+        // X = Sigma^<_i + H_{i,i-1} g^<_{i-1} H_{i-1,i}
+        sa.X = (i > 0) ? slot(c, c->glst, i - 1) : nullptr;
+        sa.sign = 1.0; sa.mode = 2; sa.O = c->tmp[1];
+        sa.scat = reinterpret_cast<const double2*>(scat_L);
+        NEGF_HIP_CHECK(sandwich_launch(s, sdt, sdt, sa));
+        // g^<_i = g_i X g_i^dagger
+        GemmArgs G = gargs(n, hi, act);
+        G.A = slot(c, c->gst, i); G.sA = sst; G.B = c->tmp[1]; G.sB = nn; G.C = c->tmp[2]; G.sC = nn;
+        NEGF_HIP_CHECK(run_gemm(c, s, TS, OP_N, OP_N, EPI_STORE, G, cnt));
+        G.A = c->tmp[2]; G.sA = nn; G.B = slot(c, c->gst, i); G.sB = sst; G.C = slot(c, c->glst, i); G.sC = sst;
+        NEGF_HIP_CHECK(run_gemm(c, s, TS, OP_N, OP_C, EPI_STORE, G, cnt));
+        if (wantT) {
+            // left-column chain G_{i,1} = g_i H_{i,i-1} G_{i-1,1}
+            if (i == 0) {
+                NEGF_HIP_CHECK(copy_launch(s, sdt, sdt, slot(c, c->gst, 0), sst, c->tmp[5], nn, nn, hi, act));
+            } else {
+                SandArgs sc = sand_base(c, p0, act, hi);
+                sc.X = c->tmp[5]; sc.sX = nn; sc.uslab = i - 1; sc.opL = 2; sc.opR = 0;
+                sc.O = c->tmp[6]; sc.sO = nn; sc.mode = 0;
+                NEGF_HIP_CHECK(sandwich_launch(s, sdt, sdt, sc));
+                GemmArgs Gc = gargs(n, hi, act);
+                Gc.A = slot(c, c->gst, i); Gc.sA = sst; Gc.B = c->tmp[6]; Gc.sB = nn; Gc.C = c->tmp[5]; Gc.sC = nn;
+                NEGF_HIP_CHECK(run_gemm(c, s, TS, OP_N, OP_N, EPI_STORE, Gc, cnt));
+            }
+        }
+    }
+    if (wantT) {
+        // T = Tr[Gamma_R C Gamma_L C^dagger], C = G_{N,1}
+        PointSet ps{c->desc_d, c->soff_d, p0};
+        Active all{c->desc_d, p0, 0, PRED_ALL, nullptr};
+        NEGF_HIP_CHECK(gamma_launch(s, sdt, sL, c->sys.n_e, ps, c->tmp[7], nn, n, np));
+        NEGF_HIP_CHECK(gamma_launch(s, sdt, sR, c->sys.n_e, ps, c->tmp[8], nn, n, np));
+        GemmArgs G = gargs(n, np, all);
+        G.A = c->tmp[8]; G.sA = nn; G.B = c->tmp[5]; G.sB = nn; G.C = c->tmp[9]; G.sC = nn;
+        NEGF_HIP_CHECK(run_gemm(c, s, TS, OP_N, OP_N, EPI_STORE, G, np));
+        G.A = c->tmp[7]; G.B = c->tmp[5]; G.C = c->tmp[10];
+        NEGF_HIP_CHECK(run_gemm(c, s, TS, OP_N, OP_C, EPI_STORE, G, np));
+        NEGF_HIP_CHECK(trace_prod_launch(s, sdt, c->tmp[9], c->tmp[10], nn, n, np, c->trans_d, p0));
+    }
+    c->fwd_done = true;
+    c->fwd_p0 = p0;
+    c->fwd_np = np;
+    c->fwd_flags = flags;
+    return NEGF_OK;
+}
+
+int negf_rgf_backward(negf_ctx* c, void* stream, int p0, int np, negf_c128* GR, negf_c128* GL, negf_c128* GG,
+                      int full_blocks, int slab_stride, double* bond_j, double* transmission) {
+    if (!c) return NEGF_EINVAL;
+    if (!c->bound || !c->fwd_done || p0 != c->fwd_p0 || np != c->fwd_np) return NEGF_ESTATE;
+    if (transmission && !(c->fwd_flags & NEGF_WANT_TRANSMISSION)) return NEGF_ESTATE;
+    hipStream_t s = (hipStream_t)stream;
+    const int n = c->nb;
+    const long long nn = (long long)n * n;
+    const long long sst = store_stride(c);
+    const int sdt = c->sdt;
+    const GemmTypes TS{sdt, sdt, sdt, sdt};
+    int maxN = 0;
+    for (int q = 0; q < np; ++q) maxN = std::max(maxN, c->desc_h[p0 + q].w);
+    if (slab_stride < maxN) return NEGF_EINVAL;
+    double2* Gb[2] = {c->tmp[8], c->tmp[9]};
+    double2* GLb[2] = {c->tmp[10], c->tmp[11]};
+    PointSet ps{c->desc_d, c->soff_d, p0};
+    for (int st = maxN - 1; st >= 0; --st) {
+        const int cur = st & 1, nxt = cur ^ 1;
+        int hiF, hiB, hiI;
+        long long cF, cB, cI;
+        extent(c, p0, np, PRED_FWD, st, &hiF, &cF);
+        extent(c, p0, np, PRED_BWD, st, &hiB, &cB);
+        extent(c, p0, np, PRED_INIT, st, &hiI, &cI);
+        Active aI{c->desc_d, p0, st, PRED_INIT, nullptr};
+        Active aB{c->desc_d, p0, st, PRED_BWD, nullptr};
+        Active aF{c->desc_d, p0, st, PRED_FWD, nullptr};
+        if (cI > 0) {
+            NEGF_HIP_CHECK(copy_launch(s, sdt, sdt, slot(c, c->gst, st), sst, Gb[cur], nn, nn, hiI, aI));
+            NEGF_HIP_CHECK(copy_launch(s, sdt, sdt, slot(c, c->glst, st), sst, GLb[cur], nn, nn, hiI, aI));
+        }
+        if (cB > 0) {
+            SandArgs sa = sand_base(c, p0, aB, hiB);
+            sa.uslab = st; sa.mode = 0;
+            // L = g_s H_{s,s+1}
+            sa.X = slot(c, c->gst, st); sa.sX = sst; sa.opL = 0; sa.opR = 1; sa.O = c->tmp[0]; sa.sO = nn;
+            NEGF_HIP_CHECK(sandwich_launch(s, sdt, sdt, sa));
+            // R = H_{s+1,s} g_s
+            sa.opL = 2; sa.opR = 0; sa.O = c->tmp[1];
+            NEGF_HIP_CHECK(sandwich_launch(s, sdt, sdt, sa));
+            // Q = H_{s+1,s} g^<_s
+            sa.X = slot(c, c->glst, st); sa.O = c->tmp[3];
+            NEGF_HIP_CHECK(sandwich_launch(s, sdt, sdt, sa));
+            GemmArgs G = gargs(n, hiB, aB);
+            // P = L G_{s+1}
+            G.A = c->tmp[0]; G.sA = nn; G.B = Gb[nxt]; G.sB = nn; G.C = c->tmp[2]; G.sC = nn;
+            NEGF_HIP_CHECK(run_gemm(c, s, TS, OP_N, OP_N, EPI_STORE, G, cB));
+            // G_s = g_s + P R
+            G.A = c->tmp[2]; G.B = c->tmp[1]; G.C = Gb[cur]; G.D = slot(c, c->gst, st); G.sD = sst;
+            NEGF_HIP_CHECK(run_gemm(c, s, TS, OP_N, OP_N, EPI_ADD, G, cB));
+            // T = P Q
+            G.A = c->tmp[2]; G.B = c->tmp[3]; G.C = c->tmp[6];
+            NEGF_HIP_CHECK(run_gemm(c, s, TS, OP_N, OP_N, EPI_STORE, G, cB));
+            // W = L G^<_{s+1}
+            G.A = c->tmp[0]; G.B = GLb[nxt]; G.C = c->tmp[7];
+            NEGF_HIP_CHECK(run_gemm(c, s, TS, OP_N, OP_N, EPI_STORE, G, cB));
+            // G^<_s = g^<_s + W L^dagger + T - T^dagger
+            G.A = c->tmp[7]; G.B = c->tmp[0]; G.C = GLb[cur]; G.D = slot(c, c->glst, st); G.sD = sst;
+            G.T = c->tmp[6]; G.sT = nn;
+            NEGF_HIP_CHECK(run_gemm(c, s, TS, OP_N, OP_C, EPI_ADD_TTD, G, cB));
+            if (bond_j) {
+                BondArgs b{};
+                b.hup = reinterpret_cast<const double2*>(c->sys.h_up);
+                b.hup_k = c->sys.h_up_k_stride;
+                b.ub = c->sys.up_block; b.slab = st;
+                b.G = Gb[nxt]; b.GL = GLb[nxt]; b.Q = c->tmp[3]; b.L = c->tmp[0]; b.sM = nn;
+                b.partial = c->bond_partial; b.n = n; b.np = hiB; b.act = aB; b.ps = ps;
+                NEGF_HIP_CHECK(bond_launch(s, sdt, b, bond_j, slab_stride));
+            }
+        }
+        if (GR || GL || GG) {
+            ExtArgs e{};
+            e.G = Gb[cur]; e.GL = GLb[cur]; e.sG = nn;
+            e.outR = reinterpret_cast<double2*>(GR); e.outL = reinterpret_cast<double2*>(GL);
+            e.outG = reinterpret_cast<double2*>(GG);
+            e.full = full_blocks ? 1 : 0; e.slab_stride = slab_stride; e.slab = st; e.n = n; e.np = hiF; e.p0 = p0;
+            e.act = aF;
+            NEGF_HIP_CHECK(extract_launch(s, sdt, e));
+        }
+    }
+    if (transmission) {
+        hipLaunchKernelGGL(copy_d_kernel, dim3((np + 255) / 256), dim3(256), 0, s, c->trans_d + p0, transmission + p0, np);
+        NEGF_HIP_CHECK(hipGetLastError());
+    }
+    return NEGF_OK;
+}
+
+int negf_scba_selfenergy(negf_ctx* c, void* stream, const negf_c128* GR, const negf_c128* GL, int slab_stride,
+                         const double* w_k, double D_ac, double M_op, int shift, double n_bose, negf_c128* sig_R,
+                         negf_c128* sig_L, double* rel_change) {
+    if (!c) return NEGF_EINVAL;
+    if (!c->bound || !c->is_grid) return NEGF_ESTATE;
+    if (!GR || !GL || !w_k || !sig_R || !sig_L || shift < 0) return NEGF_EINVAL;
+    const int N = (int)c->soff_h.back();
+    if (slab_stride < N) return NEGF_EINVAL;
+    ScbaArgs a{};
+    a.GR = reinterpret_cast<const double2*>(GR);
+    a.GL = reinterpret_cast<const double2*>(GL);
+    a.w_k = w_k; a.D = D_ac; a.M = M_op; a.n0 = n_bose; a.shift = shift;
+    a.n_k = c->sys.n_k; a.n_e = c->sys.n_e; a.N = N; a.n = c->nb; a.slab_stride = slab_stride;
+    a.sigR = reinterpret_cast<double2*>(sig_R);
+    a.sigL = reinterpret_cast<double2*>(sig_L);
+    a.partial = c->scba_partial_d;
+    NEGF_HIP_CHECK(scba_launch((hipStream_t)stream, a, rel_change));
+    return NEGF_OK;
+}
+
+int negf_observables(negf_ctx* c, void* stream, const negf_c128* GL, const double* bond_j, int slab_stride,
+                     const double* w_e, const double* w_k, double g_s, int orbs_per_atom, double* n_out, double* J,
+                     double* j_E) {
+    if (!c) return NEGF_EINVAL;
+    if (!c->bound) return NEGF_ESTATE;
+    if (!w_e || !w_k || orbs_per_atom < 1 || c->nb % orbs_per_atom != 0) return NEGF_EINVAL;
+    if ((n_out && !GL) || ((J || j_E) && !bond_j)) return NEGF_EINVAL;
+    int maxN = 0;
+    for (size_t s = 0; s + 1 < c->soff_h.size(); ++s) maxN = std::max<long long>(maxN, c->soff_h[s + 1] - c->soff_h[s]);
+    if (slab_stride < maxN) return NEGF_EINVAL;
+    ObsArgs a{};
+    a.GL = reinterpret_cast<const double2*>(GL);
+    a.bond = bond_j; a.slab_stride = slab_stride; a.w_e = w_e; a.w_k = w_k; a.g_s = g_s;
+    a.opa = orbs_per_atom; a.n = c->nb; a.n_e = c->sys.n_e; a.n_samples = c->sys.n_samples;
+    a.total = c->soff_h.back();
+    a.desc = c->desc_d; a.slab_off = c->soff_d; a.slab_sample = c->slab_sample_d;
+    a.csr_off = c->csr_off_d; a.csr_pts = c->csr_pts_d; a.orb_tmp = c->orb_tmp_d;
+    a.n_out = n_out; a.J = J; a.jE = j_E;
+    NEGF_HIP_CHECK(observables_launch((hipStream_t)stream, a));
+    return NEGF_OK;
+}
+
+int negf_zgemm_batched(negf_ctx* c, void* stream, int n, int batch, int opa, int opb, const void* A, const void* B,
+                       void* C, int dtype) {
+    if (!c || !A || !B || !C || n < 1 || batch < 1) return NEGF_EINVAL;
+    if ((opa != 0 && opa != 1) || (opb != 0 && opb != 1) || (dtype != 0 && dtype != 1)) return NEGF_EINVAL;
+    const int dt = dtype == 0 ? DT_C128 : DT_C64;
+    const long long nn = (long long)n * n;
+    Active all{nullptr, 0, 0, PRED_ALL, nullptr};
+    GemmArgs G = gargs(n, batch, all);
+    G.A = A; G.sA = nn; G.B = B; G.sB = nn; G.C = C; G.sC = nn;
+    NEGF_HIP_CHECK(run_gemm(c, (hipStream_t)stream, GemmTypes{dt, dt, dt, dt}, opa, opb, EPI_STORE, G, batch));
+    return NEGF_OK;
+}
+
+int negf_zinv_batched(negf_ctx* c, void* stream, int n, int batch, void* A, void* Ainv, int dtype) {
+    if (!c || !A || !Ainv || n < 1 || batch < 1 || (dtype != 0 && dtype != 1)) return NEGF_EINVAL;
+    if (n > c->nb || batch > c->cap) return NEGF_ESHAPE;
+    const long long nn = (long long)n * n;
+    Active all{nullptr, 0, 0, PRED_ALL, nullptr};
+    NEGF_HIP_CHECK(inverse_launch((hipStream_t)stream, dtype == 0 ? DT_C128 : DT_C64, A, nn, Ainv, nn, n, batch, all,
+                                  invwork(c, c->tmp[14])));
+    return NEGF_OK;
+}
+
+int negf_mixed_stats(negf_ctx* c, void* stream, long long* n_fallback, double* max_residual) {
+    if (!c) return NEGF_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<double> mx(c->cap);
+    NEGF_HIP_CHECK(hipMemcpyAsync(c->h_pinned, c->ns_count, sizeof(int), hipMemcpyDeviceToHost, s));
+    NEGF_HIP_CHECK(hipStreamSynchronize(s));
+    NEGF_HIP_CHECK(hipMemcpy(mx.data(), c->ns_max, c->cap * sizeof(double), hipMemcpyDeviceToHost));
+    if (n_fallback) *n_fallback = c->h_pinned[0];
+    if (max_residual) *max_residual = mx.empty() ? 0.0 : *std::max_element(mx.begin(), mx.end());
+    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, s, c->ns_count, 0, 1);
+    hipLaunchKernelGGL(zero_d_kernel, dim3((c->cap + 255) / 256), dim3(256), 0, s, c->ns_max, c->cap);
+    NEGF_HIP_CHECK(hipGetLastError());
+    return NEGF_OK;
+}
+
+int negf_gemm_timing_enable(negf_ctx* c, int enable) {
+    if (!c) return NEGF_EINVAL;
+    c->timing = enable != 0;
+    if (c->timing) { c->t_launches = 0; c->t_ms = 0; c->t_flops = 0; }
+    return NEGF_OK;
+}
+
+int negf_gemm_timing(negf_ctx* c, void* stream, long long* launches, double* ms, double* flops) {
+    if (!c) return NEGF_EINVAL;
+    NEGF_HIP_CHECK(hipStreamSynchronize((hipStream_t)stream));
+    NEGF_HIP_CHECK(drain_timing(c));
+    if (launches) *launches = c->t_launches;
+    if (ms) *ms = c->t_ms;
+    if (flops) *flops = c->t_flops;
+    return NEGF_OK;
+}
+
+}  // extern "C"

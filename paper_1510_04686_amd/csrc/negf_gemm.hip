@@ -1,0 +1,159 @@
+// Batched complex GEMM on CDNA4 matrix cores.
+//
+// Every slab step of the RGF recursions (g_i X, Y g_i^dagger, L G_{i+1},
+// P R, ...) is a dense complex b x b x b product for each (sample, k, E)
+// point of a batch.  One launch covers the whole batch: a 64 x 64 output tile
+// of one point per 256-thread workgroup (4 wavefronts of 32 x 32), K staged
+// through LDS in 16-wide double-buffered slices, split real/imaginary planes.
+// A complex product is four real MFMA products (re*re - im*im, re*im + im*re)
+// on v_mfma_f64_16x16x4f64 (FP64) or v_mfma_f32_16x16x4f32 (FP32).
+#include "negf_internal.hpp"
+#include "negf_mfma.hpp"
+
+namespace negf {
+
+template <typename TA, typename TB, typename TC, typename Acc, int OPA, int OPB, int EPI>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
+    __shared__ Acc As[2][2][BK][LP];
+    __shared__ Acc Bs[2][2][BK][LP];
+    const int n = g.n;
+    const int tiles = (n + BM - 1) / BM;
+    const int tpp = tiles * tiles;
+    const int lid = xcd_remap(blockIdx.x, gridDim.x);
+    const int q = lid / tpp;
+    if (q >= g.np || !g.act(q)) return;
+    const int t = lid - q * tpp;
+    const int m0 = (t / tiles) * BM, n0 = (t % tiles) * BM;
+    const TA* __restrict__ A = (const TA*)g.A + q * g.sA;
+    const TB* __restrict__ B = (const TB*)g.B + q * g.sB;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int rowbase = m0 + wm * 32, colbase = n0 + wn * 32;
+    const int nmi = rowbase >= n ? 0 : (rowbase + 16 >= n ? 1 : 2);
+    const int nnj = colbase >= n ? 0 : (colbase + 16 >= n ? 1 : 2);
+
+    typename MF<Acc>::V cr[2][2], ci[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) { cr[a][b][r] = 0; ci[a][b][r] = 0; }
+
+    // op(A) slice: OPA = N -> rows m, contiguous k (pattern X); C -> rows k (pattern Y)
+    // op(B) slice: OPB = N -> rows k (pattern Y); C -> rows n, contiguous k (pattern X)
+    constexpr bool AK = (OPA == OP_C);
+    constexpr bool BKR = (OPB == OP_N);
+    TA ra[4];
+    TB rb[4];
+    const int nkt = (n + BK - 1) / BK;
+    load_slice<TA, AK>(A, n, m0, 0, tid, ra);
+    load_slice<TB, BKR>(B, n, n0, 0, tid, rb);
+    store_slice<Acc, TA, AK, OPA == OP_C>(As[0], tid, ra);
+    store_slice<Acc, TB, BKR, OPB == OP_C>(Bs[0], tid, rb);
+    __syncthreads();
+    for (int kt = 0; kt < nkt; ++kt) {
+        const int buf = kt & 1;
+        const bool more = kt + 1 < nkt;
+        if (more) {
+            load_slice<TA, AK>(A, n, m0, (kt + 1) * BK, tid, ra);
+            load_slice<TB, BKR>(B, n, n0, (kt + 1) * BK, tid, rb);
+        }
+        if (nmi == 2 && nnj == 2) mma_slice<Acc, 2, 2>(As[buf], Bs[buf], lane, wm, wn, cr, ci);
+        else if (nmi == 2 && nnj == 1) mma_slice<Acc, 2, 1>(As[buf], Bs[buf], lane, wm, wn, cr, ci);
+        else if (nmi == 1 && nnj == 2) mma_slice<Acc, 1, 2>(As[buf], Bs[buf], lane, wm, wn, cr, ci);
+        else if (nmi == 1 && nnj == 1) mma_slice<Acc, 1, 1>(As[buf], Bs[buf], lane, wm, wn, cr, ci);
+        if (more) {
+            store_slice<Acc, TA, AK, OPA == OP_C>(As[buf ^ 1], tid, ra);
+            store_slice<Acc, TB, BKR, OPB == OP_C>(Bs[buf ^ 1], tid, rb);
+        }
+        __syncthreads();
+    }
+
+    TC* __restrict__ C = (TC*)g.C + q * g.sC;
+    const TC* D = (const TC*)g.D + q * g.sD;
+    const TC* T = (const TC*)g.T + q * g.sT;
+    TC* C2 = (TC*)g.C2 + q * g.sC2;
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi) {
+        if (mi >= nmi) break;
+#pragma unroll
+        for (int nj = 0; nj < 2; ++nj) {
+            if (nj >= nnj) break;
+            const int col = colbase + nj * 16 + (lane & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = rowbase + mi * 16 + out_row<Acc>(lane, r);
+                if (row < n && col < n) {
+                    const long long idx = (long long)row * n + col;
+                    double vr = (double)cr[mi][nj][r], vi = (double)ci[mi][nj][r];
+                    TC out;
+                    if (EPI == EPI_STORE) {
+                        out.x = vr; out.y = vi; C[idx] = out;
+                    } else if (EPI == EPI_ADD || EPI == EPI_SUB) {
+                        TC d = D[idx];
+                        double s = (EPI == EPI_ADD) ? 1.0 : -1.0;
+                        out.x = (double)d.x + s * vr; out.y = (double)d.y + s * vi; C[idx] = out;
+                    } else if (EPI == EPI_ADD_TTD) {
+                        TC d = D[idx], t1 = T[idx], t2 = T[(long long)col * n + row];
+                        out.x = (double)d.x + vr + (double)t1.x - (double)t2.x;
+                        out.y = (double)d.y + vi + (double)t1.y + (double)t2.y;
+                        C[idx] = out;
+                    } else if (EPI == EPI_DUAL) {
+                        TC c1 = C[idx], c2 = C2[idx];
+                        out.x = (double)c1.x + vr; out.y = (double)c1.y + vi; C[idx] = out;
+                        out.x = (double)c2.x + vr; out.y = (double)c2.y + vi; C2[idx] = out;
+                    } else if (EPI == EPI_IMINUS) {
+                        out.x = (row == col ? 1.0 : 0.0) - vr; out.y = -vi; C[idx] = out;
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <typename TA, typename TB, typename TC, typename Acc, int OPA, int OPB>
+static hipError_t launch_epi(hipStream_t s, int epi, const GemmArgs& g, dim3 grid) {
+    switch (epi) {
+#define NEGF_EPI(E) case E: hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, Acc, OPA, OPB, E>), grid, dim3(256), 0, s, g); break;
+        NEGF_EPI(EPI_STORE) NEGF_EPI(EPI_ADD) NEGF_EPI(EPI_ADD_TTD) NEGF_EPI(EPI_DUAL) NEGF_EPI(EPI_IMINUS) NEGF_EPI(EPI_SUB)
+#undef NEGF_EPI
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename TA, typename TB, typename TC, typename Acc>
+static hipError_t launch_ops(hipStream_t s, int opa, int opb, int epi, const GemmArgs& g, dim3 grid) {
+    if (opa == OP_N && opb == OP_N) return launch_epi<TA, TB, TC, Acc, OP_N, OP_N>(s, epi, g, grid);
+    if (opa == OP_N && opb == OP_C) return launch_epi<TA, TB, TC, Acc, OP_N, OP_C>(s, epi, g, grid);
+    if (opa == OP_C && opb == OP_N) return launch_epi<TA, TB, TC, Acc, OP_C, OP_N>(s, epi, g, grid);
+    return launch_epi<TA, TB, TC, Acc, OP_C, OP_C>(s, epi, g, grid);
+}
+
+hipError_t gemm_launch(hipStream_t s, GemmTypes ty, int opa, int opb, int epi, const GemmArgs& g) {
+    if (g.np <= 0 || g.n <= 0) return hipSuccess;
+    const int tiles = (g.n + BM - 1) / BM;
+    dim3 grid((unsigned)((long long)g.np * tiles * tiles));
+    if (ty.ta == DT_C128 && ty.tb == DT_C128 && ty.tc == DT_C128 && ty.acc == DT_C128)
+        return launch_ops<double2, double2, double2, double>(s, opa, opb, epi, g, grid);
+    if (ty.ta == DT_C64 && ty.tb == DT_C64 && ty.tc == DT_C64 && ty.acc == DT_C64)
+        return launch_ops<float2, float2, float2, float>(s, opa, opb, epi, g, grid);
+    // Mixed-precision refinement: FP64 residual R = I - A X0 with X0 in FP32.
+    if (ty.ta == DT_C128 && ty.tb == DT_C64 && ty.tc == DT_C128 && ty.acc == DT_C128 &&
+        opa == OP_N && opb == OP_N && epi == EPI_IMINUS) {
+        hipLaunchKernelGGL((gemm_kernel<double2, float2, double2, double, OP_N, OP_N, EPI_IMINUS>),
+                           grid, dim3(256), 0, s, g);
+        return hipGetLastError();
+    }
+    // Mixed-precision correction X1 = X0 + X0 R in FP32 with R read in FP64.
+    if (ty.ta == DT_C64 && ty.tb == DT_C128 && ty.tc == DT_C64 && ty.acc == DT_C64 &&
+        opa == OP_N && opb == OP_N && epi == EPI_ADD) {
+        hipLaunchKernelGGL((gemm_kernel<float2, double2, float2, float, OP_N, OP_N, EPI_ADD>),
+                           grid, dim3(256), 0, s, g);
+        return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace negf

@@ -1,0 +1,57 @@
+// Host-side launchers shared by the library's translation units.
+#pragma once
+#include "negf_common.hpp"
+
+namespace negf {
+
+// ------------------------------------------------------------- batched GEMM
+enum Op : int { OP_N = 0, OP_C = 1 };   // op(X) = X or X^dagger
+enum Epi : int {
+    EPI_STORE = 0,     // C = op(A) op(B)
+    EPI_ADD = 1,       // C = D + op(A) op(B)
+    EPI_ADD_TTD = 2,   // C = D + op(A) op(B) + T - T^dagger
+    EPI_DUAL = 3,      // C += op(A) op(B);  C2 += op(A) op(B)
+    EPI_IMINUS = 4,    // C = I - op(A) op(B)
+    EPI_SUB = 5,       // C = D - op(A) op(B)
+};
+enum Dt : int { DT_C128 = 0, DT_C64 = 1 };
+
+// One batched product over points q in [0, np): every operand X of point q
+// sits at X + q * sX (elements of its own type).
+struct GemmArgs {
+    const void* A; long long sA;
+    const void* B; long long sB;
+    void* C; long long sC;
+    const void* D; long long sD;
+    const void* T; long long sT;
+    void* C2; long long sC2;
+    int n;
+    int np;
+    Active act;
+};
+
+struct GemmTypes {
+    int ta, tb, tc;   // Dt of A, B and of C/D/T/C2
+    int acc;          // DT_C128: FP64 MFMA, DT_C64: FP32 MFMA
+};
+
+// Launches C = op(A) op(B) (+ epilogue).  Returns hipError_t.
+hipError_t gemm_launch(hipStream_t s, GemmTypes ty, int opa, int opb, int epi, const GemmArgs& g);
+
+// ------------------------------------------------- batched block inverse
+struct InvWork {
+    void* pa;            // ping-pong partner of the source matrix, [np][n][n]
+    void* E;             // panel buffer [np][n][NB] (complex, matrix type)
+    void* Prow;          // pivot rows [np][NB][n]
+    int* rowsrc;         // [np][n]
+    int* piv;            // [np][n]
+    int* coldst;         // [np][n]
+    int* status;
+};
+// dst = src^-1 for every active point (Gauss-Jordan, partial pivoting).  src
+// is destroyed.  dt = DT_C128 or DT_C64 (matrix and arithmetic type).
+hipError_t inverse_init();
+hipError_t inverse_launch(hipStream_t s, int dt, void* src, long long s_src, void* dst, long long s_dst,
+                          int n, int np, const Active& act, const InvWork& w);
+
+}  // namespace negf

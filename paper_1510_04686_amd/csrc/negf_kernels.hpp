@@ -1,0 +1,94 @@
+// Argument blocks and launchers of the non-GEMM kernels.
+#pragma once
+#include "negf_internal.hpp"
+
+namespace negf {
+
+struct SandArgs {
+    const void* X; long long sX;        // X operand per point (NULL: no sandwich term)
+    const double2* hup; long long hup_k;  // H_{i,i+1} blocks and their k stride (elements)
+    int ub, tile;                       // coupling block size and output tile edge
+    int uslab;                          // local slab index u of U = H_{u,u+1}
+    int opL, opR;                       // 0: none, 1: U, 2: U^dagger
+    double sign;
+    void* O; long long sO;
+    int mode;                           // 0 plain, 1 retarded assembly, 2 lesser assembly
+    int slab;                           // local slab index of the assembled block
+    const double2* hdiag; long long hdiag_k;
+    const double* v;                    // [total][n] or NULL
+    const double2* scat;                // [n_e][total][n] or NULL (R for mode 1, < for mode 2)
+    long long total;
+    const double2* sigL; const double2* sigR; int n_e;
+    const double* energy; double eta, muL, muR, kT; int eta_fill;
+    int n, np;
+    Active act;
+    PointSet ps;
+};
+
+struct ExtArgs {
+    const void* G; const void* GL; long long sG;
+    double2* outR; double2* outL; double2* outG;
+    int full, slab_stride, slab, n, np, p0;
+    Active act;
+};
+
+struct BondArgs {
+    const double2* hup; long long hup_k;
+    int ub, slab;
+    const void* G; const void* GL; const void* Q; const void* L; long long sM;
+    double* partial;                    // [np][8]
+    int n, np;
+    Active act;
+    PointSet ps;
+};
+
+struct SrArgs {
+    const double2* h00; const double2* h01; const double2* tauin;   // [n_k][n][n]
+    double2 *eps_s, *eps, *alpha, *beta, *tau;                      // [np][n][n]
+    int* flags; int* iters; double* ref; int* count;
+    const double* energy; double eta, tol;
+    long long f0;
+    int n, n_e, np;
+};
+
+struct ScbaArgs {
+    const double2* GR; const double2* GL;     // [n_k][n_e][slab_stride][n]
+    const double* w_k;
+    double D, M, n0;
+    int shift, n_k, n_e, N, n, slab_stride;
+    double2* sigR; double2* sigL;             // [n_e][N][n]
+    double* partial;
+};
+
+struct ObsArgs {
+    const double2* GL; const double* bond;
+    int slab_stride;
+    const double* w_e; const double* w_k;
+    double g_s;
+    int opa, n, n_e, n_samples;
+    long long total;
+    const int4* desc; const long long* slab_off; const int* slab_sample;
+    const int* csr_off; const int* csr_pts;
+    double* orb_tmp; double* n_out; double* J; double* jE;
+};
+
+int sandwich_tile(int ub);
+size_t sandwich_lds(int ub);
+hipError_t sandwich_init();
+hipError_t sandwich_launch(hipStream_t s, int xdt, int odt, const SandArgs& a);
+hipError_t copy_launch(hipStream_t s, int tdi, int tdo, const void* src, long long ss, void* dst, long long sd,
+                       long long nel, int np, const Active& act);
+hipError_t extract_launch(hipStream_t s, int dt, const ExtArgs& a);
+hipError_t bond_launch(hipStream_t s, int dt, const BondArgs& a, double* out, int slab_stride);
+hipError_t gamma_launch(hipStream_t s, int dt, const double2* sig, int n_e, const PointSet& ps, void* out,
+                        long long so, int n, int np);
+hipError_t trace_prod_launch(hipStream_t s, int dt, const void* W1, const void* W2, long long sw, int n, int np,
+                             double* out, int p0);
+hipError_t sr_launch_init(hipStream_t s, const SrArgs& a);
+hipError_t sr_launch_zminus(hipStream_t s, const SrArgs& a, const double2* X, double2* M, const Active& act);
+hipError_t sr_launch_check(hipStream_t s, const SrArgs& a, const double2* alpha, const double2* beta, int it);
+hipError_t sr_launch_iters(hipStream_t s, const SrArgs& a, int* out);
+hipError_t scba_launch(hipStream_t s, const ScbaArgs& a, double* rel_change);
+hipError_t observables_launch(hipStream_t s, const ObsArgs& a);
+
+}  // namespace negf

@@ -1,0 +1,113 @@
+// MFMA tile helpers shared by the batched GEMM and the block-inverse update.
+#pragma once
+#include "negf_common.hpp"
+
+namespace negf {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <typename Acc> struct MF;
+template <> struct MF<double> {
+    typedef v4d V;
+    __device__ static inline V mma(double a, double b, V c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct MF<float> {
+    typedef v4f V;
+    __device__ static inline V mma(float a, float b, V c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+
+// Row (within a 16 x 16 output block) held in accumulator register r of `lane`;
+// the column is lane % 16.  The two 16x16x4 forms differ:
+//   f64: D[i][j] in lane j + 16 (i % 4), register i / 4
+//   f32: D[i][j] in lane j + 16 (i / 4), register i % 4
+template <typename Acc> __device__ inline int out_row(int lane, int r);
+template <> __device__ inline int out_row<double>(int lane, int r) { return (lane >> 4) + 4 * r; }
+template <> __device__ inline int out_row<float>(int lane, int r) { return (lane >> 4) * 4 + r; }
+
+constexpr int BM = 64;   // tile rows = tile cols
+constexpr int BK = 16;   // K slice
+constexpr int LP = 80;   // LDS row stride (elements): rows k, k+1 of a fragment read land on disjoint banks
+
+// Loads one K slice of op(X) into registers.
+//   OUTER_K = false ("pattern X"): 64 source rows (outer index), 16 contiguous k.
+//   OUTER_K = true  ("pattern Y"): 16 source rows (k), 64 contiguous outer indices.
+template <typename TX, bool KROWS>
+__device__ inline void load_slice(const TX* __restrict__ X, int n, int o0, int k0, int tid, TX (&r)[4]) {
+    int row, col;
+    if (!KROWS) { row = o0 + (tid >> 2); col = k0 + (tid & 3) * 4; }
+    else        { row = k0 + (tid >> 4); col = o0 + (tid & 15) * 4; }
+    const TX* p = X + (long long)row * n + col;
+    if (row < n && col + 3 < n) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) r[j] = p[j];
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (row < n && col + j < n) r[j] = p[j];
+            else { r[j].x = 0; r[j].y = 0; }
+        }
+    }
+}
+
+// Writes the register slice into LDS planes S[re/im][k][outer] (conjugated if CONJ).
+template <typename Acc, typename TX, bool KROWS, bool CONJ>
+__device__ inline void store_slice(Acc (*S)[BK][LP], int tid, const TX (&r)[4]) {
+    if (!KROWS) {
+        int o = tid >> 2, k = (tid & 3) * 4;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            S[0][k + j][o] = (Acc)r[j].x;
+            S[1][k + j][o] = CONJ ? -(Acc)r[j].y : (Acc)r[j].y;
+        }
+    } else {
+        int k = tid >> 4, o = (tid & 15) * 4;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            S[0][k][o + j] = (Acc)r[j].x;
+            S[1][k][o + j] = CONJ ? -(Acc)r[j].y : (Acc)r[j].y;
+        }
+    }
+}
+
+template <typename Acc, int MI, int NJ>
+__device__ inline void mma_slice(Acc (*As)[BK][LP], Acc (*Bs)[BK][LP], int lane, int wm, int wn,
+                                 typename MF<Acc>::V (&cr)[2][2], typename MF<Acc>::V (&ci)[2][2]) {
+    const int o = lane & 15;
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk) {
+        const int k = kk * 4 + (lane >> 4);
+        Acc ar[MI], ai[MI], nai[MI], br[NJ], bi[NJ];
+#pragma unroll
+        for (int mi = 0; mi < MI; ++mi) {
+            ar[mi] = As[0][k][wm * 32 + mi * 16 + o];
+            ai[mi] = As[1][k][wm * 32 + mi * 16 + o];
+            nai[mi] = -ai[mi];
+        }
+#pragma unroll
+        for (int nj = 0; nj < NJ; ++nj) {
+            br[nj] = Bs[0][k][wn * 32 + nj * 16 + o];
+            bi[nj] = Bs[1][k][wn * 32 + nj * 16 + o];
+        }
+#pragma unroll
+        for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+            for (int nj = 0; nj < NJ; ++nj) {
+                cr[mi][nj] = MF<Acc>::mma(ar[mi], br[nj], cr[mi][nj]);
+                ci[mi][nj] = MF<Acc>::mma(ar[mi], bi[nj], ci[mi][nj]);
+            }
+#pragma unroll
+        for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+            for (int nj = 0; nj < NJ; ++nj) {
+                cr[mi][nj] = MF<Acc>::mma(nai[mi], bi[nj], cr[mi][nj]);
+                ci[mi][nj] = MF<Acc>::mma(ai[mi], br[nj], ci[mi][nj]);
+            }
+    }
+}
+
+}  // namespace negf

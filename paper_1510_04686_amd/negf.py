@@ -1,0 +1,258 @@
+"""ctypes binding of the C ABI declared in include/negf.h.
+
+Argument marshalling only: every function has the name of the C entry point it
+calls, takes torch tensors already on the GPU, checks dtype / contiguity /
+device, and passes raw pointers.  No arithmetic of the method happens here.
+The library must have been built (paper_1510_04686_amd.build); loading fails
+loudly otherwise -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int, c_longlong, c_void_p
+
+import torch
+
+from .build import LIB_PATH
+
+_lib = None
+
+NEGF_FP64 = 0
+NEGF_MIXED = 1
+NEGF_WANT_TRANSMISSION = 1
+
+STATUS = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "ENOMEM", -4: "EHIP", -5: "ESTATE",
+          1: "WNOCONV", 2: "WSINGULAR", 3: "WNONFINITE", 4: "WFALLBACK"}
+
+
+class NegfError(RuntimeError):
+    def __init__(self, fn, code):
+        super().__init__(f"{fn} failed: {STATUS.get(code, code)} ({lib().negf_error_string(code).decode()})")
+        self.code = code
+
+
+class negf_config(ctypes.Structure):
+    _fields_ = [("nb", c_int), ("n_slab_max", c_int), ("capacity", c_int), ("precision", c_int)]
+
+
+class negf_system(ctypes.Structure):
+    _fields_ = [
+        ("nb", c_int), ("n_samples", c_int), ("slab_offset", POINTER(c_longlong)),
+        ("n_k", c_int), ("n_e", c_int),
+        ("h_diag", c_void_p), ("h_up", c_void_p), ("h_up_k_stride", c_longlong), ("up_block", c_int),
+        ("v_onsite", c_void_p), ("energy", c_void_p),
+        ("eta", c_double), ("mu_L", c_double), ("mu_R", c_double), ("kT", c_double),
+        ("eta_fill", c_int),
+    ]
+
+
+EXPORTS = [
+    "negf_create", "negf_destroy", "negf_workspace_bytes", "negf_sync_status", "negf_error_string",
+    "negf_bind", "negf_lead_selfenergy", "negf_rgf_forward", "negf_rgf_backward",
+    "negf_scba_selfenergy", "negf_observables", "negf_zgemm_batched", "negf_zinv_batched", "negf_mixed_stats",
+    "negf_gemm_timing_enable", "negf_gemm_timing",
+]
+
+
+def lib():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} missing (run paper_1510_04686_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i, d, ll = c_void_p, c_int, c_double, c_longlong
+    sig = {
+        "negf_create": (i, [POINTER(negf_config), POINTER(vp)]),
+        "negf_destroy": (None, [vp]),
+        "negf_workspace_bytes": (ll, [vp]),
+        "negf_sync_status": (i, [vp, vp]),
+        "negf_error_string": (ctypes.c_char_p, [i]),
+        "negf_bind": (i, [vp, POINTER(negf_system), i, POINTER(c_int)]),
+        "negf_lead_selfenergy": (i, [vp, vp, i, vp, vp, vp, i, vp, d, d, i, vp, vp]),
+        "negf_rgf_forward": (i, [vp, vp, i, i, vp, vp, vp, vp, i]),
+        "negf_rgf_backward": (i, [vp, vp, i, i, vp, vp, vp, i, i, vp, vp]),
+        "negf_scba_selfenergy": (i, [vp, vp, vp, vp, i, vp, d, d, i, d, vp, vp, vp]),
+        "negf_observables": (i, [vp, vp, vp, vp, i, vp, vp, d, i, vp, vp, vp]),
+        "negf_zgemm_batched": (i, [vp, vp, i, i, i, i, vp, vp, vp, i]),
+        "negf_zinv_batched": (i, [vp, vp, i, i, vp, vp, i]),
+        "negf_mixed_stats": (i, [vp, vp, POINTER(ll), POINTER(d)]),
+        "negf_gemm_timing_enable": (i, [vp, i]),
+        "negf_gemm_timing": (i, [vp, vp, POINTER(ll), POINTER(d), POINTER(d)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(fn, code, warn_ok=False):
+    if code < 0 or (code > 0 and not warn_ok):
+        raise NegfError(fn, code)
+    return code
+
+
+def _ptr(t, dtype=None, name="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    return t.data_ptr()
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return c_void_p(s.cuda_stream)
+
+
+class Context:
+    """Owns a negf_ctx handle (negf_create / negf_destroy)."""
+
+    def __init__(self, handle, cfg):
+        self.handle = handle
+        self.cfg = cfg
+        self._keep = []
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            try:
+                lib().negf_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+
+def negf_create(nb, n_slab_max, capacity, precision=NEGF_FP64):
+    cfg = negf_config(nb, n_slab_max, capacity, precision)
+    h = c_void_p()
+    _check("negf_create", lib().negf_create(ctypes.byref(cfg), ctypes.byref(h)))
+    return Context(h, cfg)
+
+
+def negf_workspace_bytes(ctx):
+    return int(lib().negf_workspace_bytes(ctx.handle))
+
+
+def negf_sync_status(ctx, stream=None):
+    return int(lib().negf_sync_status(ctx.handle, _stream(stream)))
+
+
+def negf_bind(ctx, nb, slab_offset, n_k, n_e, h_diag, h_up, h_up_k_stride, up_block, v_onsite, energy,
+              eta, mu_L, mu_R, kT, eta_fill, points):
+    """slab_offset and points are host sequences; the tensors are device tensors
+    kept alive by the context while bound."""
+    import numpy as np
+    off = np.ascontiguousarray(np.asarray(slab_offset, dtype=np.int64))
+    pts = np.ascontiguousarray(np.asarray(points, dtype=np.int32).reshape(-1, 3))
+    sys_ = negf_system(
+        nb, len(off) - 1, off.ctypes.data_as(POINTER(c_longlong)), n_k, n_e,
+        _ptr(h_diag, torch.complex128, "h_diag"), _ptr(h_up, torch.complex128, "h_up"), int(h_up_k_stride),
+        int(up_block), _ptr(v_onsite, torch.float64, "v_onsite"), _ptr(energy, torch.float64, "energy"),
+        float(eta), float(mu_L), float(mu_R), float(kT), int(eta_fill))
+    code = lib().negf_bind(ctx.handle, ctypes.byref(sys_), len(pts), pts.ctypes.data_as(POINTER(c_int)))
+    _check("negf_bind", code)
+    ctx._keep = [h_diag, h_up, v_onsite, energy]
+
+
+def negf_lead_selfenergy(ctx, h00, h01, tau, energy, eta, tol, max_iter, sigma, iters=None, stream=None):
+    n_k = h00.shape[0]
+    n_e = energy.shape[0]
+    code = lib().negf_lead_selfenergy(
+        ctx.handle, _stream(stream), n_k, _ptr(h00, torch.complex128, "h00"), _ptr(h01, torch.complex128, "h01"),
+        _ptr(tau, torch.complex128, "tau"), n_e, _ptr(energy, torch.float64, "energy"), float(eta), float(tol),
+        int(max_iter), _ptr(sigma, torch.complex128, "sigma"), _ptr(iters, torch.int32, "iters"))
+    return _check("negf_lead_selfenergy", code, warn_ok=True)
+
+
+def negf_rgf_forward(ctx, p0, np_, sigma_L, sigma_R, scat_R=None, scat_L=None, flags=0, stream=None):
+    code = lib().negf_rgf_forward(
+        ctx.handle, _stream(stream), int(p0), int(np_), _ptr(sigma_L, torch.complex128, "sigma_L"),
+        _ptr(sigma_R, torch.complex128, "sigma_R"), _ptr(scat_R, torch.complex128, "scat_R"),
+        _ptr(scat_L, torch.complex128, "scat_L"), int(flags))
+    _check("negf_rgf_forward", code)
+
+
+def negf_rgf_backward(ctx, p0, np_, GR=None, GL=None, GG=None, full_blocks=0, slab_stride=1, bond_j=None,
+                      transmission=None, stream=None):
+    code = lib().negf_rgf_backward(
+        ctx.handle, _stream(stream), int(p0), int(np_), _ptr(GR, torch.complex128, "GR"),
+        _ptr(GL, torch.complex128, "GL"), _ptr(GG, torch.complex128, "GG"), int(full_blocks), int(slab_stride),
+        _ptr(bond_j, torch.float64, "bond_j"), _ptr(transmission, torch.float64, "transmission"))
+    _check("negf_rgf_backward", code)
+
+
+def negf_scba_selfenergy(ctx, GR, GL, slab_stride, w_k, D_ac, M_op, shift, n_bose, sig_R, sig_L, rel_change=None,
+                         stream=None):
+    code = lib().negf_scba_selfenergy(
+        ctx.handle, _stream(stream), _ptr(GR, torch.complex128, "GR"), _ptr(GL, torch.complex128, "GL"),
+        int(slab_stride), _ptr(w_k, torch.float64, "w_k"), float(D_ac), float(M_op), int(shift), float(n_bose),
+        _ptr(sig_R, torch.complex128, "sig_R"), _ptr(sig_L, torch.complex128, "sig_L"),
+        _ptr(rel_change, torch.float64, "rel_change"))
+    _check("negf_scba_selfenergy", code)
+
+
+def negf_observables(ctx, GL, bond_j, slab_stride, w_e, w_k, g_s, orbs_per_atom, n=None, J=None, j_E=None,
+                     stream=None):
+    code = lib().negf_observables(
+        ctx.handle, _stream(stream), _ptr(GL, torch.complex128, "GL"), _ptr(bond_j, torch.float64, "bond_j"),
+        int(slab_stride), _ptr(w_e, torch.float64, "w_e"), _ptr(w_k, torch.float64, "w_k"), float(g_s),
+        int(orbs_per_atom), _ptr(n, torch.float64, "n"), _ptr(J, torch.float64, "J"),
+        _ptr(j_E, torch.float64, "j_E"))
+    _check("negf_observables", code)
+
+
+def _cdt(t):
+    if t.dtype == torch.complex128:
+        return 0
+    if t.dtype == torch.complex64:
+        return 1
+    raise TypeError("complex128 or complex64 expected")
+
+
+def negf_zgemm_batched(ctx, A, B, C, opa=0, opb=0, stream=None):
+    """C[b] = op(A[b]) op(B[b]) for [batch, n, n] tensors of one complex dtype."""
+    batch, n = A.shape[0], A.shape[-1]
+    dt = A.dtype
+    code = lib().negf_zgemm_batched(ctx.handle, _stream(stream), int(n), int(batch), int(opa), int(opb),
+                                    _ptr(A, dt, "A"), _ptr(B, dt, "B"), _ptr(C, dt, "C"), _cdt(A))
+    _check("negf_zgemm_batched", code)
+
+
+def negf_zinv_batched(ctx, A, Ainv, stream=None):
+    """Ainv[b] = A[b]^-1 ([batch, n, n]); A is overwritten."""
+    batch, n = A.shape[0], A.shape[-1]
+    dt = A.dtype
+    code = lib().negf_zinv_batched(ctx.handle, _stream(stream), int(n), int(batch), _ptr(A, dt, "A"),
+                                   _ptr(Ainv, dt, "Ainv"), _cdt(A))
+    _check("negf_zinv_batched", code)
+
+
+def negf_mixed_stats(ctx, stream=None):
+    nf = c_longlong()
+    mr = c_double()
+    _check("negf_mixed_stats", lib().negf_mixed_stats(ctx.handle, _stream(stream), ctypes.byref(nf), ctypes.byref(mr)))
+    return int(nf.value), float(mr.value)
+
+
+def negf_gemm_timing_enable(ctx, enable=True):
+    _check("negf_gemm_timing_enable", lib().negf_gemm_timing_enable(ctx.handle, int(bool(enable))))
+
+
+def negf_gemm_timing(ctx, stream=None):
+    n = c_longlong()
+    ms = c_double()
+    fl = c_double()
+    _check("negf_gemm_timing", lib().negf_gemm_timing(ctx.handle, _stream(stream), ctypes.byref(n),
+                                                       ctypes.byref(ms), ctypes.byref(fl)))
+    return int(n.value), float(ms.value), float(fl.value)

@@ -1,0 +1,185 @@
+"""Host driver: uploads a workload, then issues the C ABI calls in order.
+
+Leads once per (k, E) grid -> batched forward / backward sweeps over the bound
+points (`capacity` points per call) -> observables; the SCBA loop captures one
+whole iteration (self-energy update + every batch) into a HIP graph and
+replays it.  All arithmetic runs in the HIP library; this module only
+allocates device buffers and sequences calls.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+from . import negf as N
+
+
+def _dev(a, dtype, device):
+    a = np.ascontiguousarray(a)
+    if not a.flags.writeable:
+        a = a.copy()
+    return torch.from_numpy(a).to(device=device, dtype=dtype)
+
+
+class RGFSolver:
+    """Batched RGF over every (sample, k, E) point of a workload on one GPU."""
+
+    def __init__(self, wl, precision="fp64", capacity=None, device="cuda", mem_fraction=0.6):
+        self.wl = wl
+        self.device = torch.device(device)
+        self.prec = N.NEGF_MIXED if precision == "mixed" else N.NEGF_FP64
+        nb = wl.nb
+        counts = np.diff(wl.slab_offset).astype(np.int64)
+        self.n_slab_max = int(counts.max())
+        self.slab_stride = self.n_slab_max
+        # Longest sample first, so every launch covers only an active prefix.
+        order = np.argsort(-counts, kind="stable")
+        pts = [(int(s), ik, ie) for s in order for ik in range(wl.n_k) for ie in range(wl.n_e)]
+        self.points = np.array(pts, dtype=np.int32).reshape(-1, 3)
+        self.n_points = len(self.points)
+        # index of the bound point of each (sample, ik, ie)
+        self.index = {tuple(p): i for i, p in enumerate(self.points.tolist())}
+        c128, f64 = torch.complex128, torch.float64
+        self.h_diag = _dev(wl.h_diag, c128, self.device)
+        self.h_up = _dev(wl.h_up, c128, self.device)
+        self.energy = _dev(wl.energy, f64, self.device)
+        self.w_e = _dev(wl.w_e, f64, self.device)
+        self.w_k = _dev(wl.w_k, f64, self.device)
+        self.v = None if wl.v_onsite is None else _dev(wl.v_onsite, f64, self.device)
+        nk = wl.n_k
+        self.lead_h00 = _dev(wl.lead_h00, c128, self.device)
+        rep = lambda m: _dev(np.broadcast_to(m, (nk, nb, nb)), c128, self.device)
+        self.lead_h01_L, self.lead_tau_L = rep(wl.lead_h01_L), rep(wl.lead_tau_L)
+        self.lead_h01_R, self.lead_tau_R = rep(wl.lead_h01_R), rep(wl.lead_tau_R)
+        if capacity is None:
+            ce = 8 if self.prec == N.NEGF_MIXED else 16
+            per_point = 2 * self.n_slab_max * nb * nb * ce + 15 * nb * nb * 16 + 64 * nb * 16
+            free, _ = torch.cuda.mem_get_info(self.device)
+            capacity = int(max(1, min(self.n_points, 256, (free * mem_fraction) // per_point)))
+        self.capacity = int(capacity)
+        self.ctx = N.negf_create(nb, self.n_slab_max, self.capacity, self.prec)
+        self.eta_fill = 0
+        self._bind()
+        self.sigma_L = self.sigma_R = None
+
+    def _bind(self):
+        wl = self.wl
+        N.negf_bind(self.ctx, wl.nb, wl.slab_offset, wl.n_k, wl.n_e, self.h_diag, self.h_up, 0, wl.up_block,
+                    self.v, self.energy, wl.eta, wl.mu_L, wl.mu_R, wl.kT, self.eta_fill, self.points)
+
+    def set_eta_fill(self, on: bool):
+        self.eta_fill = int(bool(on))
+        self._bind()
+
+    def set_potential(self, v_orb: torch.Tensor):
+        self.v = v_orb.contiguous()
+        self._bind()
+
+    # ------------------------------------------------------------------ leads
+    def lead_selfenergies(self, tol=1e-14, max_iter=100):
+        wl = self.wl
+        shape = (wl.n_k, wl.n_e, wl.nb, wl.nb)
+        self.sigma_L = torch.empty(shape, dtype=torch.complex128, device=self.device)
+        self.sigma_R = torch.empty(shape, dtype=torch.complex128, device=self.device)
+        self.iters_L = torch.empty((wl.n_k, wl.n_e), dtype=torch.int32, device=self.device)
+        self.iters_R = torch.empty((wl.n_k, wl.n_e), dtype=torch.int32, device=self.device)
+        cL = N.negf_lead_selfenergy(self.ctx, self.lead_h00, self.lead_h01_L, self.lead_tau_L, self.energy, wl.eta,
+                                    tol, max_iter, self.sigma_L, self.iters_L)
+        cR = N.negf_lead_selfenergy(self.ctx, self.lead_h00, self.lead_h01_R, self.lead_tau_R, self.energy, wl.eta,
+                                    tol, max_iter, self.sigma_R, self.iters_R)
+        self.lead_status = max(cL, cR)
+        return self.sigma_L, self.sigma_R
+
+    # ------------------------------------------------------------------ RGF
+    def alloc_outputs(self, full_blocks=False, want=("GR", "GL", "GG", "bond"), want_T=False):
+        nb, P, S = self.wl.nb, self.n_points, self.slab_stride
+        shp = (P, S, nb, nb) if full_blocks else (P, S, nb)
+        out = {}
+        for k in ("GR", "GL", "GG"):
+            if k in want:
+                out[k] = torch.zeros(shp, dtype=torch.complex128, device=self.device)
+        if "bond" in want:
+            out["bond"] = torch.zeros((P, S), dtype=torch.float64, device=self.device)
+        if want_T:
+            out["T"] = torch.zeros(P, dtype=torch.float64, device=self.device)
+        return out
+
+    def run_batches(self, out, full_blocks=False, want_T=False, scat_R=None, scat_L=None, stream=None):
+        flags = N.NEGF_WANT_TRANSMISSION if want_T else 0
+        for p0 in range(0, self.n_points, self.capacity):
+            np_ = min(self.capacity, self.n_points - p0)
+            N.negf_rgf_forward(self.ctx, p0, np_, self.sigma_L, self.sigma_R, scat_R, scat_L, flags, stream=stream)
+            N.negf_rgf_backward(self.ctx, p0, np_, out.get("GR"), out.get("GL"), out.get("GG"),
+                                int(full_blocks), self.slab_stride, out.get("bond"), out.get("T"), stream=stream)
+
+    def solve(self, full_blocks=False, want=("GR", "GL", "GG", "bond"), want_T=False, scat_R=None, scat_L=None):
+        if self.sigma_L is None:
+            self.lead_selfenergies()
+        out = self.alloc_outputs(full_blocks, want, want_T)
+        self.run_batches(out, full_blocks, want_T, scat_R, scat_L)
+        return out
+
+    def observables(self, GL, bond, g_s=None, spectral=True):
+        wl = self.wl
+        g_s = wl.g_s if g_s is None else g_s
+        n = torch.zeros((wl.total_slabs, wl.atoms_per_slab), dtype=torch.float64, device=self.device)
+        J = torch.zeros(wl.total_slabs, dtype=torch.float64, device=self.device)
+        jE = (torch.zeros((wl.n_samples, wl.n_e, self.slab_stride), dtype=torch.float64, device=self.device)
+              if spectral else None)
+        N.negf_observables(self.ctx, GL, bond, self.slab_stride, self.w_e, self.w_k, g_s, wl.orbs_per_atom,
+                           n, J, jE)
+        return n, J, jE
+
+    def status(self):
+        return N.negf_sync_status(self.ctx)
+
+    # ------------------------------------------------------------------ SCBA
+    def scba(self, n_iter=None, graph=True):
+        """Self-consistent Born loop (Eqs. 1-6) for a single-sample grid
+        workload.  One iteration = scattering self-energy update from the last
+        diagonals + a full forward/backward pass; captured once into a HIP
+        graph and replayed when ``graph`` is true."""
+        wl = self.wl
+        assert wl.n_samples == 1
+        n_iter = wl.n_scba if n_iter is None else n_iter
+        if self.sigma_L is None:
+            self.lead_selfenergies()
+        Ns = wl.total_slabs
+        shp = (wl.n_e, Ns, wl.nb)
+        self.scat_R = torch.zeros(shp, dtype=torch.complex128, device=self.device)
+        self.scat_L = torch.zeros(shp, dtype=torch.complex128, device=self.device)
+        out = self.alloc_outputs(want=("GR", "GL", "bond"))
+        rel = torch.zeros(1, dtype=torch.float64, device=self.device)
+        hist = []
+        # iteration 0: ballistic pass (Sigma_scat = 0)
+        self.run_batches(out, scat_R=self.scat_R, scat_L=self.scat_L)
+
+        def one_iteration(stream=None):
+            N.negf_scba_selfenergy(self.ctx, out["GR"], out["GL"], self.slab_stride, self.w_k, wl.D_ac, wl.M_op,
+                                   wl.shift, wl.n_bose, self.scat_R, self.scat_L, rel, stream=stream)
+            self.run_batches(out, scat_R=self.scat_R, scat_L=self.scat_L, stream=stream)
+
+        if n_iter <= 1 or not graph:
+            for _ in range(n_iter - 1):
+                one_iteration()
+                hist.append(float(rel.item()))
+        else:
+            g = torch.cuda.CUDAGraph()
+            s = torch.cuda.Stream()
+            s.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(s):
+                torch.cuda.synchronize()
+            with torch.cuda.graph(g, stream=s):
+                one_iteration(stream=s)
+            torch.cuda.current_stream().wait_stream(s)
+            for _ in range(n_iter - 1):
+                g.replay()
+                hist.append(float(rel.item()))
+        # last update: Sigma_n from the n-th solve (the solve itself is not redone)
+        N.negf_scba_selfenergy(self.ctx, out["GR"], out["GL"], self.slab_stride, self.w_k, wl.D_ac, wl.M_op,
+                               wl.shift, wl.n_bose, self.scat_R, self.scat_L, rel)
+        hist.append(float(rel.item()))
+        self.scba_out = out
+        return out, hist

@@ -1,0 +1,114 @@
+"""GPU: the two dense block kernels (batched complex GEMM on MFMA, batched
+Gauss-Jordan inverse) against NumPy, through the C ABI."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1510_04686_amd import negf
+    return negf.negf_create(nb=416, n_slab_max=1, capacity=6)
+
+
+def _rand(rng, shape, dtype=np.complex128):
+    return (rng.normal(size=shape) + 1j * rng.normal(size=shape)).astype(dtype)
+
+
+def _op(a, op):
+    return a.conj().transpose(0, 2, 1) if op else a
+
+
+@pytest.mark.parametrize("n", [1, 3, 16, 17, 64, 65, 100, 130, 400])
+@pytest.mark.parametrize("opa,opb", [(0, 0), (0, 1), (1, 0), (1, 1)])
+def test_zgemm_fp64(ctx, n, opa, opb):
+    from paper_1510_04686_amd import negf
+    _say(f"zgemm fp64 n={n} op=({opa},{opb})")
+    rng = np.random.default_rng(n * 10 + opa * 2 + opb)
+    A, B = _rand(rng, (3, n, n)), _rand(rng, (3, n, n))
+    dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    dC = torch.zeros_like(dA)
+    negf.negf_zgemm_batched(ctx, dA, dB, dC, opa, opb)
+    ref = _op(A, opa) @ _op(B, opb)
+    err = np.max(np.abs(dC.cpu().numpy() - ref)) / np.max(np.abs(ref))
+    assert err < 1e-13 * max(1, np.sqrt(n)), err
+
+
+@pytest.mark.parametrize("n", [5, 64, 100, 400])
+@pytest.mark.parametrize("opa,opb", [(0, 0), (0, 1)])
+def test_zgemm_fp32(ctx, n, opa, opb):
+    from paper_1510_04686_amd import negf
+    _say(f"zgemm fp32 n={n} op=({opa},{opb})")
+    rng = np.random.default_rng(n + 7)
+    A, B = _rand(rng, (2, n, n), np.complex64), _rand(rng, (2, n, n), np.complex64)
+    dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    dC = torch.zeros_like(dA)
+    negf.negf_zgemm_batched(ctx, dA, dB, dC, opa, opb)
+    ref = _op(A.astype(np.complex128), opa) @ _op(B.astype(np.complex128), opb)
+    err = np.max(np.abs(dC.cpu().numpy() - ref)) / np.max(np.abs(ref))
+    assert err < 2e-6 * max(1, np.sqrt(n)), err
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 16, 17, 33, 64, 65, 100, 130, 400])
+def test_zinv_fp64(ctx, n):
+    from paper_1510_04686_amd import negf
+    _say(f"zinv fp64 n={n}")
+    rng = np.random.default_rng(1000 + n)
+    A = _rand(rng, (4, n, n))
+    # matrices 2 and 3 need row exchanges: zero diagonal / permuted identity
+    if n > 1:
+        A[2][np.diag_indices(n)] = 0
+    perm = rng.permutation(n)
+    A[3] = np.eye(n)[perm] + 1e-3 * A[3]
+    ref = np.linalg.inv(A)
+    dA = torch.from_numpy(A.copy()).cuda()
+    dX = torch.zeros_like(dA)
+    negf.negf_zinv_batched(ctx, dA, dX)
+    assert negf.negf_sync_status(ctx) == 0
+    X = dX.cpu().numpy()
+    for b in range(4):
+        cond = np.linalg.cond(A[b])
+        err = np.max(np.abs(X[b] - ref[b])) / np.max(np.abs(ref[b]))
+        assert err < 1e-14 * cond * n + 1e-13, (b, err, cond)
+
+
+@pytest.mark.parametrize("n", [7, 64, 100])
+def test_zinv_fp32(ctx, n):
+    from paper_1510_04686_amd import negf
+    _say(f"zinv fp32 n={n}")
+    rng = np.random.default_rng(2000 + n)
+    A = _rand(rng, (2, n, n), np.complex64) + 4 * np.eye(n, dtype=np.complex64)
+    ref = np.linalg.inv(A.astype(np.complex128))
+    dA = torch.from_numpy(A.copy()).cuda()
+    dX = torch.zeros_like(dA)
+    negf.negf_zinv_batched(ctx, dA, dX)
+    X = dX.cpu().numpy()
+    for b in range(2):
+        cond = np.linalg.cond(A[b])
+        err = np.max(np.abs(X[b] - ref[b])) / np.max(np.abs(ref[b]))
+        assert err < 1e-6 * cond * np.sqrt(n), (b, err, cond)
+
+
+def test_zinv_flags_singular_block(ctx):
+    from paper_1510_04686_amd import negf
+    _say("zinv singular")
+    A = torch.zeros((1, 8, 8), dtype=torch.complex128, device="cuda")
+    X = torch.zeros_like(A)
+    negf.negf_zinv_batched(ctx, A, X)
+    assert negf.negf_sync_status(ctx) in (2, 3)
+    assert negf.negf_sync_status(ctx) == 0     # cleared by the previous read
+
+
+def test_zinv_rejects_oversized(ctx):
+    from paper_1510_04686_amd import negf
+    A = torch.zeros((1, 420, 420), dtype=torch.complex128, device="cuda")
+    with pytest.raises(negf.NegfError):
+        negf.negf_zinv_batched(ctx, A, torch.zeros_like(A))

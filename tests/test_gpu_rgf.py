@@ -1,0 +1,237 @@
+"""GPU parity of the RGF path (leads, forward/backward sweeps, observables,
+SCBA) against the CPU oracle on the same seeded inputs, through the C ABI."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from synth import make_workload, random_tiny
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10   # relative, FP64 path
+
+
+def _say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _solver(wl, **kw):
+    from paper_1510_04686_amd.runtime import RGFSolver
+    return RGFSolver(wl, **kw)
+
+
+def _rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.max(np.abs(a - b)) / max(float(np.max(np.abs(b))), 1e-300))
+
+
+def _ref_and_tol(wl, pts, **kw):
+    """Oracle results plus a per-point tolerance: 1e-10 relative, or 20 x the
+    drift between two correct FP64 evaluations of the point by the oracle itself
+    (default vs alternate association in the lead decimation) where that drift
+    is larger -- the point's own conditioning, measured without the GPU."""
+    ref = O.solve_points(wl, pts, **kw)
+    alt = O.solve_points(wl, pts, variant="alt", **kw)
+    tols = []
+    for r, a in zip(ref, alt):
+        spread = max(_rel(a[k], r[k]) for k in ("GR", "GL", "GG"))
+        if "T" in r:
+            spread = max(spread, abs(a["T"] - r["T"]) / max(1.0, abs(r["T"])))
+        tols.append(max(TOL, 20.0 * spread))
+    return ref, tols
+
+
+def _check_point(out, p, r, N, full=False, T=False, tol=TOL):
+    gr = out["GR"][p, :N].cpu().numpy()
+    gl = out["GL"][p, :N].cpu().numpy()
+    gg = out["GG"][p, :N].cpu().numpy()
+    if full:
+        rr, rl, rg = r["GR"], r["GL"], r["GG"]
+    else:
+        d = lambda x: np.diagonal(x, axis1=1, axis2=2)
+        rr, rl, rg = d(r["GR"]), d(r["GL"]), d(r["GG"])
+    assert _rel(gr, rr) < tol, ("GR", _rel(gr, rr))
+    assert _rel(gl, rl) < tol, ("GL", _rel(gl, rl))
+    assert _rel(gg, rg) < tol, ("GG", _rel(gg, rg))
+    if N > 1:
+        b = out["bond"][p, :N - 1].cpu().numpy()
+        scale = max(np.max(np.abs(r["bond"])), 1e-300)
+        # bond currents are small differences of O(|G^<|) terms: compare on that scale
+        ref_scale = max(scale, 1e-6 * np.max(np.abs(rl)))
+        assert np.max(np.abs(b - r["bond"])) < tol * 10 * ref_scale, ("bond", b, r["bond"])
+    if T:
+        t = float(out["T"][p])
+        assert abs(t - r["T"]) < tol * max(1.0, abs(r["T"])), ("T", t, r["T"])
+
+
+# ---------------------------------------------------------------------------
+# Leads
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("nb,seed", [(1, 0), (6, 1), (20, 2)])
+def test_lead_selfenergy_matches_oracle(nb, seed):
+    _say(f"leads tiny nb={nb}")
+    wl = random_tiny(nb, 2, n_e=5, seed=seed, eta=1e-4)
+    s = _solver(wl)
+    sL, sR = s.lead_selfenergies()
+    torch.cuda.synchronize()
+    assert s.lead_status == 0
+    for ie in range(wl.n_e):
+        z = wl.energy[ie] + 1j * wl.eta
+        rL, itL, _ = O.lead_selfenergy(wl.lead_h00[0], wl.lead_h01_L, wl.lead_tau_L, z)
+        rR, itR, _ = O.lead_selfenergy(wl.lead_h00[0], wl.lead_h01_R, wl.lead_tau_R, z)
+        aL, _, _ = O.lead_selfenergy(wl.lead_h00[0], wl.lead_h01_L, wl.lead_tau_L, z, variant="alt")
+        aR, _, _ = O.lead_selfenergy(wl.lead_h00[0], wl.lead_h01_R, wl.lead_tau_R, z, variant="alt")
+        tL = max(TOL, 20 * _rel(aL, rL))
+        tR = max(TOL, 20 * _rel(aR, rR))
+        assert _rel(sL[0, ie].cpu().numpy(), rL) < tL
+        assert _rel(sR[0, ie].cpu().numpy(), rR) < tR
+        assert abs(int(s.iters_L[0, ie]) - itL) <= 1 and abs(int(s.iters_R[0, ie]) - itR) <= 1
+
+
+def test_lead_selfenergy_reports_iteration_cap():
+    _say("leads max_iter=1")
+    wl = random_tiny(4, 2, n_e=2, seed=3, eta=1e-6)
+    s = _solver(wl)
+    s.lead_selfenergies(max_iter=1)
+    assert s.lead_status == 1
+
+
+# ---------------------------------------------------------------------------
+# RGF sweeps
+# ---------------------------------------------------------------------------
+
+def _scat(wl, seed):
+    rng = np.random.default_rng(seed)
+    shp = (wl.n_e, wl.total_slabs, wl.nb)
+    sR = rng.normal(size=shp) * 0.02 - 0.03j * rng.uniform(size=shp)
+    sL = 0.02j * rng.uniform(size=shp)
+    return sR, sL
+
+
+@pytest.mark.parametrize("nb,N,up,seed", [(1, 1, None, 0), (3, 2, None, 1), (8, 5, 2, 2), (12, 4, 4, 3),
+                                          (20, 3, 10, 4), (70, 3, 10, 5), (72, 2, 8, 6), (40, 6, 40, 7)])
+@pytest.mark.parametrize("full", [False, True])
+def test_rgf_matches_oracle_tiny(nb, N, up, seed, full):
+    _say(f"rgf tiny nb={nb} N={N} up={up} full={full}")
+    wl = random_tiny(nb, N, n_e=3, seed=seed, up_block=up, eta=1e-3)
+    rng = np.random.default_rng(seed)
+    wl.v_onsite = rng.uniform(0, 0.3, size=(N, nb))
+    scR, scL = _scat(wl, seed)
+    s = _solver(wl)
+    s.lead_selfenergies()
+    dR = torch.from_numpy(scR).cuda()
+    dL = torch.from_numpy(scL).cuda()
+    out = s.solve(full_blocks=full, want_T=True, scat_R=dR, scat_L=dL)
+    torch.cuda.synchronize()
+    assert s.status() == 0
+    ref, tols = _ref_and_tol(wl, [tuple(p) for p in s.points], scatR=scR, scatL=scL, transmission=True)
+    for p, r in enumerate(ref):
+        _check_point(out, p, r, N, full=full, T=True, tol=tols[p])
+
+
+def test_rgf_strip_workload_all_energies():
+    _say("rgf C1 strip, 256 energies")
+    wl = make_workload("C1")
+    s = _solver(wl)
+    out = s.solve(want_T=True)
+    torch.cuda.synchronize()
+    assert s.status() == 0
+    ref, tols = _ref_and_tol(wl, [tuple(p) for p in s.points], transmission=True)
+    for p, r in enumerate(ref):
+        _check_point(out, p, r, wl.total_slabs, T=True, tol=tols[p])
+
+
+def test_rgf_ordered_strip_integer_transmission_on_gpu():
+    from synth import strip_workload
+    _say("rgf ordered strip integer T")
+    wl = strip_workload(width=8, disorder=0.0, n_slab=20, eta=1e-9, n_e=64, e_lo=-3.9, e_hi=3.9)
+    s = _solver(wl)
+    s.lead_selfenergies(max_iter=200)
+    out = s.solve(want_T=True, want=("GR", "GL", "GG", "bond"))
+    T = out["T"].cpu().numpy()
+    eps = -2 * np.cos(np.arange(1, 9) * np.pi / 9)
+    for ie, E in enumerate(wl.energy):
+        if np.min(np.abs(np.abs(E - eps) - 2)) < 0.05:
+            continue
+        assert abs(T[ie] - np.sum(np.abs(E - eps) < 2)) < 1e-5
+
+
+def test_rgf_ragged_samples_and_observables():
+    _say("rgf ragged multi-sample + observables")
+    wl = make_workload("C4", n_slab=8, n_e=4, n_z=2, n_y=2, n_samples=5)
+    counts = np.diff(wl.slab_offset)
+    assert len(set(counts.tolist())) > 1
+    s = _solver(wl, capacity=7)      # batches straddle samples of different length
+    out = s.solve(want_T=True)
+    n, J, jE = s.observables(out["GL"], out["bond"])
+    torch.cuda.synchronize()
+    assert s.status() == 0
+    pts = [tuple(p) for p in s.points]
+    ref, tols = _ref_and_tol(wl, pts, transmission=True)
+    for p, r in enumerate(ref):
+        _check_point(out, p, r, int(counts[pts[p][0]]), T=True, tol=tols[p])
+    GLd = [np.diagonal(r["GL"], axis1=1, axis2=2) for r in ref]
+    rn, rJ, rjE = O.observables(wl, pts, GLd, [r["bond"] for r in ref])
+    tol = max(tols)
+    assert _rel(n.cpu().numpy(), rn) < tol
+    assert np.max(np.abs(J.cpu().numpy() - rJ)) < tol * 10 * max(np.max(np.abs(rJ)), 1e-6 * np.max(np.abs(rn)))
+    jg = jE.cpu().numpy()
+    assert np.max(np.abs(jg[:, :, :rjE.shape[2]] - rjE)) < tol * 10 * max(np.max(np.abs(rjE)), 1e-6)
+
+
+def test_rgf_block400_reduced_length():
+    _say("rgf block 400, 5 slabs, 2 k x 3 E")
+    wl = make_workload("C2", n_slab=5, n_e=3, n_k=2)
+    s = _solver(wl)
+    out = s.solve(want_T=True)
+    torch.cuda.synchronize()
+    assert s.status() == 0
+    pts = [tuple(p) for p in s.points]
+    ref, tols = _ref_and_tol(wl, pts, transmission=True)
+    for p, r in enumerate(ref):
+        _check_point(out, p, r, 5, T=True, tol=tols[p])
+
+
+def test_equilibrium_filled_eta_gives_kms_on_gpu():
+    """mu_L = mu_R and a filled eta contact: G^< = -f (G - G^dagger) diagonal."""
+    _say("rgf equilibrium")
+    wl = random_tiny(10, 4, n_e=4, seed=9, up_block=5, eta=1e-3)
+    wl.mu_L = wl.mu_R = 0.2
+    s = _solver(wl)
+    s.set_eta_fill(True)
+    out = s.solve()
+    GR = out["GR"].cpu().numpy()
+    GL = out["GL"].cpu().numpy()
+    for p, (_, _, ie) in enumerate(s.points):
+        f = O.fermi(wl.energy[ie], 0.2, wl.kT)
+        A = GR[p] - np.conj(GR[p])
+        assert np.max(np.abs(GL[p] + f * A)) < 1e-10 * np.max(np.abs(A))
+
+
+# ---------------------------------------------------------------------------
+# SCBA (Eqs. 4-6) with the iteration captured in a HIP graph
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_scba_matches_oracle(graph):
+    _say(f"scba graph={graph}")
+    wl = make_workload("C3", n_slab=4, n_e=40, n_k=2, n_z=2, n_y=1)
+    wl.D_ac, wl.M_op = 0.02, 0.03
+    wl.eta = 1e-3
+    n_iter = 3
+    s = _solver(wl, capacity=23)
+    out, hist = s.scba(n_iter=n_iter, graph=graph)
+    torch.cuda.synchronize()
+    assert s.status() == 0
+    ref = O.scba(wl, n_iter)
+    assert _rel(s.scat_R.cpu().numpy(), ref["sigR"]) < TOL
+    assert _rel(s.scat_L.cpu().numpy(), ref["sigL"]) < TOL
+    GR = out["GR"].cpu().numpy().reshape(wl.n_k, wl.n_e, -1, wl.nb)
+    GL = out["GL"].cpu().numpy().reshape(wl.n_k, wl.n_e, -1, wl.nb)
+    assert _rel(GR, ref["GRd"]) < TOL
+    assert _rel(GL, ref["GLd"]) < TOL
+    assert np.allclose(hist, ref["hist"], rtol=1e-8, atol=1e-14)

@@ -365,3 +365,15 @@ def test_memory_model_matches_paper():
     assert abs(gb - g["memory_per_ek_tuple_GB_6x10"]) / g["memory_per_ek_tuple_GB_6x10"] < 0.03
     wl_b = 12 * 10 * 10
     assert wl_b == g["block_rows_6x10"]
+
+
+@pytest.mark.parametrize("E", [-2.7, -0.2, 0.9, 2.6])
+def test_sancho_rubio_alternate_association_closed_form(E):
+    """The reproducibility variant is the same method: it meets the closed form too."""
+    t, eps, eta = -1.0, 0.1, 1e-6
+    z = E + 1j * eta
+    sig, it, conv = O.lead_selfenergy(np.array([[eps]], dtype=complex), np.array([[t]], dtype=complex),
+                                      np.array([[t]], dtype=complex), z, variant="alt")
+    assert conv
+    ref = _chain_sigma(z - eps, t)
+    assert abs(sig[0, 0] - ref) < 1e-10 * max(1, abs(ref))
