@@ -59,7 +59,7 @@ enum { NEGF_FP64 = 0, NEGF_MIXED = 1 };   /* negf_config.precision */
 enum { NEGF_WANT_TRANSMISSION = 1 };
 
 typedef struct {
-    int nb;           /* orbitals per slab (block size), >= 1 */
+    int nb;           /* orbitals per slab (block size), 1 <= nb <= 2048 */
     int n_slab_max;   /* largest slab count of any sample that will be bound */
     int capacity;     /* points per negf_rgf_forward/backward call and per lead batch */
     int precision;    /* NEGF_FP64, or NEGF_MIXED: FP32 MFMA block algebra with one

@@ -16,7 +16,7 @@ using namespace negf;
 namespace {
 
 constexpr int NTMP = 15;
-constexpr int NBMAX_INV = 16;
+constexpr int NBMAX_INV = 32;   // widest Gauss-Jordan panel
 constexpr int EV_POOL = 2048;
 
 struct TimedLaunch {
@@ -278,7 +278,7 @@ const char* negf_error_string(int st) {
 int negf_create(const negf_config* cfg, negf_ctx** out) {
     if (!cfg || !out) return NEGF_EINVAL;
     *out = nullptr;
-    if (cfg->nb < 1 || cfg->n_slab_max < 1 || cfg->capacity < 1) return NEGF_EINVAL;
+    if (cfg->nb < 1 || cfg->nb > INV_NMAX || cfg->n_slab_max < 1 || cfg->capacity < 1) return NEGF_EINVAL;
     if (cfg->precision != NEGF_FP64 && cfg->precision != NEGF_MIXED) return NEGF_EINVAL;
     negf_ctx* c = new (std::nothrow) negf_ctx();
     if (!c) return NEGF_ENOMEM;

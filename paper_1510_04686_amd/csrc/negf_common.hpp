@@ -36,6 +36,13 @@ template <typename C> __host__ __device__ inline void cfma(C& acc, C a, C b) {
 }
 template <typename C> __host__ __device__ inline C cscale(C a, double s) { a.x *= s; a.y *= s; return a; }
 
+// Component-wise select.  A ?: on the two-element struct itself is lowered to a
+// select between stack addresses (scratch memory); selecting each component
+// keeps both operands in registers.
+template <typename C> __host__ __device__ inline C csel(bool c, C a, C b) {
+    C r; r.x = c ? a.x : b.x; r.y = c ? a.y : b.y; return r;
+}
+
 template <typename Cto, typename Cfrom> __device__ inline Cto cconv(Cfrom a) {
     Cto c; c.x = a.x; c.y = a.y; return c;
 }

@@ -50,6 +50,7 @@ struct InvWork {
 };
 // dst = src^-1 for every active point (Gauss-Jordan, partial pivoting).  src
 // is destroyed.  dt = DT_C128 or DT_C64 (matrix and arithmetic type).
+constexpr int INV_NMAX = 2048;   // largest block the inverse handles
 hipError_t inverse_init();
 hipError_t inverse_launch(hipStream_t s, int dt, void* src, long long s_src, void* dst, long long s_dst,
                           int n, int np, const Active& act, const InvWork& w);

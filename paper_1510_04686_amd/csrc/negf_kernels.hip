@@ -53,7 +53,8 @@ __global__ __launch_bounds__(256) void sandwich_kernel(SandArgs a) {
                 int c = idx / ub, j = idx - c * ub;
                 int gc = c0 + c, l = (gc / ub) * ub + j;
                 // opR(U)[l][gc]
-                UR[c * ub + j] = (a.opR == 1) ? U[(long long)l * n + gc] : cconj(U[(long long)gc * n + l]);
+                if (a.opR == 1) UR[c * ub + j] = U[(long long)l * n + gc];
+                else UR[c * ub + j] = cconj(U[(long long)gc * n + l]);
             }
         }
         if (a.opL) {
@@ -61,7 +62,8 @@ __global__ __launch_bounds__(256) void sandwich_kernel(SandArgs a) {
                 int r = idx / ub, j = idx - r * ub;
                 int gr = r0 + r, l = (gr / ub) * ub + j;
                 // opL(U)[gr][l]
-                UL[r * ub + j] = (a.opL == 1) ? U[(long long)gr * n + l] : cconj(U[(long long)l * n + gr]);
+                if (a.opL == 1) UL[r * ub + j] = U[(long long)gr * n + l];
+                else UL[r * ub + j] = cconj(U[(long long)l * n + gr]);
             }
         }
         __syncthreads();
@@ -204,7 +206,8 @@ __global__ __launch_bounds__(256) void extract_kernel(ExtArgs a) {
     if (a.outR) a.outR[o] = g;
     if (a.outL) a.outL[o] = gl;
     if (a.outG) {
-        double2 gt = (r == c) ? g : cconv<double2>(G[(long long)c * n + r]);
+        double2 gt = g;
+        if (r != c) gt = cconv<double2>(G[(long long)c * n + r]);
         a.outG[o] = make_double2(gl.x + g.x - gt.x, gl.y + g.y + gt.y);
     }
 }
