@@ -531,6 +531,8 @@ int negf_rgf_forward(negf_ctx* c, void* stream, int p0, int np, const negf_c128*
         sa.X = (i > 0) ? slot(c, c->glst, i - 1) : nullptr;
         sa.sign = 1.0; sa.mode = 2; sa.O = c->tmp[1];
         sa.scat = reinterpret_cast<const double2*>(scat_L);
+        sa.lesser_ref = mixed ? 1 : 0;
+        sa.scat2 = reinterpret_cast<const double2*>(scat_R);
         NEGF_HIP_CHECK(sandwich_launch(s, sdt, sdt, sa));
         // g^<_i = g_i X g_i^dagger
         GemmArgs G = gargs(n, hi, act);
@@ -650,6 +652,8 @@ int negf_rgf_backward(negf_ctx* c, void* stream, int p0, int np, negf_c128* GR, 
             e.outG = reinterpret_cast<double2*>(GG);
             e.full = full_blocks ? 1 : 0; e.slab_stride = slab_stride; e.slab = st; e.n = n; e.np = hiF; e.p0 = p0;
             e.act = aF;
+            e.lesser_ref = (c->prec == NEGF_MIXED) ? 1 : 0;
+            e.energy = c->sys.energy; e.muR = c->sys.mu_R; e.kT = c->sys.kT;
             NEGF_HIP_CHECK(extract_launch(s, sdt, e));
         }
     }

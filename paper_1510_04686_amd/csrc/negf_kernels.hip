@@ -109,18 +109,24 @@ __global__ __launch_bounds__(256) void sandwich_kernel(SandArgs a) {
             if (a.slab == 0) { double2 s = a.sigL[lo + (long long)gr * n + gc]; z.x -= s.x; z.y -= s.y; }
             if (a.slab == ns - 1) { double2 s = a.sigR[lo + (long long)gr * n + gc]; z.x -= s.x; z.y -= s.y; }
         } else if (a.mode == 2) {
+            // lesser_ref: subtract the equilibrium source at the right-lead
+            // occupation, i f_R (Gamma_L + Gamma_R + Gamma_scat + 2 eta); the
+            // remaining source drives only the non-equilibrium part of G^<.
+            const double fR = a.lesser_ref ? fermi_d(E, a.muR, a.kT) : 0.0;
             if (gr == gc) {
                 if (a.scat) { double2 s = a.scat[((long long)ie * a.total + gslab) * n + gr]; z.x += s.x; z.y += s.y; }
+                if (a.lesser_ref && a.scat2) z.y += 2.0 * fR * a.scat2[((long long)ie * a.total + gslab) * n + gr].y;
                 if (a.eta_fill) z.y += 2.0 * a.eta * fermi_d(E, a.muL, a.kT);
+                z.y -= 2.0 * a.eta * fR;
             }
             const long long lo = ((long long)ik * a.n_e + ie) * n * n;
             if (a.slab == 0) {
-                double f = fermi_d(E, a.muL, a.kT);
+                double f = fermi_d(E, a.muL, a.kT) - fR;
                 double2 s1 = a.sigL[lo + (long long)gr * n + gc], s2 = a.sigL[lo + (long long)gc * n + gr];
                 z.x -= f * (s1.x - s2.x); z.y -= f * (s1.y + s2.y);
             }
             if (a.slab == ns - 1) {
-                double f = fermi_d(E, a.muR, a.kT);
+                double f = fermi_d(E, a.muR, a.kT) - fR;
                 double2 s1 = a.sigR[lo + (long long)gr * n + gc], s2 = a.sigR[lo + (long long)gc * n + gr];
                 z.x -= f * (s1.x - s2.x); z.y -= f * (s1.y + s2.y);
             }
@@ -202,14 +208,20 @@ __global__ __launch_bounds__(256) void extract_kernel(ExtArgs a) {
     if (a.full) { r = (int)(i / n); c = (int)(i - (long long)r * n); } else { r = c = (int)i; }
     double2 g = cconv<double2>(G[(long long)r * n + c]);
     double2 gl = cconv<double2>(GL[(long long)r * n + c]);
+    double2 gt = g;
+    if (r != c) gt = cconv<double2>(G[(long long)c * n + r]);
+    // spectral part (G - G^dagger)_rc = g - conj(gt)
+    const double2 sp = make_double2(g.x - gt.x, g.y + gt.y);
+    if (a.lesser_ref) {
+        // G^< = G^<_noneq - f_R (G - G^dagger)
+        const int ie = a.act.desc[p].z;
+        const double fR = 1.0 / (1.0 + exp((a.energy[ie] - a.muR) / a.kT));
+        gl.x -= fR * sp.x; gl.y -= fR * sp.y;
+    }
     const long long o = (p * a.slab_stride + a.slab) * nel + i;
     if (a.outR) a.outR[o] = g;
     if (a.outL) a.outL[o] = gl;
-    if (a.outG) {
-        double2 gt = g;
-        if (r != c) gt = cconv<double2>(G[(long long)c * n + r]);
-        a.outG[o] = make_double2(gl.x + g.x - gt.x, gl.y + g.y + gt.y);
-    }
+    if (a.outG) a.outG[o] = make_double2(gl.x + sp.x, gl.y + sp.y);
 }
 
 hipError_t extract_launch(hipStream_t s, int dt, const ExtArgs& a) {

@@ -20,6 +20,8 @@ struct SandArgs {
     long long total;
     const double2* sigL; const double2* sigR; int n_e;
     const double* energy; double eta, muL, muR, kT; int eta_fill;
+    int lesser_ref;                     // mode 2: drop the f_R-equilibrium source (mixed precision)
+    const double2* scat2;               // Sigma^R_scat (for lesser_ref), or NULL
     int n, np;
     Active act;
     PointSet ps;
@@ -30,6 +32,8 @@ struct ExtArgs {
     double2* outR; double2* outL; double2* outG;
     int full, slab_stride, slab, n, np, p0;
     Active act;
+    int lesser_ref;                     // GL holds the non-equilibrium part: add -f_R (G - G^dagger)
+    const double* energy; double muR, kT;
 };
 
 struct BondArgs {
