@@ -64,6 +64,8 @@ typedef struct {
     int capacity;     /* points per negf_rgf_forward/backward call and per lead batch */
     int precision;    /* NEGF_FP64, or NEGF_MIXED: FP32 MFMA block algebra with one
                          FP64-residual Newton-Schulz step per block inverse */
+    int adjoint_segment; /* 0: no adjoint workspace; > 0: slabs per checkpoint segment of
+                            negf_rgf_adjoint; -1: ceil(sqrt(n_slab_max)) */
 } negf_config;
 
 /* Create a context and allocate its device workspace (the only allocation of
@@ -198,6 +200,27 @@ int negf_scba_selfenergy(negf_ctx* ctx, void* stream,
 int negf_observables(negf_ctx* ctx, void* stream, const negf_c128* GL, const double* bond_j,
                      int slab_stride, const double* w_e, const double* w_k, double g_s,
                      int orbs_per_atom, double* n, double* J, double* j_E);
+
+/*
+ * Vector-Jacobian product of the density with respect to the onsite potential
+ * (the differentiation form; the consumer is the Newton step of the
+ * Poisson loop, Eq. 9).  For f = sum_o w_o n_o with n from Eq. (7):
+ *   df/dV_o = sum_points c_p 2 Im[(G^< W G^R)_oo],  W = diag(w),
+ * since dG^R = G^R dV G^R and dG^< = G^R dV G^< + G^< dV G^A.  (G^< W G^R) is
+ * the (1,3) level of the inverse of the level-upper-triangular system
+ * [[A, -Sigma^<, 0], [0, A^dagger, -W], [0, 0, A]]; its RGF reuses the g and
+ * g^< the preceding negf_rgf_forward stored (same p0, np), adds a forward
+ * recursion for y = g^dagger (W + H y H) g and x = g^< (W + H y H) g +
+ * g (H x H) g, checkpointed every `adjoint_segment` slabs and recomputed per
+ * segment, and a backward recursion for the (2,3) and (1,3) levels.
+ *   w_orb  [total_slabs][nb] cotangent weight per orbital (device double)
+ *   dX     out [p][slab_stride][nb]: 2 (G^< W G^R)_oo per point (complex); the
+ *          per-atom gradient is then negf_observables(GL = dX): same weights
+ *          g_s w_E w_k / 2pi and the same deterministic reduction.
+ * Requires a context created with adjoint_segment != 0.  FP64 only.
+ * Errors: NEGF_ESTATE (no matching forward sweep / no adjoint workspace), NEGF_EINVAL. */
+int negf_rgf_adjoint(negf_ctx* ctx, void* stream, int p0, int np, const double* w_orb,
+                     negf_c128* dX, int slab_stride);
 
 /*
  * The two dense block kernels of every slab step, exposed on their own (the

@@ -15,7 +15,7 @@ using namespace negf;
 
 namespace {
 
-constexpr int NTMP = 15;
+constexpr int NTMP = 24;
 constexpr int NBMAX_INV = 32;   // widest Gauss-Jordan panel
 constexpr int EV_POOL = 2048;
 
@@ -50,6 +50,11 @@ struct negf_ctx {
     int* ns_flag = nullptr;       // [cap] fallback flag per point
     int* ns_count = nullptr;      // device fallback counter
     double* ns_max = nullptr;     // device: per-point max residual history (max)
+    int adj_K = 0, adj_nseg = 0;  // adjoint checkpoint segment length and count
+    double2* adj_yseg = nullptr;  // [cap][K][nb][nb]  y of the segment being swept
+    double2* adj_xseg = nullptr;  // [cap][K][nb][nb]  x of the segment being swept
+    double2* adj_yck = nullptr;   // [cap][nseg][nb][nb] y at segment ends
+    double2* adj_xck = nullptr;   // [cap][nseg][nb][nb] x at segment ends
     int* h_pinned = nullptr;      // host pinned scratch
     long long ws_bytes = 0;
 
@@ -309,6 +314,17 @@ int negf_create(const negf_config* cfg, negf_ctx** out) {
          dev_alloc(c, &c->ns_flag, cap * sizeof(int), c->allocs) &&
          dev_alloc(c, &c->ns_count, 4 * sizeof(int), c->allocs) &&
          dev_alloc(c, &c->ns_max, cap * sizeof(double), c->allocs);
+    if (ok && cfg->adjoint_segment != 0) {
+        int K = cfg->adjoint_segment;
+        if (K < 0) { K = (int)std::ceil(std::sqrt((double)c->nsm)); }
+        if (K > c->nsm) K = c->nsm;
+        c->adj_K = K;
+        c->adj_nseg = (c->nsm + K - 1) / K;
+        ok = dev_alloc(c, &c->adj_yseg, cap * K * nn * sizeof(double2), c->allocs) &&
+             dev_alloc(c, &c->adj_xseg, cap * K * nn * sizeof(double2), c->allocs) &&
+             dev_alloc(c, &c->adj_yck, cap * c->adj_nseg * nn * sizeof(double2), c->allocs) &&
+             dev_alloc(c, &c->adj_xck, cap * c->adj_nseg * nn * sizeof(double2), c->allocs);
+    }
     if (ok && hipHostMalloc((void**)&c->h_pinned, 64) != hipSuccess) { c->h_pinned = nullptr; ok = false; }
     if (!ok) { delete c; return NEGF_ENOMEM; }
     if (inverse_init() != hipSuccess || sandwich_init() != hipSuccess) { delete c; return NEGF_EHIP; }
@@ -703,6 +719,167 @@ int negf_observables(negf_ctx* c, void* stream, const negf_c128* GL, const doubl
     a.csr_off = c->csr_off_d; a.csr_pts = c->csr_pts_d; a.orb_tmp = c->orb_tmp_d;
     a.n_out = n_out; a.J = J; a.jE = j_E;
     NEGF_HIP_CHECK(observables_launch((hipStream_t)stream, a));
+    return NEGF_OK;
+}
+
+
+int negf_rgf_adjoint(negf_ctx* c, void* stream, int p0, int np, const double* w_orb, negf_c128* dX,
+                     int slab_stride) {
+    if (!c) return NEGF_EINVAL;
+    if (!c->bound || !c->fwd_done || p0 != c->fwd_p0 || np != c->fwd_np) return NEGF_ESTATE;
+    if (c->adj_K <= 0 || c->prec != NEGF_FP64) return NEGF_ESTATE;
+    if (!w_orb || !dX) return NEGF_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const int n = c->nb;
+    const long long nn = (long long)n * n;
+    const long long sst = store_stride(c);
+    const GemmTypes T64{DT_C128, DT_C128, DT_C128, DT_C128};
+    int maxN = 0;
+    for (int q = 0; q < np; ++q) maxN = std::max(maxN, c->desc_h[p0 + q].w);
+    if (slab_stride < maxN) return NEGF_EINVAL;
+    const int K = c->adj_K;
+    const int nseg = (maxN + K - 1) / K;
+    const long long sseg = (long long)K * nn, sck = (long long)c->adj_nseg * nn;
+    double2** t = c->tmp;
+    double2 *tw = t[0], *tWG = t[1], *tc = t[2], *tcg = t[3];
+
+    // One slab of the forward recursion for y_i, x_i (g_i, g^<_i from the stores).
+    auto fwd_step = [&](int i, const double2* yp, const double2* xp, long long sp, double2* yo, double2* xo,
+                        long long so) -> int {
+        int hi;
+        long long cnt;
+        extent(c, p0, np, PRED_FWD, i, &hi, &cnt);
+        if (cnt == 0) return NEGF_OK;
+        Active act{c->desc_d, p0, i, PRED_FWD, nullptr};
+        SandArgs sa = sand_base(c, p0, act, hi);
+        sa.mode = 3; sa.wdiag = w_orb; sa.slab = i;
+        sa.X = (i > 0) ? yp : nullptr; sa.sX = sp; sa.uslab = i - 1; sa.opL = 2; sa.opR = 1;
+        sa.O = tw; sa.sO = nn;
+        NEGF_HIP_CHECK(sandwich_launch(s, DT_C128, DT_C128, sa));          // w_i = W_i + H y H
+        GemmArgs G = gargs(n, hi, act);
+        G.A = tw; G.sA = nn; G.B = slot(c, c->gst, i); G.sB = sst; G.C = tWG; G.sC = nn;
+        NEGF_HIP_CHECK(run_gemm(c, s, T64, OP_N, OP_N, EPI_STORE, G, cnt));   // w_i g_i
+        G.A = slot(c, c->gst, i); G.sA = sst; G.B = tWG; G.sB = nn; G.C = yo; G.sC = so;
+        NEGF_HIP_CHECK(run_gemm(c, s, T64, OP_C, OP_N, EPI_STORE, G, cnt));   // y_i = g^dag w g
+        G.A = slot(c, c->glst, i); G.C = xo;
+        NEGF_HIP_CHECK(run_gemm(c, s, T64, OP_N, OP_N, EPI_STORE, G, cnt));   // x_i = g^< w g
+        if (i > 0) {
+            SandArgs sc = sand_base(c, p0, act, hi);
+            sc.mode = 0; sc.X = xp; sc.sX = sp; sc.uslab = i - 1; sc.opL = 2; sc.opR = 1;
+            sc.O = tc; sc.sO = nn;
+            NEGF_HIP_CHECK(sandwich_launch(s, DT_C128, DT_C128, sc));      // c_i = H x H
+            GemmArgs H = gargs(n, hi, act);
+            H.A = tc; H.sA = nn; H.B = slot(c, c->gst, i); H.sB = sst; H.C = tcg; H.sC = nn;
+            NEGF_HIP_CHECK(run_gemm(c, s, T64, OP_N, OP_N, EPI_STORE, H, cnt));
+            H.A = slot(c, c->gst, i); H.sA = sst; H.B = tcg; H.sB = nn; H.C = xo; H.sC = so; H.D = xo; H.sD = so;
+            NEGF_HIP_CHECK(run_gemm(c, s, T64, OP_N, OP_N, EPI_ADD, H, cnt));  // x_i += g c g
+        }
+        return NEGF_OK;
+    };
+
+    // Pass 1: forward over all slabs, keeping (y, x) at the end of every segment.
+    double2* yp[2] = {t[4], t[5]};
+    double2* xp[2] = {t[6], t[7]};
+    for (int i = 0; i < maxN; ++i) {
+        int st = fwd_step(i, yp[(i + 1) & 1], xp[(i + 1) & 1], nn, yp[i & 1], xp[i & 1], nn);
+        if (st != NEGF_OK) return st;
+        if ((i + 1) % K == 0 && i + 1 < maxN) {
+            int hi;
+            long long cnt;
+            extent(c, p0, np, PRED_FWD, i, &hi, &cnt);
+            Active act{c->desc_d, p0, i, PRED_FWD, nullptr};
+            const int sg = (i + 1) / K - 1;
+            NEGF_HIP_CHECK(copy_launch(s, DT_C128, DT_C128, yp[i & 1], nn, c->adj_yck + sg * nn, sck, nn, hi, act));
+            NEGF_HIP_CHECK(copy_launch(s, DT_C128, DT_C128, xp[i & 1], nn, c->adj_xck + sg * nn, sck, nn, hi, act));
+        }
+    }
+
+    // Pass 2: per segment (last first), recompute (y, x) and sweep backward.
+    double2* Gb[2] = {t[8], t[9]};
+    double2* GLb[2] = {t[10], t[11]};
+    double2* Yb[2] = {t[12], t[13]};
+    double2* Xb[2] = {t[14], t[15]};
+    double2 *tL = t[16], *tR = t[17], *tQ = t[18], *tP = t[19], *tT = t[20], *tW = t[21], *tGR = t[22],
+            *tK1 = t[23], *tK2 = t[0], *tLg = t[1], *tRy = t[2], *tLy = t[3], *tRx = t[4], *tLx = t[5];
+    for (int sg = nseg - 1; sg >= 0; --sg) {
+        const int i0 = sg * K, i1 = std::min((sg + 1) * K, maxN);
+        for (int i = i0; i < i1; ++i) {
+            const double2 *ypv, *xpv;
+            long long spv;
+            if (i == i0) {
+                ypv = sg > 0 ? c->adj_yck + (sg - 1) * nn : nullptr;
+                xpv = sg > 0 ? c->adj_xck + (sg - 1) * nn : nullptr;
+                spv = sck;
+            } else {
+                ypv = c->adj_yseg + (i - 1 - i0) * nn;
+                xpv = c->adj_xseg + (i - 1 - i0) * nn;
+                spv = sseg;
+            }
+            int st = fwd_step(i, ypv, xpv, spv, c->adj_yseg + (i - i0) * nn, c->adj_xseg + (i - i0) * nn, sseg);
+            if (st != NEGF_OK) return st;
+        }
+        for (int st = i1 - 1; st >= i0; --st) {
+            const int cur = st & 1, nxt = cur ^ 1;
+            double2* ys = c->adj_yseg + (st - i0) * nn;
+            double2* xs = c->adj_xseg + (st - i0) * nn;
+            int hiF, hiB, hiI;
+            long long cF, cB, cI;
+            extent(c, p0, np, PRED_FWD, st, &hiF, &cF);
+            extent(c, p0, np, PRED_BWD, st, &hiB, &cB);
+            extent(c, p0, np, PRED_INIT, st, &hiI, &cI);
+            Active aI{c->desc_d, p0, st, PRED_INIT, nullptr};
+            Active aB{c->desc_d, p0, st, PRED_BWD, nullptr};
+            Active aF{c->desc_d, p0, st, PRED_FWD, nullptr};
+            if (cI > 0) {
+                NEGF_HIP_CHECK(copy_launch(s, DT_C128, DT_C128, slot(c, c->gst, st), sst, Gb[cur], nn, nn, hiI, aI));
+                NEGF_HIP_CHECK(copy_launch(s, DT_C128, DT_C128, slot(c, c->glst, st), sst, GLb[cur], nn, nn, hiI, aI));
+                NEGF_HIP_CHECK(copy_launch(s, DT_C128, DT_C128, ys, sseg, Yb[cur], nn, nn, hiI, aI));
+                NEGF_HIP_CHECK(copy_launch(s, DT_C128, DT_C128, xs, sseg, Xb[cur], nn, nn, hiI, aI));
+            }
+            if (cB > 0) {
+                SandArgs sa = sand_base(c, p0, aB, hiB);
+                sa.uslab = st; sa.mode = 0; sa.sO = nn;
+                struct { const void* X; long long sX; int opL, opR; double2* O; } sw[8] = {
+                    {slot(c, c->gst, st), sst, 0, 1, tL},  {slot(c, c->gst, st), sst, 2, 0, tR},
+                    {slot(c, c->glst, st), sst, 2, 0, tQ}, {slot(c, c->glst, st), sst, 0, 1, tLg},
+                    {ys, sseg, 2, 0, tRy},                  {ys, sseg, 0, 1, tLy},
+                    {xs, sseg, 2, 0, tRx},                  {xs, sseg, 0, 1, tLx}};
+                for (auto& w : sw) {
+                    sa.X = w.X; sa.sX = w.sX; sa.opL = w.opL; sa.opR = w.opR; sa.O = w.O;
+                    NEGF_HIP_CHECK(sandwich_launch(s, DT_C128, DT_C128, sa));
+                }
+                auto mm = [&](int opa, int opb, int epi, const void* A, long long sA, const void* B, long long sB,
+                              void* C, long long sC, const void* D = nullptr, long long sD = 0,
+                              const void* T = nullptr) -> hipError_t {
+                    GemmArgs G = gargs(n, hiB, aB);
+                    G.A = A; G.sA = sA; G.B = B; G.sB = sB; G.C = C; G.sC = sC; G.D = D; G.sD = sD;
+                    G.T = T; G.sT = nn;
+                    return run_gemm(c, s, T64, opa, opb, epi, G, cB);
+                };
+                // retarded and lesser levels (as in negf_rgf_backward)
+                NEGF_HIP_CHECK(mm(OP_N, OP_N, EPI_STORE, tL, nn, Gb[nxt], nn, tP, nn));
+                NEGF_HIP_CHECK(mm(OP_N, OP_N, EPI_ADD, tP, nn, tR, nn, Gb[cur], nn, slot(c, c->gst, st), sst));
+                NEGF_HIP_CHECK(mm(OP_N, OP_N, EPI_STORE, tP, nn, tQ, nn, tT, nn));
+                NEGF_HIP_CHECK(mm(OP_N, OP_N, EPI_STORE, tL, nn, GLb[nxt], nn, tW, nn));
+                NEGF_HIP_CHECK(mm(OP_N, OP_C, EPI_ADD_TTD, tW, nn, tL, nn, GLb[cur], nn, slot(c, c->glst, st), sst, tT));
+                // (2,3) level: Y_i = y + R^dag (G^dag R_y + Y R) + L_y G R
+                NEGF_HIP_CHECK(mm(OP_N, OP_N, EPI_STORE, Gb[nxt], nn, tR, nn, tGR, nn));
+                NEGF_HIP_CHECK(mm(OP_C, OP_N, EPI_STORE, Gb[nxt], nn, tRy, nn, tK1, nn));
+                NEGF_HIP_CHECK(mm(OP_N, OP_N, EPI_ADD, Yb[nxt], nn, tR, nn, tK1, nn, tK1, nn));
+                NEGF_HIP_CHECK(mm(OP_C, OP_N, EPI_ADD, tR, nn, tK1, nn, Yb[cur], nn, ys, sseg));
+                NEGF_HIP_CHECK(mm(OP_N, OP_N, EPI_ADD, tLy, nn, tGR, nn, Yb[cur], nn, Yb[cur], nn));
+                // (1,3) level: X_i = x + L (G R_x + G^< R_y + X R) + L_g K1 + L_x G R
+                NEGF_HIP_CHECK(mm(OP_N, OP_N, EPI_STORE, Gb[nxt], nn, tRx, nn, tK2, nn));
+                NEGF_HIP_CHECK(mm(OP_N, OP_N, EPI_ADD, GLb[nxt], nn, tRy, nn, tK2, nn, tK2, nn));
+                NEGF_HIP_CHECK(mm(OP_N, OP_N, EPI_ADD, Xb[nxt], nn, tR, nn, tK2, nn, tK2, nn));
+                NEGF_HIP_CHECK(mm(OP_N, OP_N, EPI_ADD, tL, nn, tK2, nn, Xb[cur], nn, xs, sseg));
+                NEGF_HIP_CHECK(mm(OP_N, OP_N, EPI_ADD, tLg, nn, tK1, nn, Xb[cur], nn, Xb[cur], nn));
+                NEGF_HIP_CHECK(mm(OP_N, OP_N, EPI_ADD, tLx, nn, tGR, nn, Xb[cur], nn, Xb[cur], nn));
+            }
+            NEGF_HIP_CHECK(diag_out_launch(s, Xb[cur], nn, n, hiF, aF, 2.0, reinterpret_cast<double2*>(dX),
+                                           slab_stride, st, p0));
+        }
+    }
     return NEGF_OK;
 }
 

@@ -108,6 +108,9 @@ __global__ __launch_bounds__(256) void sandwich_kernel(SandArgs a) {
             const long long lo = ((long long)ik * a.n_e + ie) * n * n;
             if (a.slab == 0) { double2 s = a.sigL[lo + (long long)gr * n + gc]; z.x -= s.x; z.y -= s.y; }
             if (a.slab == ns - 1) { double2 s = a.sigR[lo + (long long)gr * n + gc]; z.x -= s.x; z.y -= s.y; }
+        } else if (a.mode == 3) {
+            // adjoint source: the cotangent weights W_i on the diagonal
+            if (gr == gc) z.x += a.wdiag[gslab * n + gr];
         } else if (a.mode == 2) {
             // lesser_ref: subtract the equilibrium source at the right-lead
             // occupation, i f_R (Gamma_L + Gamma_R + Gamma_scat + 2 eta); the
@@ -222,6 +225,27 @@ __global__ __launch_bounds__(256) void extract_kernel(ExtArgs a) {
     if (a.outR) a.outR[o] = g;
     if (a.outL) a.outL[o] = gl;
     if (a.outG) a.outG[o] = make_double2(gl.x + sp.x, gl.y + sp.y);
+}
+
+// out[p][slab][o] = scale * X_q[o][o]  (FP64 blocks, active points only)
+__global__ __launch_bounds__(256) void diag_out_kernel(const double2* X, long long sX, int n, int np, Active act,
+                                                       double scale, double2* out, int slab_stride, int slab, int p0) {
+    const int per = (n + 255) / 256;
+    const int q = blockIdx.x / per;
+    if (q >= np || !act(q)) return;
+    const int o = (blockIdx.x - q * per) * 256 + threadIdx.x;
+    if (o >= n) return;
+    double2 v = X[q * sX + (long long)o * n + o];
+    out[((long long)(p0 + q) * slab_stride + slab) * n + o] = make_double2(scale * v.x, scale * v.y);
+}
+
+hipError_t diag_out_launch(hipStream_t s, const double2* X, long long sX, int n, int np, const Active& act,
+                           double scale, double2* out, int slab_stride, int slab, int p0) {
+    if (np <= 0) return hipSuccess;
+    const int per = (n + 255) / 256;
+    hipLaunchKernelGGL(diag_out_kernel, dim3(np * per), dim3(256), 0, s, X, sX, n, np, act, scale, out,
+                       slab_stride, slab, p0);
+    return hipGetLastError();
 }
 
 hipError_t extract_launch(hipStream_t s, int dt, const ExtArgs& a) {

@@ -21,6 +21,7 @@ struct SandArgs {
     const double2* sigL; const double2* sigR; int n_e;
     const double* energy; double eta, muL, muR, kT; int eta_fill;
     int lesser_ref;                     // mode 2: drop the f_R-equilibrium source (mixed precision)
+    const double* wdiag;                // mode 3: [total][n] diagonal weights
     const double2* scat2;               // Sigma^R_scat (for lesser_ref), or NULL
     int n, np;
     Active act;
@@ -83,6 +84,8 @@ hipError_t sandwich_launch(hipStream_t s, int xdt, int odt, const SandArgs& a);
 hipError_t copy_launch(hipStream_t s, int tdi, int tdo, const void* src, long long ss, void* dst, long long sd,
                        long long nel, int np, const Active& act);
 hipError_t extract_launch(hipStream_t s, int dt, const ExtArgs& a);
+hipError_t diag_out_launch(hipStream_t s, const double2* X, long long sX, int n, int np, const Active& act,
+                           double scale, double2* out, int slab_stride, int slab, int p0);
 hipError_t bond_launch(hipStream_t s, int dt, const BondArgs& a, double* out, int slab_stride);
 hipError_t gamma_launch(hipStream_t s, int dt, const double2* sig, int n_e, const PointSet& ps, void* out,
                         long long so, int n, int np);

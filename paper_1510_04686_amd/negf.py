@@ -33,7 +33,8 @@ class NegfError(RuntimeError):
 
 
 class negf_config(ctypes.Structure):
-    _fields_ = [("nb", c_int), ("n_slab_max", c_int), ("capacity", c_int), ("precision", c_int)]
+    _fields_ = [("nb", c_int), ("n_slab_max", c_int), ("capacity", c_int), ("precision", c_int),
+                ("adjoint_segment", c_int)]
 
 
 class negf_system(ctypes.Structure):
@@ -50,7 +51,7 @@ class negf_system(ctypes.Structure):
 EXPORTS = [
     "negf_create", "negf_destroy", "negf_workspace_bytes", "negf_sync_status", "negf_error_string",
     "negf_bind", "negf_lead_selfenergy", "negf_rgf_forward", "negf_rgf_backward",
-    "negf_scba_selfenergy", "negf_observables", "negf_zgemm_batched", "negf_zinv_batched", "negf_mixed_stats",
+    "negf_scba_selfenergy", "negf_observables", "negf_rgf_adjoint", "negf_zgemm_batched", "negf_zinv_batched", "negf_mixed_stats",
     "negf_gemm_timing_enable", "negf_gemm_timing",
 ]
 
@@ -76,6 +77,7 @@ def lib():
         "negf_rgf_backward": (i, [vp, vp, i, i, vp, vp, vp, i, i, vp, vp]),
         "negf_scba_selfenergy": (i, [vp, vp, vp, vp, i, vp, d, d, i, d, vp, vp, vp]),
         "negf_observables": (i, [vp, vp, vp, vp, i, vp, vp, d, i, vp, vp, vp]),
+        "negf_rgf_adjoint": (i, [vp, vp, i, i, vp, vp, i]),
         "negf_zgemm_batched": (i, [vp, vp, i, i, i, i, vp, vp, vp, i]),
         "negf_zinv_batched": (i, [vp, vp, i, i, vp, vp, i]),
         "negf_mixed_stats": (i, [vp, vp, POINTER(ll), POINTER(d)]),
@@ -133,8 +135,8 @@ class Context:
             self.handle = None
 
 
-def negf_create(nb, n_slab_max, capacity, precision=NEGF_FP64):
-    cfg = negf_config(nb, n_slab_max, capacity, precision)
+def negf_create(nb, n_slab_max, capacity, precision=NEGF_FP64, adjoint_segment=0):
+    cfg = negf_config(nb, n_slab_max, capacity, precision, adjoint_segment)
     h = c_void_p()
     _check("negf_create", lib().negf_create(ctypes.byref(cfg), ctypes.byref(h)))
     return Context(h, cfg)
@@ -210,6 +212,13 @@ def negf_observables(ctx, GL, bond_j, slab_stride, w_e, w_k, g_s, orbs_per_atom,
         int(orbs_per_atom), _ptr(n, torch.float64, "n"), _ptr(J, torch.float64, "J"),
         _ptr(j_E, torch.float64, "j_E"))
     _check("negf_observables", code)
+
+
+def negf_rgf_adjoint(ctx, p0, np_, w_orb, dX, slab_stride, stream=None):
+    """dX[p][i][o] = 2 (G^< W G^R)_oo for the points of the preceding forward sweep."""
+    code = lib().negf_rgf_adjoint(ctx.handle, _stream(stream), int(p0), int(np_), _ptr(w_orb, torch.float64, "w_orb"),
+                                  _ptr(dX, torch.complex128, "dX"), int(slab_stride))
+    _check("negf_rgf_adjoint", code)
 
 
 def _cdt(t):

@@ -26,7 +26,7 @@ def _dev(a, dtype, device):
 class RGFSolver:
     """Batched RGF over every (sample, k, E) point of a workload on one GPU."""
 
-    def __init__(self, wl, precision="fp64", capacity=None, device="cuda", mem_fraction=0.6):
+    def __init__(self, wl, precision="fp64", capacity=None, device="cuda", mem_fraction=0.6, adjoint_segment=0):
         self.wl = wl
         self.device = torch.device(device)
         self.prec = N.NEGF_MIXED if precision == "mixed" else N.NEGF_FP64
@@ -59,7 +59,8 @@ class RGFSolver:
             free, _ = torch.cuda.mem_get_info(self.device)
             capacity = int(max(1, min(self.n_points, 256, (free * mem_fraction) // per_point)))
         self.capacity = int(capacity)
-        self.ctx = N.negf_create(nb, self.n_slab_max, self.capacity, self.prec)
+        self.ctx = N.negf_create(nb, self.n_slab_max, self.capacity, self.prec, adjoint_segment)
+        self._last_fwd = None
         self.eta_fill = 0
         self._bind()
         self.sigma_L = self.sigma_R = None
@@ -111,6 +112,7 @@ class RGFSolver:
         for p0 in range(0, self.n_points, self.capacity):
             np_ = min(self.capacity, self.n_points - p0)
             N.negf_rgf_forward(self.ctx, p0, np_, self.sigma_L, self.sigma_R, scat_R, scat_L, flags, stream=stream)
+            self._last_fwd = (p0, np_)
             N.negf_rgf_backward(self.ctx, p0, np_, out.get("GR"), out.get("GL"), out.get("GG"),
                                 int(full_blocks), self.slab_stride, out.get("bond"), out.get("T"), stream=stream)
 
@@ -125,12 +127,41 @@ class RGFSolver:
         wl = self.wl
         g_s = wl.g_s if g_s is None else g_s
         n = torch.zeros((wl.total_slabs, wl.atoms_per_slab), dtype=torch.float64, device=self.device)
-        J = torch.zeros(wl.total_slabs, dtype=torch.float64, device=self.device)
+        J = None if bond is None else torch.zeros(wl.total_slabs, dtype=torch.float64, device=self.device)
         jE = (torch.zeros((wl.n_samples, wl.n_e, self.slab_stride), dtype=torch.float64, device=self.device)
-              if spectral else None)
+              if (spectral and bond is not None) else None)
         N.negf_observables(self.ctx, GL, bond, self.slab_stride, self.w_e, self.w_k, g_s, wl.orbs_per_atom,
                            n, J, jE)
         return n, J, jE
+
+    # ------------------------------------------------------------------ adjoint
+    def density(self):
+        """Electron density per atom (Eq. 7) for the current potential."""
+        if self.sigma_L is None:
+            self.lead_selfenergies()
+        out = self.alloc_outputs(want=("GL",))
+        self.run_batches(out)
+        n, _, _ = self.observables(out["GL"], None)
+        return n
+
+    def density_vjp(self, w_atom):
+        """grad_V (per atom) of sum_a w_a n_a through the adjoint RGF."""
+        wl = self.wl
+        w_orb = w_atom.to(device=self.device, dtype=torch.float64).reshape(wl.total_slabs, -1)
+        w_orb = w_orb.repeat_interleave(wl.orbs_per_atom, dim=1).contiguous()
+        dX = torch.zeros((self.n_points, self.slab_stride, wl.nb), dtype=torch.complex128, device=self.device)
+        batches = [(p0, min(self.capacity, self.n_points - p0)) for p0 in range(0, self.n_points, self.capacity)]
+        # the batch whose stores are still in the context goes first
+        if self._last_fwd in batches:
+            batches.remove(self._last_fwd)
+            batches.insert(0, self._last_fwd)
+        for p0, np_ in batches:
+            if self._last_fwd != (p0, np_):
+                N.negf_rgf_forward(self.ctx, p0, np_, self.sigma_L, self.sigma_R)
+                self._last_fwd = (p0, np_)
+            N.negf_rgf_adjoint(self.ctx, p0, np_, w_orb, dX, self.slab_stride)
+        g, _, _ = self.observables(dX, None)
+        return g
 
     def status(self):
         return N.negf_sync_status(self.ctx)
@@ -183,3 +214,23 @@ class RGFSolver:
         hist.append(float(rel.item()))
         self.scba_out = out
         return out, hist
+
+
+class RGFDensity(torch.autograd.Function):
+    """n = RGFDensity.apply(v_atom, solver): density per atom (Eq. 7) as a
+    differentiable function of the onsite potential per atom; backward runs the
+    adjoint RGF (one VJP per call)."""
+
+    @staticmethod
+    def forward(ctx, v_atom, solver):
+        wl = solver.wl
+        v = v_atom.detach().to(device=solver.device, dtype=torch.float64).reshape(wl.total_slabs, -1)
+        solver.set_potential(v.repeat_interleave(wl.orbs_per_atom, dim=1).contiguous())
+        n = solver.density()
+        ctx.solver = solver
+        return n
+
+    @staticmethod
+    def backward(ctx, grad_n):
+        g = ctx.solver.density_vjp(grad_n.contiguous())
+        return g, None

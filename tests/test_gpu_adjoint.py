@@ -1,0 +1,104 @@
+"""GPU: the adjoint RGF (dn/dV vector-Jacobian product) against the oracle's
+dense-inverse gradient and the oracle's central finite differences."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from synth import make_workload, random_tiny
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _solver(wl, **kw):
+    from paper_1510_04686_amd.runtime import RGFSolver
+    return RGFSolver(wl, **kw)
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _tiny(seed=3, nb=8, N=5, up=4, n_e=3):
+    wl = random_tiny(nb, N, n_e=n_e, seed=seed, up_block=up, eta=1e-3)
+    rng = np.random.default_rng(seed + 50)
+    wl.v_onsite = np.repeat(rng.uniform(0, 0.3, size=(N, nb // up)), up, axis=1)
+    return wl
+
+
+@pytest.mark.parametrize("segment", [1, 2, -1, 5])
+def test_adjoint_matches_dense_gradient(segment):
+    _say(f"adjoint tiny segment={segment}")
+    wl = _tiny()
+    rng = np.random.default_rng(7)
+    w = rng.normal(size=(wl.total_slabs, wl.atoms_per_slab))
+    s = _solver(wl, adjoint_segment=segment)
+    s.density()
+    g = s.density_vjp(torch.from_numpy(w)).cpu().numpy()
+    torch.cuda.synchronize()
+    assert s.status() == 0
+    pts = [tuple(p) for p in s.points]
+    ref = O.dense_grad(wl, w, wl.v_onsite, pts, O.lead_tables(wl))
+    assert _rel(g, ref) < 1e-10
+
+
+def test_adjoint_ragged_samples_multi_batch():
+    _say("adjoint ragged multi-sample, 3 batches")
+    wl = make_workload("C4", n_slab=5, n_e=2, n_z=1, n_y=2, n_samples=4)
+    wl.eta = 1e-3
+    wl.v_onsite = np.full((wl.total_slabs, wl.nb), 0.05)
+    assert len(set(np.diff(wl.slab_offset).tolist())) > 1
+    rng = np.random.default_rng(8)
+    w = rng.normal(size=(wl.total_slabs, wl.atoms_per_slab))
+    s = _solver(wl, capacity=3, adjoint_segment=2)
+    s.density()
+    g = s.density_vjp(torch.from_numpy(w)).cpu().numpy()
+    pts = [tuple(p) for p in s.points]
+    ref = O.dense_grad(wl, w, wl.v_onsite, pts, O.lead_tables(wl))
+    assert _rel(g, ref) < 1e-10
+
+
+def test_adjoint_matches_oracle_finite_differences():
+    """Paper-shaped potential profile (smooth, 0..0.3 eV), central differences
+    h = 1e-5 eV of the oracle's own density at a few atoms."""
+    _say("adjoint vs oracle FD")
+    wl = make_workload("C5", n_slab=6, n_e=2, n_z=1, n_y=2)
+    wl.eta = 1e-3
+    rng = np.random.default_rng(9)
+    w = rng.normal(size=(wl.total_slabs, wl.atoms_per_slab))
+    s = _solver(wl, adjoint_segment=-1)
+    s.density()
+    g = s.density_vjp(torch.from_numpy(w)).cpu().numpy()
+    pts = [tuple(p) for p in s.points]
+    leads = O.lead_tables(wl)
+    h = 1e-5
+    for sl, a in [(0, 0), (2, 1), (5, 0), (3, 1)]:
+        vp, vm = wl.v_onsite.copy(), wl.v_onsite.copy()
+        vp[sl, a * 10:(a + 1) * 10] += h
+        vm[sl, a * 10:(a + 1) * 10] -= h
+        fd = (O.density_objective(wl, w, vp, pts, leads) - O.density_objective(wl, w, vm, pts, leads)) / (2 * h)
+        assert abs(fd - g[sl, a]) < 1e-6 * np.max(np.abs(g)) + 1e-12, (sl, a, fd, g[sl, a])
+
+
+def test_autograd_function_backward():
+    from paper_1510_04686_amd.runtime import RGFDensity
+    _say("adjoint through torch.autograd")
+    wl = _tiny(seed=11)
+    s = _solver(wl, adjoint_segment=2)
+    v = torch.from_numpy(wl.v_onsite[:, ::wl.orbs_per_atom].copy()).cuda().requires_grad_(True)
+    n = RGFDensity.apply(v, s)
+    w = torch.randn_like(n)
+    (n * w).sum().backward()
+    ref = O.dense_grad(wl, w.cpu().numpy(), wl.v_onsite, [tuple(p) for p in s.points], O.lead_tables(wl))
+    assert _rel(v.grad.cpu().numpy(), ref) < 1e-10
+    # density itself against the oracle
+    res = O.solve_points(wl, [tuple(p) for p in s.points])
+    GLd = [np.diagonal(r["GL"], axis1=1, axis2=2) for r in res]
+    rn, _, _ = O.observables(wl, [tuple(p) for p in s.points], GLd, [r["bond"] for r in res])
+    assert _rel(n.detach().cpu().numpy(), rn) < 1e-10
