@@ -1,11 +1,17 @@
 """Benchmark of the batched RGF hot path on one MI355X.
 
-One step = the whole path over the workload: lead self-energies (Sancho-Rubio,
-FP64) for every (k, E), forward + backward RGF sweeps for every (sample, k, E)
-point in batches, and the density / current reductions.  Inputs are uploaded
-before the timed region.  Prints ONE JSON line.
+One step = the whole path over the workload with inputs resident in HBM:
+lead self-energies (Sancho-Rubio, FP64) for every (k, E), forward + backward
+RGF sweeps for every (sample, k, E) point in batches, and the density /
+current reductions.  Prints ONE JSON line.
 
     python bench.py [--steps K] [--warmup W] [--workload C2] [--precision fp64|mixed]
+
+Workloads (default C2, the block-400 headline):
+  C2/C1/C4  one step as above
+  C3        one step = leads + the SCBA loop (iteration replayed from a HIP graph)
+  C5        one step = leads + forward density; the adjoint dn/dV (VJP) is timed
+            after the steps and reported as a cost ratio
 """
 from __future__ import annotations
 
@@ -24,13 +30,13 @@ PEAK = {"f64": 78.6e12, "f32": 157.3e12}   # MI355X dense matrix-core peaks (FLO
 WORKLOAD_DESC = {
     "C1": "single-orbital strip: block 8, 20 slabs, 256 E, 1 k",
     "C2": "sp3d5s*-sized cross-section: block 400 (40 atoms x 10 orbitals), 70 slabs, 512 E x 8 k, 10% Ge",
-    "C3": "SCBA cross-section: block 240, 120 slabs, 1024 E x 4 k",
+    "C3": "SCBA cross-section: block 240, 120 slabs, 1024 E x 4 k, acoustic + optical phonons",
     "C4": "alloy ensemble: block 400, 128 samples x 256 E, 50-90 slabs",
-    "C5": "paper-shaped slice: block 1200, 200 slabs, 16 E x 1 k",
+    "C5": "paper-shaped slice: block 1200, 200 slabs, 16 E x 1 k, smooth 0-0.3 eV potential",
 }
 
 
-def model_flops(wl, iters_L, iters_R):
+def model_flops(wl, iters_L, iters_R, n_solves=1):
     """Algorithmic flops of one step.  U = 8 b^3 (one complex b x b x b product
     or one complex inverse).  RGF for G^R + G^<: 8 U per slab per point (forward:
     inverse + g X g^dagger; backward: P = L G, G = g + P R, T = P Q, L G^< L^dagger).
@@ -40,9 +46,31 @@ def model_flops(wl, iters_L, iters_R):
     b = wl.nb
     U = 8.0 * b ** 3
     counts = np.diff(wl.slab_offset)
-    rgf = 8.0 * U * float(np.sum(counts)) * wl.n_k * wl.n_e
+    rgf = 8.0 * U * float(np.sum(counts)) * wl.n_k * wl.n_e * n_solves
     lead = U * (7.0 * (float(np.sum(iters_L)) + float(np.sum(iters_R))) + 3.0 * 2 * wl.n_k * wl.n_e)
     return rgf, lead
+
+
+GEMM_SOURCES = ["negf_gemm.hip", "negf_mfma.hpp", "negf_common.hpp", "negf_internal.hpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_traffic_C2.json")
+
+
+def gemm_traffic_per_point_launch(precision):
+    """Calibrated HBM bytes per point per GEMM launch from the committed
+    rocprofv3 counter summary, or None when the GEMM sources changed since the
+    counters were taken (or for another precision)."""
+    import hashlib
+    if precision != "fp64" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    h = hashlib.sha1()
+    for f in GEMM_SOURCES:
+        with open(os.path.join(ROOT, "paper_1510_04686_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    with open(TRAFFIC_FILE) as fh:
+        t = json.load(fh)
+    if t.get("kernel_sources_sha1") != h.hexdigest():
+        return None
+    return float(t["hbm_bytes_per_point_launch"])
 
 
 def cpu_baseline(wl, n_points, seed=0):
@@ -74,8 +102,12 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--capacity", type=int, default=None)
     ap.add_argument("--n-e", type=int, default=None, help="shrink the energy grid (not for reported runs)")
+    ap.add_argument("--samples", type=int, default=None, help="C4: number of alloy samples (default 128)")
+    ap.add_argument("--scba-iters", type=int, default=None, help="C3: SCBA iterations (default 20)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-points", type=int, default=4)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the (E,k) points of a step "
@@ -89,20 +121,36 @@ def main():
     from synth import make_workload
 
     N.lib()   # fail loudly if the HIP library is missing
+    if args.copy_calibration > 0:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy: {nbytes} bytes read, {nbytes} bytes written", file=sys.stderr, flush=True)
+        del src, dst
     kw = {}
     if args.n_e:
         kw["n_e"] = args.n_e
+    if args.workload == "C4" and args.samples:
+        kw["n_samples"] = args.samples
     wl = make_workload(args.workload, **kw)
-    print(f"[bench] workload {args.workload}: nb={wl.nb} slabs={wl.total_slabs} n_k={wl.n_k} n_e={wl.n_e} "
-          f"precision={args.precision}", file=sys.stderr, flush=True)
-    solver = RGFSolver(wl, precision=args.precision, capacity=args.capacity)
+    print(f"[bench] workload {args.workload}: nb={wl.nb} samples={wl.n_samples} slabs={wl.total_slabs} "
+          f"n_k={wl.n_k} n_e={wl.n_e} precision={args.precision}", file=sys.stderr, flush=True)
+    adj_seg = -1 if args.workload == "C5" else 0
+    solver = RGFSolver(wl, precision=args.precision, capacity=args.capacity, adjoint_segment=adj_seg)
     print(f"[bench] capacity={solver.capacity} points/batch, workspace "
           f"{N.negf_workspace_bytes(solver.ctx) / 2**30:.1f} GiB", file=sys.stderr, flush=True)
+    n_iter = (args.scba_iters or wl.n_scba) if args.workload == "C3" else 1
     out = solver.alloc_outputs(want=("GR", "GL", "GG", "bond"))
-    stream = torch.cuda.current_stream()
 
     def step():
         solver.lead_selfenergies()
+        if args.workload == "C3":
+            o, hist = solver.scba(n_iter=n_iter, graph=True)
+            return solver.observables(o["GL"], o["bond"])
+        if args.workload == "C5":
+            return solver.density(), None, None
         solver.run_batches(out)
         return solver.observables(out["GL"], out["bond"])
 
@@ -111,7 +159,8 @@ def main():
         torch.cuda.synchronize()
         print(f"[bench] warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
 
-    N.negf_gemm_timing_enable(solver.ctx, True)
+    timed_gemm = args.workload != "C3"   # event records cannot sit inside the captured SCBA graph
+    N.negf_gemm_timing_enable(solver.ctx, timed_gemm)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -121,16 +170,21 @@ def main():
               flush=True)
     dt = time.perf_counter() - t0
     launches, gemm_ms, gemm_flops = N.negf_gemm_timing(solver.ctx)
+    N.negf_gemm_timing_enable(solver.ctx, False)
     st = solver.status()
     iters_L = solver.iters_L.cpu().numpy()
     iters_R = solver.iters_R.cpu().numpy()
-    rgf_f, lead_f = model_flops(wl, iters_L, iters_R)
-    points = solver.n_points * args.steps
+    rgf_f, lead_f = model_flops(wl, iters_L, iters_R, n_solves=n_iter)
+    points = solver.n_points * n_iter * args.steps
     dtype = "f64" if args.precision == "fp64" else "f32+f64"
     peak = PEAK["f64"] if args.precision == "fp64" else PEAK["f32"]
     achieved = gemm_flops / (gemm_ms * 1e-3) if gemm_ms > 0 else None
+    point_launches = gemm_flops / (8.0 * wl.nb ** 3)
+    tpp = gemm_traffic_per_point_launch(args.precision) if wl.nb == 400 else None
+    traffic = tpp * point_launches / launches if (tpp and launches) else None
+    metric ="RGF (E,k) points/s" if args.workload != "C3" else "RGF (E,k) points x SCBA iterations/s"
     res = {
-        "metric": "RGF (E,k) points/s",
+        "metric": metric,
         "value": points / dt,
         "unit": "(E,k) points/s",
         "n_gpus": 1,
@@ -144,6 +198,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOAD_DESC[args.workload]}",
                    "points_per_step": solver.n_points, "block": wl.nb, "slabs": int(wl.total_slabs),
+                   "samples": wl.n_samples, "n_e": wl.n_e, "n_k": wl.n_k,
                    "batch_capacity": solver.capacity, "precision": args.precision,
                    "parallelism": "single GPU, batched (sample,k,E) points"},
         "model_tflops": (rgf_f + lead_f) * args.steps / dt / 1e12,
@@ -152,10 +207,49 @@ def main():
         "roofline": {"bound": "mfma", "kernel": "batched complex GEMM (negf::gemm_kernel)",
                      "achieved": achieved / 1e12 if achieved else None, "peak": peak / 1e12,
                      "unit": "TFLOP/s", "frac": (achieved / peak) if achieved else None,
-                     "traffic": None, "launches": launches,
+                     "traffic": traffic, "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, "
+                                                         "copy-calibrated)",
+                     "algorithmic_bytes_per_launch": 3 * 16 * wl.nb ** 2 * point_launches / launches if launches else None,
+                     "launches": launches, "points_per_launch": point_launches / launches if launches else None,
                      "avg_launch_ms": gemm_ms / launches if launches else None},
         "status": N.STATUS.get(st, st),
     }
+    if args.workload == "C3":
+        res["config"]["scba_iterations"] = n_iter
+        res["roofline"]["note"] = "GEMM events are not recorded inside the captured SCBA graph"
+    if args.precision == "mixed":
+        nfb, maxres = N.negf_mixed_stats(solver.ctx)
+        res["mixed"] = {"fp64_fallback_inverses": nfb, "max_newton_schulz_residual": maxres}
+    if args.workload == "C5":
+        # adjoint dn/dV: one VJP with a seeded cotangent over all atoms
+        wv = torch.from_numpy(np.random.default_rng(1510046865).normal(
+            size=(wl.total_slabs, wl.atoms_per_slab))).cuda()
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        g = solver.density_vjp(wv)
+        torch.cuda.synchronize()
+        t_adj = time.perf_counter() - ta
+        t_fwd = dt / args.steps
+        res["adjoint"] = {"ms": t_adj * 1e3, "forward_ms": t_fwd * 1e3, "cost_ratio": t_adj / t_fwd,
+                          "checkpoint_segment": int(np.ceil(np.sqrt(wl.total_slabs))),
+                          "grad_norm": float(torch.linalg.norm(g))}
+    if args.workload == "C4" and args.precision == "mixed":
+        # per-sample density error of the mixed path against the FP64 GPU path
+        n_mix = n.cpu().numpy()
+        del solver
+        torch.cuda.empty_cache()
+        ref = RGFSolver(wl, precision="fp64", capacity=args.capacity)
+        o64 = ref.alloc_outputs(want=("GL", "bond"))
+        ref.lead_selfenergies()
+        ref.run_batches(o64)
+        n64, _, _ = ref.observables(o64["GL"], o64["bond"])
+        n64 = n64.cpu().numpy()
+        errs = []
+        for s_ in range(wl.n_samples):
+            a0, a1 = int(wl.slab_offset[s_]), int(wl.slab_offset[s_ + 1])
+            errs.append(float(np.max(np.abs(n_mix[a0:a1] - n64[a0:a1])) / np.max(np.abs(n64[a0:a1]))))
+        res["mixed"]["per_sample_density_rel_err"] = {"max": max(errs), "median": float(np.median(errs)),
+                                                     "reference": "FP64 GPU path (oracle-checked)"}
     if not args.no_cpu_baseline and args.cpu_points > 0:
         res["cpu_baseline"] = cpu_baseline(wl, args.cpu_points)
     print(json.dumps(res), flush=True)
