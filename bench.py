@@ -36,18 +36,21 @@ WORKLOAD_DESC = {
 }
 
 
-def model_flops(wl, iters_L, iters_R, n_solves=1):
+def model_flops(wl, iters_L, iters_R, n_solves=1, shared=False):
     """Algorithmic flops of one step.  U = 8 b^3 (one complex b x b x b product
     or one complex inverse).  RGF for G^R + G^<: 8 U per slab per point (forward:
     inverse + g X g^dagger; backward: P = L G, G = g + P R, T = P Q, L G^< L^dagger).
     Sancho-Rubio: 7 U per decimation step per lead (1 inverse + 6 products)
-    plus 3 U for the final surface inverse and tau g tau^dagger."""
+    plus 3 U per lead for the final surface inverse and tau g tau^dagger; with
+    the shared decimation (h01_L = h01_R^dagger) one run of max(iters) steps
+    serves both leads."""
     import numpy as np
     b = wl.nb
     U = 8.0 * b ** 3
     counts = np.diff(wl.slab_offset)
     rgf = 8.0 * U * float(np.sum(counts)) * wl.n_k * wl.n_e * n_solves
-    lead = U * (7.0 * (float(np.sum(iters_L)) + float(np.sum(iters_R))) + 3.0 * 2 * wl.n_k * wl.n_e)
+    steps = float(np.sum(np.maximum(iters_L, iters_R))) if shared else float(np.sum(iters_L)) + float(np.sum(iters_R))
+    lead = U * (7.0 * steps + 3.0 * 2 * wl.n_k * wl.n_e)
     return rgf, lead
 
 
@@ -174,7 +177,7 @@ def main():
     st = solver.status()
     iters_L = solver.iters_L.cpu().numpy()
     iters_R = solver.iters_R.cpu().numpy()
-    rgf_f, lead_f = model_flops(wl, iters_L, iters_R, n_solves=n_iter)
+    rgf_f, lead_f = model_flops(wl, iters_L, iters_R, n_solves=n_iter, shared=bool(solver.lead_dual))
     points = solver.n_points * n_iter * args.steps
     dtype = "f64" if args.precision == "fp64" else "f32+f64"
     peak = PEAK["f64"] if args.precision == "fp64" else PEAK["f32"]
@@ -204,6 +207,7 @@ def main():
         "model_tflops": (rgf_f + lead_f) * args.steps / dt / 1e12,
         "model_flops_per_step": {"rgf": rgf_f, "leads": lead_f},
         "lead_iterations_mean": float((iters_L.mean() + iters_R.mean()) / 2),
+        "lead_shared_decimation": bool(solver.lead_dual),
         "roofline": {"bound": "mfma", "kernel": "batched complex GEMM (negf::gemm_kernel)",
                      "achieved": achieved / 1e12 if achieved else None, "peak": peak / 1e12,
                      "unit": "TFLOP/s", "frac": (achieved / peak) if achieved else None,

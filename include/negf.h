@@ -135,6 +135,31 @@ int negf_lead_selfenergy(negf_ctx* ctx, void* stream, int n_k,
                          negf_c128* sigma, int* iters);
 
 /*
+ * Both lead self-energies at once, exploiting a dependency between them (the
+ * section "Quantitative discussion of current state of the art" credits
+ * NEMO5's savings to analytical dependencies among the Green's functions and
+ * self-energies).  When the left lead's coupling into the lead is the adjoint
+ * of the right lead's (h01_L = h01_R^dagger at every k) and both share h00,
+ * the left lead is the right lead's bulk seen from the other end: one
+ * Sancho-Rubio decimation of (h00, h01_R) yields both surface functions (the
+ * dual surface accumulates beta g alpha instead of alpha g beta), at one extra
+ * surface inverse and two extra GEMMs per point instead of a second
+ * decimation.  The condition is checked on the device (max deviation
+ * <= 1e-15 max|h01_R|); if it fails, two independent decimations run.
+ *   h00 [n_k][nb][nb]; h01_L, tau_L, h01_R, tau_R [n_k][nb][nb] as in
+ *   negf_lead_selfenergy.  Outputs as there, for each lead; iters_L/R may be NULL.
+ *   dual_used (host int*, may be NULL): 1 when the shared decimation ran.
+ * Each lead stops counting at its own criterion (its own ||h01||_1); the
+ * shared decimation runs until both have converged.  Synchronises `stream`.
+ * Returns NEGF_WNOCONV if any point hit max_iter.  Errors: NEGF_EINVAL. */
+int negf_lead_selfenergy_pair(negf_ctx* ctx, void* stream, int n_k, const negf_c128* h00,
+                              const negf_c128* h01_L, const negf_c128* tau_L,
+                              const negf_c128* h01_R, const negf_c128* tau_R,
+                              int n_e, const double* energy, double eta, double tol, int max_iter,
+                              negf_c128* sigma_L, negf_c128* sigma_R, int* iters_L, int* iters_R,
+                              int* dual_used);
+
+/*
  * Forward (left-connected) RGF sweep over bound points [p0, p0+np), np <= capacity:
  *   g_i   = (A_ii - H_{i,i-1} g_{i-1} H_{i-1,i})^-1                         (Eq. 1)
  *   g^<_i = g_i (Sigma^<_i + H_{i,i-1} g^<_{i-1} H_{i-1,i}) g_i^dagger     (Eq. 2)

@@ -16,6 +16,7 @@ using namespace negf;
 namespace {
 
 constexpr int NTMP = 24;
+constexpr int DUAL_NBLK = 64;   // blocks of the h01_L = h01_R^dagger check
 constexpr int NBMAX_INV = 32;   // widest Gauss-Jordan panel
 constexpr int EV_POOL = 2048;
 
@@ -44,6 +45,9 @@ struct negf_ctx {
     int* sr_flags = nullptr;
     int* sr_iters = nullptr;
     double* sr_ref = nullptr;
+    int* sr_iters2 = nullptr;     // dual surface (other lead) iteration counts
+    double* sr_ref2 = nullptr;    // dual surface reference norms
+    double* dual_partial = nullptr;
     int* d_count = nullptr;
     int* status = nullptr;
     double* ns_res = nullptr;     // [cap] mixed-precision residual per point
@@ -308,6 +312,9 @@ int negf_create(const negf_config* cfg, negf_ctx** out) {
          dev_alloc(c, &c->sr_flags, cap * sizeof(int), c->allocs) &&
          dev_alloc(c, &c->sr_iters, cap * sizeof(int), c->allocs) &&
          dev_alloc(c, &c->sr_ref, cap * sizeof(double), c->allocs) &&
+         dev_alloc(c, &c->sr_iters2, cap * sizeof(int), c->allocs) &&
+         dev_alloc(c, &c->sr_ref2, cap * sizeof(double), c->allocs) &&
+         dev_alloc(c, &c->dual_partial, 2 * DUAL_NBLK * sizeof(double), c->allocs) &&
          dev_alloc(c, &c->d_count, 4 * sizeof(int), c->allocs) &&
          dev_alloc(c, &c->status, 4 * sizeof(int), c->allocs) &&
          dev_alloc(c, &c->ns_res, cap * sizeof(double), c->allocs) &&
@@ -422,16 +429,22 @@ int negf_bind(negf_ctx* c, const negf_system* S, int n_points, const int* points
     return NEGF_OK;
 }
 
-int negf_lead_selfenergy(negf_ctx* c, void* stream, int n_k, const negf_c128* h00, const negf_c128* h01,
-                         const negf_c128* tau, int n_e, const double* energy, double eta, double tol,
-                         int max_iter, negf_c128* sigma, int* iters) {
-    if (!c || !h00 || !h01 || !tau || !energy || !sigma) return NEGF_EINVAL;
-    if (n_k < 1 || n_e < 1 || max_iter < 1 || !(tol > 0) || !(eta >= 0)) return NEGF_EINVAL;
-    hipStream_t s = (hipStream_t)stream;
+}  // extern "C"
+
+// Sancho-Rubio over the (k, E) grid in batches of `capacity` points; writes
+// Sigma = tau g_s tau^dagger to `sigma`.  With `sigma2` set, the same
+// decimation also carries the dual surface: the lead on the other side of the
+// device, whose coupling into the lead is h01^dagger (alpha and beta swap
+// roles, so only the surface accumulator is extra); its self-energy
+// tau2 g_s' tau2^dagger goes to `sigma2`.
+static int lead_sr(negf_ctx* c, hipStream_t s, int n_k, const negf_c128* h00, const negf_c128* h01,
+                   const negf_c128* tau, int n_e, const double* energy, double eta, double tol, int max_iter,
+                   negf_c128* sigma, int* iters, const negf_c128* tau2, negf_c128* sigma2, int* iters2) {
     const int n = c->nb;
     const long long nn = (long long)n * n;
     const long long total = (long long)n_k * n_e;
     const GemmTypes T64{DT_C128, DT_C128, DT_C128, DT_C128};
+    const bool dual = sigma2 != nullptr;
     bool noconv = false;
     for (long long f0 = 0; f0 < total; f0 += c->cap) {
         const int cnt = (int)std::min<long long>(c->cap, total - f0);
@@ -441,6 +454,10 @@ int negf_lead_selfenergy(negf_ctx* c, void* stream, int n_k, const negf_c128* h0
         a.tauin = reinterpret_cast<const double2*>(tau);
         a.eps_s = c->tmp[0]; a.eps = c->tmp[1]; a.alpha = c->tmp[2]; a.beta = c->tmp[3]; a.tau = c->tmp[13];
         a.flags = c->sr_flags; a.iters = c->sr_iters; a.ref = c->sr_ref; a.count = c->d_count;
+        if (dual) {
+            a.eps_d = c->tmp[4]; a.tau2 = c->tmp[5]; a.tauin2 = reinterpret_cast<const double2*>(tau2);
+            a.iters2 = c->sr_iters2; a.ref2 = c->sr_ref2;
+        }
         a.energy = energy; a.eta = eta; a.tol = tol; a.f0 = f0; a.n = n; a.n_e = n_e; a.np = cnt;
         NEGF_HIP_CHECK(sr_launch_init(s, a));
         double2 *al = c->tmp[2], *be = c->tmp[3], *al2 = c->tmp[6], *be2 = c->tmp[7];
@@ -458,11 +475,18 @@ int negf_lead_selfenergy(negf_ctx* c, void* stream, int n_k, const negf_c128* h0
             // eps_s += X1 beta ; eps += X1 beta
             G.A = X1; G.B = be; G.C = a.eps_s; G.C2 = a.eps; G.sC2 = nn;
             NEGF_HIP_CHECK(run_gemm(c, s, T64, OP_N, OP_N, EPI_DUAL, G, active));
-            // eps += X2 alpha
-            G.A = X2; G.B = al; G.C = a.eps; G.D = a.eps; G.sD = nn;
-            NEGF_HIP_CHECK(run_gemm(c, s, T64, OP_N, OP_N, EPI_ADD, G, active));
+            // eps += X2 alpha  (and eps_dual += X2 alpha)
+            G.A = X2; G.B = al;
+            if (dual) {
+                G.C = a.eps_d; G.C2 = a.eps; G.sC2 = nn;
+                NEGF_HIP_CHECK(run_gemm(c, s, T64, OP_N, OP_N, EPI_DUAL, G, active));
+            } else {
+                G.C = a.eps; G.D = a.eps; G.sD = nn;
+                NEGF_HIP_CHECK(run_gemm(c, s, T64, OP_N, OP_N, EPI_ADD, G, active));
+            }
             // alpha' = X1 alpha ; beta' = X2 beta
-            G.A = X1; G.B = al; G.C = al2;
+            G = gargs(n, cnt, act);
+            G.A = X1; G.sA = nn; G.B = al; G.sB = nn; G.C = al2; G.sC = nn;
             NEGF_HIP_CHECK(run_gemm(c, s, T64, OP_N, OP_N, EPI_STORE, G, active));
             G.A = X2; G.B = be; G.C = be2;
             NEGF_HIP_CHECK(run_gemm(c, s, T64, OP_N, OP_N, EPI_STORE, G, active));
@@ -475,18 +499,64 @@ int negf_lead_selfenergy(negf_ctx* c, void* stream, int n_k, const negf_c128* h0
             active = c->h_pinned[0];
         }
         if (active > 0) noconv = true;
-        // g_s = (z - eps_s)^-1 ; Sigma = tau g_s tau^dagger
+        // g_s = (z - eps_s)^-1 ; Sigma = tau g_s tau^dagger  (then the same for the dual surface)
         Active all{c->desc_d, 0, 0, PRED_ALL, nullptr};
-        NEGF_HIP_CHECK(sr_launch_zminus(s, a, a.eps_s, M, all));
-        NEGF_HIP_CHECK(inverse_launch(s, DT_C128, M, nn, g, nn, n, cnt, all, invwork(c, c->tmp[12])));
-        GemmArgs G = gargs(n, cnt, all);
-        G.A = a.tau; G.sA = nn; G.B = g; G.sB = nn; G.C = X1; G.sC = nn;
-        NEGF_HIP_CHECK(run_gemm(c, s, T64, OP_N, OP_N, EPI_STORE, G, cnt));
-        G.A = X1; G.B = a.tau; G.C = reinterpret_cast<double2*>(sigma) + f0 * nn;
-        NEGF_HIP_CHECK(run_gemm(c, s, T64, OP_N, OP_C, EPI_STORE, G, cnt));
-        if (iters) NEGF_HIP_CHECK(sr_launch_iters(s, a, iters));
+        for (int side = 0; side < (dual ? 2 : 1); ++side) {
+            const double2* es = side ? a.eps_d : a.eps_s;
+            const double2* tq = side ? a.tau2 : a.tau;
+            negf_c128* out = side ? sigma2 : sigma;
+            NEGF_HIP_CHECK(sr_launch_zminus(s, a, es, M, all));
+            NEGF_HIP_CHECK(inverse_launch(s, DT_C128, M, nn, g, nn, n, cnt, all, invwork(c, c->tmp[12])));
+            GemmArgs G = gargs(n, cnt, all);
+            G.A = tq; G.sA = nn; G.B = g; G.sB = nn; G.C = X1; G.sC = nn;
+            NEGF_HIP_CHECK(run_gemm(c, s, T64, OP_N, OP_N, EPI_STORE, G, cnt));
+            G.A = X1; G.B = tq; G.C = reinterpret_cast<double2*>(out) + f0 * nn;
+            NEGF_HIP_CHECK(run_gemm(c, s, T64, OP_N, OP_C, EPI_STORE, G, cnt));
+        }
+        if (iters) NEGF_HIP_CHECK(sr_launch_iters(s, a, c->sr_iters, iters));
+        if (dual && iters2) NEGF_HIP_CHECK(sr_launch_iters(s, a, c->sr_iters2, iters2));
     }
     return noconv ? NEGF_WNOCONV : NEGF_OK;
+}
+
+extern "C" {
+
+int negf_lead_selfenergy(negf_ctx* c, void* stream, int n_k, const negf_c128* h00, const negf_c128* h01,
+                         const negf_c128* tau, int n_e, const double* energy, double eta, double tol,
+                         int max_iter, negf_c128* sigma, int* iters) {
+    if (!c || !h00 || !h01 || !tau || !energy || !sigma) return NEGF_EINVAL;
+    if (n_k < 1 || n_e < 1 || max_iter < 1 || !(tol > 0) || !(eta >= 0)) return NEGF_EINVAL;
+    return lead_sr(c, (hipStream_t)stream, n_k, h00, h01, tau, n_e, energy, eta, tol, max_iter, sigma, iters,
+                   nullptr, nullptr, nullptr);
+}
+
+int negf_lead_selfenergy_pair(negf_ctx* c, void* stream, int n_k, const negf_c128* h00, const negf_c128* h01_L,
+                              const negf_c128* tau_L, const negf_c128* h01_R, const negf_c128* tau_R, int n_e,
+                              const double* energy, double eta, double tol, int max_iter, negf_c128* sigma_L,
+                              negf_c128* sigma_R, int* iters_L, int* iters_R, int* dual_used) {
+    if (!c || !h00 || !h01_L || !tau_L || !h01_R || !tau_R || !energy || !sigma_L || !sigma_R) return NEGF_EINVAL;
+    if (n_k < 1 || n_e < 1 || max_iter < 1 || !(tol > 0) || !(eta >= 0)) return NEGF_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    NEGF_HIP_CHECK(lead_dual_check_launch(s, reinterpret_cast<const double2*>(h01_L),
+                                          reinterpret_cast<const double2*>(h01_R), n_k, c->nb, c->dual_partial,
+                                          DUAL_NBLK));
+    double part[2 * DUAL_NBLK];
+    NEGF_HIP_CHECK(hipMemcpyAsync(part, c->dual_partial, sizeof(part), hipMemcpyDeviceToHost, s));
+    NEGF_HIP_CHECK(hipStreamSynchronize(s));
+    double dev = 0.0, scale = 0.0;
+    for (int b = 0; b < DUAL_NBLK; ++b) { dev = std::max(dev, part[2 * b]); scale = std::max(scale, part[2 * b + 1]); }
+    const bool dual = dev <= 1e-15 * scale;
+    if (dual_used) *dual_used = dual ? 1 : 0;
+    if (dual)
+        return lead_sr(c, s, n_k, h00, h01_R, tau_R, n_e, energy, eta, tol, max_iter, sigma_R, iters_R, tau_L,
+                       sigma_L, iters_L);
+    int a = lead_sr(c, s, n_k, h00, h01_L, tau_L, n_e, energy, eta, tol, max_iter, sigma_L, iters_L, nullptr,
+                    nullptr, nullptr);
+    if (a < 0) return a;
+    int b = lead_sr(c, s, n_k, h00, h01_R, tau_R, n_e, energy, eta, tol, max_iter, sigma_R, iters_R, nullptr,
+                    nullptr, nullptr);
+    if (b < 0) return b;
+    return std::max(a, b);
 }
 
 int negf_rgf_forward(negf_ctx* c, void* stream, int p0, int np, const negf_c128* sigma_L,

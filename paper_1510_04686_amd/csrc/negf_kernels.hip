@@ -408,8 +408,16 @@ __global__ __launch_bounds__(256) void sr_init_kernel(SrArgs a) {
         a.alpha[q * nel + i] = a.h01[kb + i];
         a.beta[q * nel + i] = cconj(a.h01[kb + (long long)c * n + r]);
         a.tau[q * nel + i] = a.tauin[kb + i];
+        if (a.eps_d) {
+            a.eps_d[q * nel + i] = h;
+            a.tau2[q * nel + i] = a.tauin2[kb + i];
+        }
     }
-    if (i == 0) { a.flags[q] = 0; a.iters[q] = 0; }
+    if (i == 0) {
+        a.flags[q] = 0;
+        a.iters[q] = 0;
+        if (a.eps_d) a.iters2[q] = 0;
+    }
 }
 
 // M = z I - X  (X = eps or eps_s), z = E + i eta
@@ -447,18 +455,38 @@ __device__ double norm1_block(const double2* X, int n, double* red) {
     return v;
 }
 
-// Reference norm ||h01||_1 per chunk point.
+// Reference norms per chunk point: ||h01||_1, and for the dual surface
+// ||h01^dagger||_1 (the largest row sum of |h01|).
 __global__ __launch_bounds__(256) void sr_refnorm_kernel(SrArgs a) {
     const int q = blockIdx.x;
     if (q >= a.np) return;
     __shared__ double red[256];
     const long long f = a.f0 + q;
     const int ik = (int)(f / a.n_e);
-    double v = norm1_block(a.h01 + (long long)ik * a.n * a.n, a.n, red);
+    const double2* h = a.h01 + (long long)ik * a.n * a.n;
+    double v = norm1_block(h, a.n, red);
     if (threadIdx.x == 0) a.ref[q] = v;
+    if (!a.eps_d) return;
+    double best = 0.0;
+    for (int r = threadIdx.x; r < a.n; r += 256) {
+        double t = 0.0;
+        for (int c = 0; c < a.n; ++c) { double2 x = h[(long long)r * a.n + c]; t += hypot(x.x, x.y); }
+        best = fmax(best, t);
+    }
+    red[threadIdx.x] = best;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) a.ref2[q] = red[0];
 }
 
 // Convergence test after a decimation step: ||alpha||_1 + ||beta||_1 < tol ||h01||_1.
+// The dual surface shares alpha and beta (with their roles swapped), so it
+// differs only in its reference norm.  An iteration count is stored negated
+// once its surface has converged; a point is done when every surface it
+// carries has.
 __global__ __launch_bounds__(256) void sr_check_kernel(SrArgs a, const double2* alpha, const double2* beta, int it) {
     const int q = blockIdx.x;
     if (q >= a.np || a.flags[q] != 0) return;
@@ -467,16 +495,22 @@ __global__ __launch_bounds__(256) void sr_check_kernel(SrArgs a, const double2* 
     double na = norm1_block(alpha + q * nel, a.n, red);
     double nb = norm1_block(beta + q * nel, a.n, red);
     if (threadIdx.x == 0) {
-        a.iters[q] = it;
-        if (na + nb < a.tol * a.ref[q]) a.flags[q] = 1;
+        const double sum = na + nb;
+        if (a.iters[q] >= 0) a.iters[q] = sum < a.tol * a.ref[q] ? -it : it;
+        bool done = a.iters[q] < 0;
+        if (a.eps_d) {
+            if (a.iters2[q] >= 0) a.iters2[q] = sum < a.tol * a.ref2[q] ? -it : it;
+            done = done && a.iters2[q] < 0;
+        }
+        if (done) a.flags[q] = 1;
         else atomicAdd(a.count, 1);
     }
 }
 
-__global__ void sr_iters_out_kernel(SrArgs a, int* out) {
+__global__ void sr_iters_out_kernel(const int* it, long long f0, int np, int* out) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= a.np) return;
-    out[a.f0 + q] = a.iters[q];
+    if (q >= np) return;
+    out[f0 + q] = abs(it[q]);
 }
 
 // ---------------------------------------------------------------------------
@@ -664,8 +698,46 @@ hipError_t sr_launch_check(hipStream_t s, const SrArgs& a, const double2* alpha,
     hipLaunchKernelGGL(sr_check_kernel, dim3(a.np), dim3(256), 0, s, a, alpha, beta, it);
     return hipGetLastError();
 }
-hipError_t sr_launch_iters(hipStream_t s, const SrArgs& a, int* out) {
-    hipLaunchKernelGGL(sr_iters_out_kernel, dim3((a.np + 255) / 256), dim3(256), 0, s, a, out);
+hipError_t sr_launch_iters(hipStream_t s, const SrArgs& a, const int* it, int* out) {
+    hipLaunchKernelGGL(sr_iters_out_kernel, dim3((a.np + 255) / 256), dim3(256), 0, s, it, a.f0, a.np, out);
+    return hipGetLastError();
+}
+
+}  // namespace negf
+
+namespace negf {
+
+// Checks h01_L = h01_R^dagger over all k, which lets one decimation serve both
+// leads (the dual surface).  Per-block maxima of the deviation and of |h01_R|.
+__global__ __launch_bounds__(256) void lead_dual_check_kernel(const double2* h01L, const double2* h01R, int n,
+                                                              long long tot, double* partial) {
+    const long long nn = (long long)n * n;
+    double d = 0.0, m = 0.0;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < tot; i += (long long)gridDim.x * 256) {
+        const long long k = i / nn, e = i - k * nn;
+        const int r = (int)(e / n), c = (int)(e - (long long)r * n);
+        const double2 x = h01L[i], y = h01R[k * nn + (long long)c * n + r];
+        d = fmax(d, fmax(fabs(x.x - y.x), fabs(x.y + y.y)));
+        m = fmax(m, fmax(fabs(y.x), fabs(y.y)));
+    }
+    __shared__ double rd[256], rm[256];
+    rd[threadIdx.x] = d;
+    rm[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            rd[threadIdx.x] = fmax(rd[threadIdx.x], rd[threadIdx.x + o]);
+            rm[threadIdx.x] = fmax(rm[threadIdx.x], rm[threadIdx.x + o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { partial[2 * blockIdx.x] = rd[0]; partial[2 * blockIdx.x + 1] = rm[0]; }
+}
+
+hipError_t lead_dual_check_launch(hipStream_t s, const double2* h01L, const double2* h01R, int n_k, int n,
+                                  double* partial, int nblk) {
+    hipLaunchKernelGGL(lead_dual_check_kernel, dim3(nblk), dim3(256), 0, s, h01L, h01R, n,
+                       (long long)n_k * n * n, partial);
     return hipGetLastError();
 }
 

@@ -51,6 +51,8 @@ struct SrArgs {
     const double2* h00; const double2* h01; const double2* tauin;   // [n_k][n][n]
     double2 *eps_s, *eps, *alpha, *beta, *tau;                      // [np][n][n]
     int* flags; int* iters; double* ref; int* count;
+    // dual surface (the lead on the other side, coupling h01^dagger), or NULL
+    double2* eps_d; double2* tau2; const double2* tauin2; int* iters2; double* ref2;
     const double* energy; double eta, tol;
     long long f0;
     int n, n_e, np;
@@ -94,8 +96,11 @@ hipError_t trace_prod_launch(hipStream_t s, int dt, const void* W1, const void* 
 hipError_t sr_launch_init(hipStream_t s, const SrArgs& a);
 hipError_t sr_launch_zminus(hipStream_t s, const SrArgs& a, const double2* X, double2* M, const Active& act);
 hipError_t sr_launch_check(hipStream_t s, const SrArgs& a, const double2* alpha, const double2* beta, int it);
-hipError_t sr_launch_iters(hipStream_t s, const SrArgs& a, int* out);
+hipError_t sr_launch_iters(hipStream_t s, const SrArgs& a, const int* it, int* out);
 hipError_t scba_launch(hipStream_t s, const ScbaArgs& a, double* rel_change);
 hipError_t observables_launch(hipStream_t s, const ObsArgs& a);
+// partial[2 b] = block-b maximum of |h01L - h01R^dagger|, partial[2 b + 1] = of |h01R|
+hipError_t lead_dual_check_launch(hipStream_t s, const double2* h01L, const double2* h01R, int n_k, int n,
+                                  double* partial, int nblk);
 
 }  // namespace negf

@@ -50,7 +50,7 @@ class negf_system(ctypes.Structure):
 
 EXPORTS = [
     "negf_create", "negf_destroy", "negf_workspace_bytes", "negf_sync_status", "negf_error_string",
-    "negf_bind", "negf_lead_selfenergy", "negf_rgf_forward", "negf_rgf_backward",
+    "negf_bind", "negf_lead_selfenergy", "negf_lead_selfenergy_pair", "negf_rgf_forward", "negf_rgf_backward",
     "negf_scba_selfenergy", "negf_observables", "negf_rgf_adjoint", "negf_zgemm_batched", "negf_zinv_batched", "negf_mixed_stats",
     "negf_gemm_timing_enable", "negf_gemm_timing",
 ]
@@ -73,6 +73,7 @@ def lib():
         "negf_error_string": (ctypes.c_char_p, [i]),
         "negf_bind": (i, [vp, POINTER(negf_system), i, POINTER(c_int)]),
         "negf_lead_selfenergy": (i, [vp, vp, i, vp, vp, vp, i, vp, d, d, i, vp, vp]),
+        "negf_lead_selfenergy_pair": (i, [vp, vp, i, vp, vp, vp, vp, vp, i, vp, d, d, i, vp, vp, vp, vp, vp]),
         "negf_rgf_forward": (i, [vp, vp, i, i, vp, vp, vp, vp, i]),
         "negf_rgf_backward": (i, [vp, vp, i, i, vp, vp, vp, i, i, vp, vp]),
         "negf_scba_selfenergy": (i, [vp, vp, vp, vp, i, vp, d, d, i, d, vp, vp, vp]),
@@ -175,6 +176,22 @@ def negf_lead_selfenergy(ctx, h00, h01, tau, energy, eta, tol, max_iter, sigma, 
         _ptr(tau, torch.complex128, "tau"), n_e, _ptr(energy, torch.float64, "energy"), float(eta), float(tol),
         int(max_iter), _ptr(sigma, torch.complex128, "sigma"), _ptr(iters, torch.int32, "iters"))
     return _check("negf_lead_selfenergy", code, warn_ok=True)
+
+
+def negf_lead_selfenergy_pair(ctx, h00, h01_L, tau_L, h01_R, tau_R, energy, eta, tol, max_iter, sigma_L, sigma_R,
+                              iters_L=None, iters_R=None, stream=None):
+    """Returns (status, dual_used)."""
+    n_k = h00.shape[0]
+    n_e = energy.shape[0]
+    used = ctypes.c_int(0)
+    code = lib().negf_lead_selfenergy_pair(
+        ctx.handle, _stream(stream), n_k, _ptr(h00, torch.complex128, "h00"),
+        _ptr(h01_L, torch.complex128, "h01_L"), _ptr(tau_L, torch.complex128, "tau_L"),
+        _ptr(h01_R, torch.complex128, "h01_R"), _ptr(tau_R, torch.complex128, "tau_R"), n_e,
+        _ptr(energy, torch.float64, "energy"), float(eta), float(tol), int(max_iter),
+        _ptr(sigma_L, torch.complex128, "sigma_L"), _ptr(sigma_R, torch.complex128, "sigma_R"),
+        _ptr(iters_L, torch.int32, "iters_L"), _ptr(iters_R, torch.int32, "iters_R"), ctypes.byref(used))
+    return _check("negf_lead_selfenergy_pair", code, warn_ok=True), used.value
 
 
 def negf_rgf_forward(ctx, p0, np_, sigma_L, sigma_R, scat_R=None, scat_L=None, flags=0, stream=None):

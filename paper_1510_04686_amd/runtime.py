@@ -64,6 +64,7 @@ class RGFSolver:
         self.eta_fill = 0
         self._bind()
         self.sigma_L = self.sigma_R = None
+        self.lead_dual = 0
 
     def _bind(self):
         wl = self.wl
@@ -79,18 +80,23 @@ class RGFSolver:
         self._bind()
 
     # ------------------------------------------------------------------ leads
-    def lead_selfenergies(self, tol=1e-14, max_iter=100):
+    def lead_selfenergies(self, tol=1e-14, max_iter=100, shared_decimation=True):
         wl = self.wl
         shape = (wl.n_k, wl.n_e, wl.nb, wl.nb)
         self.sigma_L = torch.empty(shape, dtype=torch.complex128, device=self.device)
         self.sigma_R = torch.empty(shape, dtype=torch.complex128, device=self.device)
         self.iters_L = torch.empty((wl.n_k, wl.n_e), dtype=torch.int32, device=self.device)
         self.iters_R = torch.empty((wl.n_k, wl.n_e), dtype=torch.int32, device=self.device)
+        if shared_decimation:
+            self.lead_status, self.lead_dual = N.negf_lead_selfenergy_pair(
+                self.ctx, self.lead_h00, self.lead_h01_L, self.lead_tau_L, self.lead_h01_R, self.lead_tau_R,
+                self.energy, wl.eta, tol, max_iter, self.sigma_L, self.sigma_R, self.iters_L, self.iters_R)
+            return self.sigma_L, self.sigma_R
         cL = N.negf_lead_selfenergy(self.ctx, self.lead_h00, self.lead_h01_L, self.lead_tau_L, self.energy, wl.eta,
                                     tol, max_iter, self.sigma_L, self.iters_L)
         cR = N.negf_lead_selfenergy(self.ctx, self.lead_h00, self.lead_h01_R, self.lead_tau_R, self.energy, wl.eta,
                                     tol, max_iter, self.sigma_R, self.iters_R)
-        self.lead_status = max(cL, cR)
+        self.lead_status, self.lead_dual = max(cL, cR), 0
         return self.sigma_L, self.sigma_R
 
     # ------------------------------------------------------------------ RGF

@@ -92,6 +92,50 @@ def test_lead_selfenergy_matches_oracle(nb, seed):
         assert abs(int(s.iters_L[0, ie]) - itL) <= 1 and abs(int(s.iters_R[0, ie]) - itR) <= 1
 
 
+@pytest.mark.parametrize("complex_h", [False, True])
+def test_lead_pair_shared_decimation(complex_h):
+    """h01_L = h01_R^dagger: one decimation serves both leads.  Each lead is
+    checked against its own oracle decimation, and the shared run against two
+    independent GPU decimations."""
+    _say(f"leads shared decimation complex={complex_h}")
+    wl = random_tiny(10, 2, n_e=6, seed=11, eta=1e-3, complex_h=complex_h, n_k=2)
+    s = _solver(wl)
+    sL, sR = [x.clone() for x in s.lead_selfenergies(shared_decimation=True)]
+    itL, itR = s.iters_L.clone(), s.iters_R.clone()
+    assert s.lead_dual == 1 and s.lead_status == 0
+    qL, qR = [x.clone() for x in s.lead_selfenergies(shared_decimation=False)]
+    torch.cuda.synchronize()
+    assert s.lead_dual == 0
+    for ik in range(wl.n_k):
+        for ie in range(wl.n_e):
+            z = wl.energy[ie] + 1j * wl.eta
+            for side, h01, tau, got, it, sep in (("L", wl.lead_h01_L, wl.lead_tau_L, sL, itL, qL),
+                                                  ("R", wl.lead_h01_R, wl.lead_tau_R, sR, itR, qR)):
+                r, itr, _ = O.lead_selfenergy(wl.lead_h00[ik], h01, tau, z)
+                a, _, _ = O.lead_selfenergy(wl.lead_h00[ik], h01, tau, z, variant="alt")
+                tol = max(TOL, 20 * _rel(a, r))
+                g = got[ik, ie].cpu().numpy()
+                assert _rel(g, r) < tol, (side, ik, ie, _rel(g, r))
+                assert _rel(g, sep[ik, ie].cpu().numpy()) < tol, (side, "vs separate")
+                assert abs(int(it[ik, ie]) - itr) <= 1, (side, int(it[ik, ie]), itr)
+
+
+def test_lead_pair_falls_back_without_adjoint_couplings():
+    _say("leads pair fallback")
+    wl = random_tiny(6, 2, n_e=3, seed=12, eta=1e-3)
+    wl.lead_h01_L = wl.lead_h01_L + 1e-6   # no longer h01_R^dagger
+    s = _solver(wl)
+    sL, sR = s.lead_selfenergies(shared_decimation=True)
+    torch.cuda.synchronize()
+    assert s.lead_dual == 0
+    for ie in range(wl.n_e):
+        z = wl.energy[ie] + 1j * wl.eta
+        rL, _, _ = O.lead_selfenergy(wl.lead_h00[0], wl.lead_h01_L, wl.lead_tau_L, z)
+        rR, _, _ = O.lead_selfenergy(wl.lead_h00[0], wl.lead_h01_R, wl.lead_tau_R, z)
+        assert _rel(sL[0, ie].cpu().numpy(), rL) < 1e-9
+        assert _rel(sR[0, ie].cpu().numpy(), rR) < 1e-9
+
+
 def test_lead_selfenergy_reports_iteration_cap():
     _say("leads max_iter=1")
     wl = random_tiny(4, 2, n_e=2, seed=3, eta=1e-6)
