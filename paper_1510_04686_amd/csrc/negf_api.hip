@@ -38,6 +38,9 @@ struct negf_ctx {
     double2* tmp[NTMP] = {};
     void* invE = nullptr;
     void* invP = nullptr;
+    void* invN0 = nullptr;        // narrow outer-panel copies of the two-level inverse
+    void* invN1 = nullptr;
+    int* invComp = nullptr;
     int* rowsrc = nullptr;
     int* piv = nullptr;
     int* coldst = nullptr;
@@ -211,7 +214,8 @@ SandArgs sand_base(const negf_ctx* c, int p0, const Active& act, int np) {
 }
 
 InvWork invwork(negf_ctx* c, void* partner) {
-    return InvWork{partner, c->invE, c->invP, c->rowsrc, c->piv, c->coldst, c->status};
+    return InvWork{partner, c->invE, c->invP, c->rowsrc, c->piv, c->coldst, c->status,
+                   c->invN0, c->invN1, c->invComp};
 }
 
 __global__ void fill_int_kernel(int* p, int v, int n) {
@@ -305,6 +309,9 @@ int negf_create(const negf_config* cfg, negf_ctx** out) {
     for (int i = 0; ok && i < NTMP; ++i) ok = dev_alloc(c, &c->tmp[i], cap * nn * sizeof(double2), c->allocs);
     ok = ok && dev_alloc(c, &c->invE, cap * c->nb * NBMAX_INV * sizeof(double2), c->allocs) &&
          dev_alloc(c, &c->invP, cap * c->nb * NBMAX_INV * sizeof(double2), c->allocs) &&
+         (c->nb <= INV_W || (dev_alloc(c, &c->invN0, cap * c->nb * INV_W * sizeof(double2), c->allocs) &&
+                             dev_alloc(c, &c->invN1, cap * c->nb * INV_W * sizeof(double2), c->allocs) &&
+                             dev_alloc(c, &c->invComp, cap * c->nb * sizeof(int), c->allocs))) &&
          dev_alloc(c, &c->rowsrc, cap * c->nb * sizeof(int), c->allocs) &&
          dev_alloc(c, &c->piv, cap * c->nb * sizeof(int), c->allocs) &&
          dev_alloc(c, &c->coldst, cap * c->nb * sizeof(int), c->allocs) &&

@@ -47,10 +47,13 @@ struct InvWork {
     int* piv;            // [np][n]
     int* coldst;         // [np][n]
     int* status;
+    void* N0; void* N1;  // narrow ping-pong copies of an outer panel, [np][n][INV_W] each (NULL: one level)
+    int* comp;           // [np][n] composite row source of an outer panel
 };
 // dst = src^-1 for every active point (Gauss-Jordan, partial pivoting).  src
 // is destroyed.  dt = DT_C128 or DT_C64 (matrix and arithmetic type).
 constexpr int INV_NMAX = 2048;   // largest block the inverse handles
+constexpr int INV_W = 128;       // outer panel width of the two-level inverse
 hipError_t inverse_init();
 hipError_t inverse_launch(hipStream_t s, int dt, void* src, long long s_src, void* dst, long long s_dst,
                           int n, int np, const Active& act, const InvWork& w);

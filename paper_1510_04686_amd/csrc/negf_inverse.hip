@@ -18,20 +18,34 @@
 //      rank-nbk product, written out of place (ping-pong buffers).
 // After the last panel the column permutation of the recorded row swaps is
 // applied while writing the result, giving A^-1 = X P.
+//
+// Blocks wider than INV_W columns use two levels: inside an outer panel of
+// INV_W columns the inner steps update only that panel (a narrow n x INV_W
+// copy, ping-pong), and the rest of the matrix receives the composite
+// transform of the outer panel in one rank-INV_W update.  Because Gauss-Jordan
+// transforms a column using only that column and the panel's transform, the
+// outer panel's columns evolve exactly as in the one-level scheme; the other
+// columns receive the same composite transform in one pass instead of
+// INV_W / nbk passes, which cuts the full-matrix HBM sweeps by that factor.
 #include "negf_internal.hpp"
 #include "negf_mfma.hpp"
 
 namespace negf {
 
 constexpr int NBMAX = 32;          // widest panel (E / pivot-row buffers are sized for it)
+static_assert(INV_W % 32 == 0 && INV_W % 16 == 0, "outer panel width must be a multiple of every panel width");
 
 struct PanelArgs {
-    const void* X; long long sX;   // current matrix
+    const void* X; long long sX;   // current matrix: global columns [xcol0, ..) with row stride ldX
+    int ldX, xcol0;
     void* E;                       // [np][n][NBMAX]
-    void* Prow;                    // [np][NBMAX][n]
+    void* Prow;                    // [np][NBMAX][pnc]: pivot rows over global columns [pc0, pc0 + pnc)
+    int pc0, pnc;
     int* rowsrc;                   // [np][n]
     int* piv;                      // [np][n]
     int* coldst;                   // [np][n]
+    int* comp;                     // [np][n] composite row source over an outer panel, or NULL
+    int comp_first;                // first inner step of the outer panel
     int n, k0, nbk, np, last;
     Active act;
     int* status;
@@ -60,7 +74,7 @@ __global__ __launch_bounds__(NT) void gj_panel(PanelArgs a) {
 #pragma unroll
         for (int jj = 0; jj < NB; ++jj) {
             v[t][jj].x = 0; v[t][jj].y = 0;
-            if (r < n && jj < nbk) v[t][jj] = X[(long long)r * n + k0 + jj];
+            if (r < n && jj < nbk) v[t][jj] = X[(long long)r * a.ldX + (k0 - a.xcol0) + jj];
         }
     }
     for (int r = tid; r < n; r += NT) rsrc[r] = r;
@@ -158,13 +172,29 @@ __global__ __launch_bounds__(NT) void gj_panel(PanelArgs a) {
         }
     }
     __syncthreads();
-    C* Pr = reinterpret_cast<C*>(a.Prow) + (long long)q * NBMAX * n;
-    for (int idx = tid; idx < n * nbk; idx += NT) {
-        int jr = idx / n, col = idx - jr * n;
-        Pr[(long long)jr * n + col] = X[(long long)rsrc[k0 + jr] * n + col];
+    C* Pr = reinterpret_cast<C*>(a.Prow) + (long long)q * NBMAX * a.pnc;
+    for (int idx = tid; idx < a.pnc * nbk; idx += NT) {
+        int jr = idx / a.pnc, cc = idx - jr * a.pnc;
+        Pr[(long long)jr * a.pnc + cc] = X[(long long)rsrc[k0 + jr] * a.ldX + (a.pc0 + cc - a.xcol0)];
     }
     int* rs = a.rowsrc + (long long)q * n;
     for (int r = tid; r < n; r += NT) rs[r] = rsrc[r];
+    if (a.comp) {
+        // composite row source of the outer panel: comp'[r] = comp[rsrc[r]]
+        int* cm = a.comp + (long long)q * n;
+        int nv[RPT];
+#pragma unroll
+        for (int t = 0; t < RPT; ++t) {
+            const int r = tid + NT * t;
+            nv[t] = (r < n) ? (a.comp_first ? rsrc[r] : cm[rsrc[r]]) : 0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < RPT; ++t) {
+            const int r = tid + NT * t;
+            if (r < n) cm[r] = nv[t];
+        }
+    }
     int* pg = a.piv + (long long)q * n;
     if (tid < nbk) pg[k0 + tid] = sh_piv[tid];
     if (tid == 0 && sh_bad) raise_status(a.status, sh_bad);
@@ -188,38 +218,46 @@ __global__ __launch_bounds__(NT) void gj_panel(PanelArgs a) {
 }
 
 struct UpdArgs {
-    const void* X; long long sX;   // current matrix
-    void* Y; long long sY;         // next matrix (or the destination on the last panel)
-    const void* E; const void* Prow;
+    const void* X; long long sX; int ldX, xcol0;   // current matrix (global columns from xcol0, row stride ldX)
+    void* Y; long long sY; int ldY, ycol0;         // next matrix, same convention (full n x n when last)
+    int c0, nc;                                    // global columns to produce
+    const void* E; int ldE;                        // transform columns E[r][j], j < nbk (global column k0 + j)
+    const void* Prow; int ldP, pc0;                // pivot rows [nbk][..] from global column pc0, or NULL:
+                                                   // gathered as X[rowsrc[k0 + j]]
     const int* rowsrc; const int* coldst;
     int n, k0, nbk, np, last;
     Active act;
 };
 
+// Y[r][c] = X[rs(r)][c] + sum_j (E[r][j] - delta(r, k0 + j)) Prow[j][c] for c outside
+// [k0, k0 + nbk), Y[r][c] = E[r][c - k0] inside; 64 x 64 output tiles, K in
+// slices of BK, two slices staged in LDS at a time.
 template <typename R>
 __global__ __launch_bounds__(256) void gj_update(UpdArgs a) {
     typedef cplx<R> C;
     __shared__ R Es[2][2][BK][LP];   // [K slice][re/im][k][m]
     __shared__ R Ps[2][2][BK][LP];
     const int n = a.n;
-    const int tiles = (n + BM - 1) / BM;
-    const int tpp = tiles * tiles;
+    const int tm = (n + BM - 1) / BM, tn = (a.nc + BM - 1) / BM;
+    const int tpp = tm * tn;
     const int lid = xcd_remap(blockIdx.x, gridDim.x);
     const int q = lid / tpp;
     if (q >= a.np || !a.act(q)) return;
     const int t = lid - q * tpp;
-    const int m0 = (t / tiles) * BM, n0 = (t % tiles) * BM;
+    const int cend = a.c0 + a.nc;
+    const int m0 = (t / tn) * BM, n0 = a.c0 + (t % tn) * BM;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int k0 = a.k0, nbk = a.nbk;
     const int nsl = (nbk + BK - 1) / BK;
     const int wm = wave >> 1, wn = wave & 1;
     const int rowbase = m0 + wm * 32, colbase = n0 + wn * 32;
     const int nmi = rowbase >= n ? 0 : (rowbase + 16 >= n ? 1 : 2);
-    const int nnj = colbase >= n ? 0 : (colbase + 16 >= n ? 1 : 2);
+    const int nnj = colbase >= cend ? 0 : (colbase + 16 >= cend ? 1 : 2);
     const C* X = reinterpret_cast<const C*>(a.X) + q * a.sX;
-    const C* E = reinterpret_cast<const C*>(a.E) + (long long)q * n * NBMAX;
-    const C* Pr = reinterpret_cast<const C*>(a.Prow) + (long long)q * NBMAX * n;
+    const C* E = reinterpret_cast<const C*>(a.E) + (long long)q * n * a.ldE;
+    const C* Pr = a.Prow ? reinterpret_cast<const C*>(a.Prow) + (long long)q * NBMAX * a.ldP : nullptr;
     const int* rs = a.rowsrc + (long long)q * n;
+    const int ldX = a.ldX, xc = a.xcol0;
 
     // Issue the gathered reads of the old matrix first: they do not depend on the product.
     C xo[2][2][4];
@@ -231,43 +269,15 @@ __global__ __launch_bounds__(256) void gj_update(UpdArgs a) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = rowbase + mi * 16 + out_row<R>(lane, r);
-                const bool in = mi < nmi && nj < nnj && row < n && col < n;
+                const bool in = mi < nmi && nj < nnj && row < n && col < cend;
                 const bool inK = col >= k0 && col < k0 + nbk;
                 xo[mi][nj][r].x = 0; xo[mi][nj][r].y = 0;
                 if (in) {
-                    if (inK) xo[mi][nj][r] = E[(long long)row * NBMAX + (col - k0)];
-                    else xo[mi][nj][r] = X[(long long)rs[row] * n + col];
+                    if (inK) xo[mi][nj][r] = E[(long long)row * a.ldE + (col - k0)];
+                    else xo[mi][nj][r] = X[(long long)rs[row] * ldX + (col - xc)];
                 }
             }
         }
-    // Ecoef tile: rows m0.., k (pattern X); pivot-row tile: k rows, cols n0.. (pattern Y)
-    for (int s = 0; s < nsl; ++s) {
-        {
-            int o = tid >> 2, k = (tid & 3) * 4, row = m0 + o;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int kk = s * BK + k + j;
-                C v; v.x = 0; v.y = 0;
-                if (row < n && kk < nbk) {
-                    v = E[(long long)row * NBMAX + kk];
-                    if (row == k0 + kk) v.x -= (R)1;
-                }
-                Es[s][0][k + j][o] = v.x;
-                Es[s][1][k + j][o] = v.y;
-            }
-            int kr = tid >> 4, oc = (tid & 15) * 4;
-            const int kk = s * BK + kr;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                C v; v.x = 0; v.y = 0;
-                int col = n0 + oc + j;
-                if (kk < nbk && col < n) v = Pr[(long long)kk * n + col];
-                Ps[s][0][kr][oc + j] = v.x;
-                Ps[s][1][kr][oc + j] = v.y;
-            }
-        }
-    }
-    __syncthreads();
     typename MF<R>::V cr[2][2], ci[2][2];
 #pragma unroll
     for (int x = 0; x < 2; ++x)
@@ -275,11 +285,44 @@ __global__ __launch_bounds__(256) void gj_update(UpdArgs a) {
         for (int y = 0; y < 2; ++y)
 #pragma unroll
             for (int r = 0; r < 4; ++r) { cr[x][y][r] = 0; ci[x][y][r] = 0; }
-    for (int s = 0; s < nsl; ++s) {
-        if (nmi == 2 && nnj == 2) mma_slice<R, 2, 2>(Es[s], Ps[s], lane, wm, wn, cr, ci);
-        else if (nmi == 2 && nnj == 1) mma_slice<R, 2, 1>(Es[s], Ps[s], lane, wm, wn, cr, ci);
-        else if (nmi == 1 && nnj == 2) mma_slice<R, 1, 2>(Es[s], Ps[s], lane, wm, wn, cr, ci);
-        else if (nmi == 1 && nnj == 1) mma_slice<R, 1, 1>(Es[s], Ps[s], lane, wm, wn, cr, ci);
+    for (int s0 = 0; s0 < nsl; s0 += 2) {
+        if (s0) __syncthreads();
+        // E tile: rows m0.., k (pattern X); pivot-row tile: k rows, cols n0.. (pattern Y)
+        for (int s = s0; s < nsl && s < s0 + 2; ++s) {
+            const int b = s - s0;
+            int o = tid >> 2, k = (tid & 3) * 4, row = m0 + o;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int kk = s * BK + k + j;
+                C v; v.x = 0; v.y = 0;
+                if (row < n && kk < nbk) {
+                    v = E[(long long)row * a.ldE + kk];
+                    if (row == k0 + kk) v.x -= (R)1;
+                }
+                Es[b][0][k + j][o] = v.x;
+                Es[b][1][k + j][o] = v.y;
+            }
+            int kr = tid >> 4, oc = (tid & 15) * 4;
+            const int kk = s * BK + kr;
+            const C* prow = nullptr;
+            if (kk < nbk) prow = Pr ? Pr + (long long)kk * a.ldP - a.pc0 : X + (long long)rs[k0 + kk] * ldX - xc;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                C v; v.x = 0; v.y = 0;
+                int col = n0 + oc + j;
+                if (prow && col < cend) v = prow[col];
+                Ps[b][0][kr][oc + j] = v.x;
+                Ps[b][1][kr][oc + j] = v.y;
+            }
+        }
+        __syncthreads();
+        for (int s = s0; s < nsl && s < s0 + 2; ++s) {
+            const int b = s - s0;
+            if (nmi == 2 && nnj == 2) mma_slice<R, 2, 2>(Es[b], Ps[b], lane, wm, wn, cr, ci);
+            else if (nmi == 2 && nnj == 1) mma_slice<R, 2, 1>(Es[b], Ps[b], lane, wm, wn, cr, ci);
+            else if (nmi == 1 && nnj == 2) mma_slice<R, 1, 2>(Es[b], Ps[b], lane, wm, wn, cr, ci);
+            else if (nmi == 1 && nnj == 1) mma_slice<R, 1, 1>(Es[b], Ps[b], lane, wm, wn, cr, ci);
+        }
     }
 
     C* Y = reinterpret_cast<C*>(a.Y) + q * a.sY;
@@ -292,14 +335,14 @@ __global__ __launch_bounds__(256) void gj_update(UpdArgs a) {
             if (nj >= nnj) break;
             const int col = colbase + nj * 16 + (lane & 15);
             const bool inK = col >= k0 && col < k0 + nbk;
-            const int ocol = (a.last && col < n) ? cd[col] : col;
+            const int ocol = (a.last && col < cend) ? cd[col] : col;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = rowbase + mi * 16 + out_row<R>(lane, r);
-                if (row < n && col < n) {
+                if (row < n && col < cend) {
                     C v = xo[mi][nj][r];
                     if (!inK) { v.x += cr[mi][nj][r]; v.y += ci[mi][nj][r]; }
-                    Y[(long long)row * n + ocol] = v;
+                    Y[(long long)row * a.ldY + (ocol - a.ycol0)] = v;
                 }
             }
         }
@@ -347,26 +390,71 @@ static void launch_panel(hipStream_t s, const PanelShape& ps, int np, size_t lds
 }
 
 template <typename R>
+static hipError_t launch_update(hipStream_t s, const UpdArgs& ua) {
+    const int tm = (ua.n + BM - 1) / BM, tn = (ua.nc + BM - 1) / BM;
+    hipLaunchKernelGGL(gj_update<R>, dim3((unsigned)((long long)ua.np * tm * tn)), dim3(256), 0, s, ua);
+    return hipGetLastError();
+}
+
+template <typename R>
 static hipError_t inverse_typed(hipStream_t s, void* src, long long s_src, void* dst, long long s_dst,
                                 int n, int np, const Active& act, const InvWork& w) {
     if (n > INV_NMAX) return hipErrorInvalidValue;
     const PanelShape ps = Shapes<R>::get(n);
-    const int tiles = (n + BM - 1) / BM;
+    const size_t lds = (size_t)n * sizeof(int);
+    const long long nn = (long long)n * n;
     void* cur = src;
     void* other = w.pa;
-    long long s_cur = s_src, s_other = (long long)n * n;
-    const size_t lds = (size_t)n * sizeof(int);
-    for (int k0 = 0; k0 < n; k0 += ps.nb) {
-        const int nbk = (n - k0 < ps.nb) ? (n - k0) : ps.nb;
-        const int last = (k0 + nbk == n);
-        PanelArgs pa{cur, s_cur, w.E, w.Prow, w.rowsrc, w.piv, w.coldst, n, k0, nbk, np, last, act, w.status};
-        launch_panel<R>(s, ps, np, lds, pa);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        UpdArgs ua{cur, s_cur, last ? dst : other, last ? s_dst : s_other, w.E, w.Prow, w.rowsrc, w.coldst,
-                   n, k0, nbk, np, last, act};
-        hipLaunchKernelGGL(gj_update<R>, dim3((unsigned)((long long)np * tiles * tiles)), dim3(256), 0, s, ua);
-        e = hipGetLastError();
+    long long s_cur = s_src, s_other = nn;
+    const bool two = n > INV_W && w.N0 && w.N1 && w.comp;
+    if (!two) {
+        for (int k0 = 0; k0 < n; k0 += ps.nb) {
+            const int nbk = (n - k0 < ps.nb) ? (n - k0) : ps.nb;
+            const int last = (k0 + nbk == n);
+            PanelArgs pa{cur, s_cur, n, 0, w.E, w.Prow, 0, n, w.rowsrc, w.piv, w.coldst, nullptr, 0,
+                         n, k0, nbk, np, last, act, w.status};
+            launch_panel<R>(s, ps, np, lds, pa);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            UpdArgs ua{cur, s_cur, n, 0, last ? dst : other, last ? s_dst : s_other, n, 0, 0, n,
+                       w.E, NBMAX, w.Prow, n, 0, w.rowsrc, w.coldst, n, k0, nbk, np, last, act};
+            e = launch_update<R>(s, ua);
+            if (e != hipSuccess) return e;
+            void* tp = cur; cur = other; other = tp;
+            long long ts = s_cur; s_cur = s_other; s_other = ts;
+        }
+        return hipSuccess;
+    }
+    for (int K0 = 0; K0 < n; K0 += INV_W) {
+        const int W = (n - K0 < INV_W) ? (n - K0) : INV_W;
+        const int lastK = (K0 + W == n);
+        const long long sN = (long long)n * W;
+        // inner steps: the outer panel's columns, full matrix -> narrow copy -> ... (ping-pong)
+        const void* ncur = cur;
+        long long s_ncur = s_cur;
+        int ld_ncur = n, xc_ncur = 0;
+        void* nbuf[2] = {w.N0, w.N1};
+        int nb_i = 0;
+        for (int k0 = K0; k0 < K0 + W; k0 += ps.nb) {
+            const int nbk = (K0 + W - k0 < ps.nb) ? (K0 + W - k0) : ps.nb;
+            const int last = (k0 + nbk == n);
+            PanelArgs pa{ncur, s_ncur, ld_ncur, xc_ncur, w.E, w.Prow, K0, W, w.rowsrc, w.piv, w.coldst,
+                         w.comp, k0 == K0, n, k0, nbk, np, last, act, w.status};
+            launch_panel<R>(s, ps, np, lds, pa);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            UpdArgs ua{ncur, s_ncur, ld_ncur, xc_ncur, nbuf[nb_i], sN, W, K0, K0, W,
+                       w.E, NBMAX, w.Prow, W, K0, w.rowsrc, w.coldst, n, k0, nbk, np, 0, act};
+            e = launch_update<R>(s, ua);
+            if (e != hipSuccess) return e;
+            ncur = nbuf[nb_i]; s_ncur = sN; ld_ncur = W; xc_ncur = K0;
+            nb_i ^= 1;
+        }
+        // outer update: every column from the matrix before the outer panel, the panel's
+        // columns from the narrow copy; the composite row map gathers rows and pivot rows
+        UpdArgs ua{cur, s_cur, n, 0, lastK ? dst : other, lastK ? s_dst : s_other, n, 0, 0, n,
+                   ncur, W, nullptr, 0, 0, w.comp, w.coldst, n, K0, W, np, lastK, act};
+        hipError_t e = launch_update<R>(s, ua);
         if (e != hipSuccess) return e;
         void* tp = cur; cur = other; other = tp;
         long long ts = s_cur; s_cur = s_other; s_other = ts;

@@ -55,7 +55,7 @@ class RGFSolver:
         self.lead_h01_R, self.lead_tau_R = rep(wl.lead_h01_R), rep(wl.lead_tau_R)
         if capacity is None:
             ce = 8 if self.prec == N.NEGF_MIXED else 16
-            per_point = 2 * self.n_slab_max * nb * nb * ce + 15 * nb * nb * 16 + 64 * nb * 16
+            per_point = 2 * self.n_slab_max * nb * nb * ce + 24 * nb * nb * 16 + (64 + 256) * nb * 16
             free, _ = torch.cuda.mem_get_info(self.device)
             capacity = int(max(1, min(self.n_points, 256, (free * mem_fraction) // per_point)))
         self.capacity = int(capacity)

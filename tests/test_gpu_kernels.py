@@ -57,7 +57,9 @@ def test_zgemm_fp32(ctx, n, opa, opb):
     assert err < 2e-6 * max(1, np.sqrt(n)), err
 
 
-@pytest.mark.parametrize("n", [1, 2, 5, 16, 17, 33, 64, 65, 100, 130, 400])
+# 128/129/256/257/400/416 cover the two-level scheme (outer panels of 128 columns,
+# a ragged last outer panel, a last inner panel narrower than 32)
+@pytest.mark.parametrize("n", [1, 2, 5, 16, 17, 33, 64, 65, 100, 128, 129, 130, 256, 257, 400, 416])
 def test_zinv_fp64(ctx, n):
     from paper_1510_04686_amd import negf
     _say(f"zinv fp64 n={n}")
@@ -80,7 +82,7 @@ def test_zinv_fp64(ctx, n):
         assert err < 1e-14 * cond * n + 1e-13, (b, err, cond)
 
 
-@pytest.mark.parametrize("n", [7, 64, 100])
+@pytest.mark.parametrize("n", [7, 64, 100, 130, 300])
 def test_zinv_fp32(ctx, n):
     from paper_1510_04686_amd import negf
     _say(f"zinv fp32 n={n}")
