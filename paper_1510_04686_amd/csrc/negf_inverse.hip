@@ -49,28 +49,80 @@ struct PanelArgs {
     int n, k0, nbk, np, last;
     Active act;
     int* status;
+    // fused mode: also apply the panel's transform to global columns [uc0, uc0 + unc)
+    // and write them, with the panel's own columns, to Y (which may alias X)
+    void* Y; long long sY; int ldY, ycol0, uc0, unc;
 };
 
-template <typename R, int NB, int RPT, int NT>
+// Pivot search key: the bit pattern of a non-negative double is monotone in
+// its value (NaN sorts above +inf), so one unsigned 64-bit maximum finds the
+// largest candidate.  The 12 low mantissa bits carry 4095 - position, which
+// breaks ties (to 2^-40 relative) toward the lowest position and keeps every
+// candidate's key non-zero.
+__device__ inline unsigned long long pivot_key(double m, int pos) {
+    return ((unsigned long long)__double_as_longlong(m) & ~0xFFFull) | (unsigned long long)(4095 - pos);
+}
+
+template <int CTRL, int ROWM>
+__device__ inline unsigned long long dpp64(unsigned long long x) {
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)x, CTRL, ROWM, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(x >> 32), CTRL, ROWM, 0xf, false);
+    return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+
+// Maximum over a wavefront, returned uniformly: row shifts reduce each row of
+// 16 lanes into its lane 15, two row broadcasts carry rows 0-1 and 2-3 into
+// lane 63, which is read back.
+__device__ inline unsigned long long wave_max_u64(unsigned long long x) {
+    unsigned long long y;
+    y = dpp64<0x111, 0xf>(x); x = x > y ? x : y;   // row_shr:1
+    y = dpp64<0x112, 0xf>(x); x = x > y ? x : y;   // row_shr:2
+    y = dpp64<0x114, 0xf>(x); x = x > y ? x : y;   // row_shr:4
+    y = dpp64<0x118, 0xf>(x); x = x > y ? x : y;   // row_shr:8
+    y = dpp64<0x142, 0xa>(x); x = x > y ? x : y;   // row_bcast:15 -> rows 1, 3
+    y = dpp64<0x143, 0xc>(x); x = x > y ? x : y;   // row_bcast:31 -> rows 2, 3
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)x, 63);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(x >> 32), 63);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// Compiler-only fence: the accumulators must hold their values here and no
+// memory access moves across (emits no instruction).
+template <typename C, int CW>
+__device__ inline void pin_acc(C (&acc)[CW]) {
+#pragma unroll
+    for (int i = 0; i < CW; ++i) asm volatile("" : "+v"(acc[i].x), "+v"(acc[i].y) : : "memory");
+}
+
+// Rows stay in the thread that loaded them; a row exchange only swaps the
+// positions two threads stand for (pos[]).  Per column: every thread offers
+// its candidate key, a DPP maximum per wavefront and one LDS round across
+// wavefronts pick the pivot, the pivot thread publishes its row and 1/p, and
+// every row is eliminated with the same formula (the pivot row with f - 1 in
+// place of f, which turns the update into the scaling by 1/p).
+template <typename R, int NB, int RPT, int NT, bool FUSE>
 __global__ __launch_bounds__(NT) void gj_panel(PanelArgs a) {
     typedef cplx<R> C;
     constexpr int NW = NT / 64;
+    constexpr int CW = 8;                                // fused update: columns per chunk
     __shared__ C rowP[NB];
-    __shared__ C rowC[NB];
-    __shared__ R cand_v[NW];
-    __shared__ int cand_i[NW];
+    __shared__ C sh_inv;
+    __shared__ unsigned long long cand[NW];
     __shared__ int sh_piv[NB];
     __shared__ int sh_bad;
-    extern __shared__ int rsrc[];   // [n] row-source map (dynamic)
+    __shared__ C Pch[FUSE ? NB : 1][FUSE ? CW : 1];      // fused: pivot rows of one chunk
+    extern __shared__ int rsrc[];   // [n] position -> row of X (dynamic)
     const int q = blockIdx.x;
     if (q >= a.np || !a.act(q)) return;
-    const int n = a.n, k0 = a.k0, nbk = a.nbk, tid = threadIdx.x;
+    const int n = a.n, k0 = a.k0, nbk = a.nbk, tid = threadIdx.x, lane = tid & 63;
     const C* X = reinterpret_cast<const C*>(a.X) + q * a.sX;
 
     C v[RPT][NB];
+    int pos[RPT];
 #pragma unroll
     for (int t = 0; t < RPT; ++t) {
         const int r = tid + NT * t;
+        pos[t] = r;
 #pragma unroll
         for (int jj = 0; jj < NB; ++jj) {
             v[t][jj].x = 0; v[t][jj].y = 0;
@@ -83,104 +135,68 @@ __global__ __launch_bounds__(NT) void gj_panel(PanelArgs a) {
 
     for (int j = 0; j < nbk; ++j) {
         const int c = k0 + j;
-        // local candidate in register 0 (the current column)
-        R best = (R)-1;
-        int bi = n;
+        unsigned long long key = 0;
 #pragma unroll
         for (int t = 0; t < RPT; ++t) {
             const int r = tid + NT * t;
-            if (r >= c && r < n) {
-                R m = fabs(v[t][0].x) + fabs(v[t][0].y);
-                if (m > best) { best = m; bi = r; }
+            if (r < n && pos[t] >= c) {
+                const unsigned long long k = pivot_key((double)(fabs(v[t][0].x) + fabs(v[t][0].y)), pos[t]);
+                key = k > key ? k : key;
             }
         }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            R ob = __shfl_xor(best, off);
-            int oi = __shfl_xor(bi, off);
-            if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-        }
-        if ((tid & 63) == 0) { cand_v[tid >> 6] = best; cand_i[tid >> 6] = bi; }
+        key = wave_max_u64(key);
+        if (lane == 0) cand[tid >> 6] = key;
         __syncthreads();                                           // B1
-        R b = cand_v[0];
-        int pv = cand_i[0];
+        unsigned long long best = cand[0];
 #pragma unroll
-        for (int w = 1; w < NW; ++w)
-            if (cand_v[w] > b || (cand_v[w] == b && cand_i[w] < pv)) { b = cand_v[w]; pv = cand_i[w]; }
-        if (!(b > (R)0) || pv >= n) pv = c;    // zero / non-finite column: flagged below
+        for (int w = 1; w < NW; ++w) best = cand[w] > best ? cand[w] : best;
+        const double b = __longlong_as_double((long long)(best & ~0xFFFull));
+        int pv = 4095 - (int)(best & 0xFFFull);
+        if (!(b > 0) || pv >= n) pv = c;    // zero / non-finite column: flagged below
         if (tid == 0) {
-            if (!(b > (R)0)) sh_bad |= (b == (R)0) ? ST_SINGULAR : ST_NONFINITE;
+            if (!(b > 0)) sh_bad |= (b == 0) ? ST_SINGULAR : ST_NONFINITE;
             else if (!isfinite(b)) sh_bad |= ST_NONFINITE;
             sh_piv[j] = pv;
             int tmp = rsrc[c]; rsrc[c] = rsrc[pv]; rsrc[pv] = tmp;
         }
 #pragma unroll
         for (int t = 0; t < RPT; ++t) {
-            const int r = tid + NT * t;
-            if (r == pv) {
+            if (tid + NT * t < n && pos[t] == pv) {
 #pragma unroll
-                for (int jj = 0; jj < NB; ++jj) rowP[jj] = v[t][jj];
-            }
-            if (r == c) {
-#pragma unroll
-                for (int jj = 0; jj < NB; ++jj) rowC[jj] = v[t][jj];
+                for (int jj = 1; jj < NB; ++jj) rowP[jj] = v[t][jj];
+                const C p = v[t][0];
+                const R dd = p.x * p.x + p.y * p.y;
+                C inv; inv.x = p.x / dd; inv.y = -p.y / dd;
+                sh_inv = inv;
             }
         }
         __syncthreads();                                           // B2
-        const C p = rowP[0];
-        const R dd = p.x * p.x + p.y * p.y;
-        C inv; inv.x = p.x / dd; inv.y = -p.y / dd;
-        C f[RPT];
-        bool isc[RPT], isp[RPT];
+        const C inv = sh_inv;
 #pragma unroll
         for (int t = 0; t < RPT; ++t) {
-            const int r = tid + NT * t;
-            isc[t] = (r == c);
-            isp[t] = (r == pv) && (pv != c);
-            f[t] = csel(isp[t], rowC[0], v[t][0]);
-        }
+            const bool isp = pos[t] == pv;
+            C f = v[t][0];
+            f.x -= isp ? (R)1 : (R)0;
+            const C g = cmul(f, inv);
 #pragma unroll
-        for (int jj = 1; jj < NB; ++jj) {
-            const C w = cmul(rowP[jj], inv);                  // scaled pivot row, rotated
-#pragma unroll
-            for (int t = 0; t < RPT; ++t) {
-                const C s = csel(isp[t], rowC[jj], v[t][jj]);
+            for (int jj = 1; jj < NB; ++jj) {
+                const C w = rowP[jj];
                 C o;
-                o.x = s.x - (f[t].x * w.x - f[t].y * w.y);
-                o.y = s.y - (f[t].x * w.y + f[t].y * w.x);
-                v[t][jj - 1] = csel(isc[t], w, o);
+                o.x = v[t][jj].x - (g.x * w.x - g.y * w.y);
+                o.y = v[t][jj].y - (g.x * w.y + g.y * w.x);
+                v[t][jj - 1] = o;
             }
-        }
-#pragma unroll
-        for (int t = 0; t < RPT; ++t) {
-            C e;
-            e.x = -(f[t].x * inv.x - f[t].y * inv.y);
-            e.y = -(f[t].x * inv.y + f[t].y * inv.x);
-            v[t][NB - 1] = csel(isc[t], inv, e);
+            C e; e.x = -g.x + (isp ? (R)1 : (R)0); e.y = -g.y;
+            v[t][NB - 1] = e;
+            pos[t] = isp ? c : (pos[t] == c ? pv : pos[t]);
         }
     }
 
-    // The transform columns sit in registers NB-nbk .. NB-1.
-    C* E = reinterpret_cast<C*>(a.E) + (long long)q * n * NBMAX;
-#pragma unroll
-    for (int t = 0; t < RPT; ++t) {
-        const int r = tid + NT * t;
-        if (r < n) {
-#pragma unroll
-            for (int p = 0; p < NB; ++p)
-                if (p >= NB - nbk) E[(long long)r * NBMAX + (p - (NB - nbk))] = v[t][p];
-        }
-    }
-    __syncthreads();
-    C* Pr = reinterpret_cast<C*>(a.Prow) + (long long)q * NBMAX * a.pnc;
-    for (int idx = tid; idx < a.pnc * nbk; idx += NT) {
-        int jr = idx / a.pnc, cc = idx - jr * a.pnc;
-        Pr[(long long)jr * a.pnc + cc] = X[(long long)rsrc[k0 + jr] * a.ldX + (a.pc0 + cc - a.xcol0)];
-    }
-    int* rs = a.rowsrc + (long long)q * n;
-    for (int r = tid; r < n; r += NT) rs[r] = rsrc[r];
+    int* pg = a.piv + (long long)q * n;
+    if (tid < nbk) pg[k0 + tid] = sh_piv[tid];
+    if (tid == 0 && sh_bad) raise_status(a.status, sh_bad);
     if (a.comp) {
-        // composite row source of the outer panel: comp'[r] = comp[rsrc[r]]
+        // composite row source of the outer panel: comp'[p] = comp[rsrc[p]]
         int* cm = a.comp + (long long)q * n;
         int nv[RPT];
 #pragma unroll
@@ -195,9 +211,83 @@ __global__ __launch_bounds__(NT) void gj_panel(PanelArgs a) {
             if (r < n) cm[r] = nv[t];
         }
     }
-    int* pg = a.piv + (long long)q * n;
-    if (tid < nbk) pg[k0 + tid] = sh_piv[tid];
-    if (tid == 0 && sh_bad) raise_status(a.status, sh_bad);
+
+    if constexpr (FUSE) {
+        // The transform columns are v[0][0 .. NB) (nbk == NB).  Write them in place of
+        // the panel's columns, then update the other columns chunk by chunk:
+        //   Y[p][col] = X[rsrc[p]][col] + sum_j (E[p][j] - delta(p, k0 + j)) X[rsrc[k0 + j]][col].
+        C* Y = reinterpret_cast<C*>(a.Y) + q * a.sY;
+        const int r = tid;
+        const int p = pos[0];
+        if (r < n) {
+#pragma unroll
+            for (int jj = 0; jj < NB; ++jj) Y[(long long)p * a.ldY + (k0 - a.ycol0) + jj] = v[0][jj];
+#pragma unroll
+            for (int jj = 0; jj < NB; ++jj) v[0][jj].x -= (p == k0 + jj) ? (R)1 : (R)0;
+        }
+        const int cend = a.uc0 + a.unc;
+        for (int cc = a.uc0; cc < cend; cc += CW) {
+            if (cc >= k0 && cc + CW <= k0 + NB) continue;          // the panel itself
+            __syncthreads();                                        // Pch reuse
+            for (int idx = tid; idx < NB * CW; idx += NT) {
+                const int jr = idx / CW, c2 = idx - jr * CW, col = cc + c2;
+                C val; val.x = 0; val.y = 0;
+                if (col < cend) val = X[(long long)rsrc[k0 + jr] * a.ldX + (col - a.xcol0)];
+                Pch[jr][c2] = val;
+            }
+            C acc[CW];
+#pragma unroll
+            for (int c2 = 0; c2 < CW; ++c2) {
+                acc[c2].x = 0; acc[c2].y = 0;
+                if (r < n && cc + c2 < cend) acc[c2] = X[(long long)rsrc[p] * a.ldX + (cc + c2 - a.xcol0)];
+            }
+            __syncthreads();                                        // every read of the chunk is done
+#pragma unroll
+            for (int jj = 0; jj < NB; ++jj) {
+                const C e = v[0][jj];
+#pragma unroll
+                for (int c2 = 0; c2 < CW; ++c2) {
+                    const C w = Pch[jj][c2];
+                    acc[c2].x = fma(e.x, w.x, acc[c2].x);
+                    acc[c2].x = fma(-e.y, w.y, acc[c2].x);
+                    acc[c2].y = fma(e.x, w.y, acc[c2].y);
+                    acc[c2].y = fma(e.y, w.x, acc[c2].y);
+                }
+                // keep each row of pivot values next to its use: hoisting every LDS read of the
+                // unrolled loop ahead of the arithmetic would exceed the register budget.  The
+                // empty statement orders the LDS reads and pins the accumulators here.
+                pin_acc<C, CW>(acc);
+            }
+            if (r < n) {
+#pragma unroll
+                for (int c2 = 0; c2 < CW; ++c2) {
+                    const int col = cc + c2;
+                    if (col < cend && (col < k0 || col >= k0 + NB))
+                        Y[(long long)p * a.ldY + (col - a.ycol0)] = acc[c2];
+                }
+            }
+        }
+    } else {
+        // The transform columns sit in registers NB-nbk .. NB-1.
+        C* E = reinterpret_cast<C*>(a.E) + (long long)q * n * NBMAX;
+#pragma unroll
+        for (int t = 0; t < RPT; ++t) {
+            const int r = tid + NT * t;
+            if (r < n) {
+#pragma unroll
+                for (int pp = 0; pp < NB; ++pp)
+                    if (pp >= NB - nbk) E[(long long)pos[t] * NBMAX + (pp - (NB - nbk))] = v[t][pp];
+            }
+        }
+        __syncthreads();
+        C* Pr = reinterpret_cast<C*>(a.Prow) + (long long)q * NBMAX * a.pnc;
+        for (int idx = tid; idx < a.pnc * nbk; idx += NT) {
+            int jr = idx / a.pnc, cc = idx - jr * a.pnc;
+            Pr[(long long)jr * a.pnc + cc] = X[(long long)rsrc[k0 + jr] * a.ldX + (a.pc0 + cc - a.xcol0)];
+        }
+        int* rs = a.rowsrc + (long long)q * n;
+        for (int r = tid; r < n; r += NT) rs[r] = rsrc[r];
+    }
 
     if (a.last) {
         // Column permutation of the final result: A^-1 = X S_{n-1} ... S_0.
@@ -366,7 +456,7 @@ template <> struct Shapes<double> {
 template <> struct Shapes<float> {
     static PanelShape get(int n) {
         if (n <= 256) return {32, 1, 256};
-        if (n <= 512) return {32, 2, 256};
+        if (n <= 512) return {32, 1, 512};
         if (n <= 1024) return {32, 2, 512};
         if (n <= 1536) return {32, 3, 512};
         return {16, 4, 512};  // up to 2048
@@ -374,16 +464,22 @@ template <> struct Shapes<float> {
 };
 
 template <typename R>
-static void launch_panel(hipStream_t s, const PanelShape& ps, int np, size_t lds, const PanelArgs& pa) {
+static void launch_panel(hipStream_t s, const PanelShape& ps, int np, size_t lds, const PanelArgs& pa, bool fuse) {
 #define NEGF_PANEL(NB_, RPT_, NT_)                                                                        \
     if (ps.nb == NB_ && ps.rpt == RPT_ && ps.nt == NT_) {                                                 \
-        hipLaunchKernelGGL((gj_panel<R, NB_, RPT_, NT_>), dim3(np), dim3(NT_), lds, s, pa);               \
+        if constexpr (RPT_ == 1) {                                                                        \
+            if (fuse) {                                                                                   \
+                hipLaunchKernelGGL((gj_panel<R, NB_, RPT_, NT_, true>), dim3(np), dim3(NT_), lds, s, pa); \
+                return;                                                                                   \
+            }                                                                                             \
+        }                                                                                                 \
+        hipLaunchKernelGGL((gj_panel<R, NB_, RPT_, NT_, false>), dim3(np), dim3(NT_), lds, s, pa);        \
         return;                                                                                           \
     }
     if constexpr (sizeof(R) == 8) {
         NEGF_PANEL(32, 1, 512) NEGF_PANEL(16, 2, 512) NEGF_PANEL(16, 3, 512) NEGF_PANEL(8, 4, 512)
     } else {
-        NEGF_PANEL(32, 1, 256) NEGF_PANEL(32, 2, 256) NEGF_PANEL(32, 2, 512) NEGF_PANEL(32, 3, 512)
+        NEGF_PANEL(32, 1, 256) NEGF_PANEL(32, 1, 512) NEGF_PANEL(32, 2, 512) NEGF_PANEL(32, 3, 512)
         NEGF_PANEL(16, 4, 512)
     }
 #undef NEGF_PANEL
@@ -412,8 +508,8 @@ static hipError_t inverse_typed(hipStream_t s, void* src, long long s_src, void*
             const int nbk = (n - k0 < ps.nb) ? (n - k0) : ps.nb;
             const int last = (k0 + nbk == n);
             PanelArgs pa{cur, s_cur, n, 0, w.E, w.Prow, 0, n, w.rowsrc, w.piv, w.coldst, nullptr, 0,
-                         n, k0, nbk, np, last, act, w.status};
-            launch_panel<R>(s, ps, np, lds, pa);
+                         n, k0, nbk, np, last, act, w.status, nullptr, 0, 0, 0, 0, 0};
+            launch_panel<R>(s, ps, np, lds, pa, false);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
             UpdArgs ua{cur, s_cur, n, 0, last ? dst : other, last ? s_dst : s_other, n, 0, 0, n,
@@ -429,26 +525,35 @@ static hipError_t inverse_typed(hipStream_t s, void* src, long long s_src, void*
         const int W = (n - K0 < INV_W) ? (n - K0) : INV_W;
         const int lastK = (K0 + W == n);
         const long long sN = (long long)n * W;
-        // inner steps: the outer panel's columns, full matrix -> narrow copy -> ... (ping-pong)
+        // inner steps: the outer panel's columns, full matrix -> narrow copy.  A full-width
+        // panel with one row per thread updates the other columns itself (in place once
+        // the narrow copy exists); otherwise a separate update writes the other narrow buffer.
         const void* ncur = cur;
         long long s_ncur = s_cur;
         int ld_ncur = n, xc_ncur = 0;
+        bool in_narrow = false;
         void* nbuf[2] = {w.N0, w.N1};
         int nb_i = 0;
         for (int k0 = K0; k0 < K0 + W; k0 += ps.nb) {
             const int nbk = (K0 + W - k0 < ps.nb) ? (K0 + W - k0) : ps.nb;
             const int last = (k0 + nbk == n);
+            const bool fuse = ps.rpt == 1 && nbk == ps.nb;
+            void* ydst = fuse && in_narrow ? const_cast<void*>(ncur) : nbuf[nb_i];
             PanelArgs pa{ncur, s_ncur, ld_ncur, xc_ncur, w.E, w.Prow, K0, W, w.rowsrc, w.piv, w.coldst,
-                         w.comp, k0 == K0, n, k0, nbk, np, last, act, w.status};
-            launch_panel<R>(s, ps, np, lds, pa);
+                         w.comp, k0 == K0, n, k0, nbk, np, last, act, w.status,
+                         ydst, sN, W, K0, K0, W};
+            launch_panel<R>(s, ps, np, lds, pa, fuse);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
-            UpdArgs ua{ncur, s_ncur, ld_ncur, xc_ncur, nbuf[nb_i], sN, W, K0, K0, W,
-                       w.E, NBMAX, w.Prow, W, K0, w.rowsrc, w.coldst, n, k0, nbk, np, 0, act};
-            e = launch_update<R>(s, ua);
-            if (e != hipSuccess) return e;
-            ncur = nbuf[nb_i]; s_ncur = sN; ld_ncur = W; xc_ncur = K0;
-            nb_i ^= 1;
+            if (!fuse) {
+                UpdArgs ua{ncur, s_ncur, ld_ncur, xc_ncur, ydst, sN, W, K0, K0, W,
+                           w.E, NBMAX, w.Prow, W, K0, w.rowsrc, w.coldst, n, k0, nbk, np, 0, act};
+                e = launch_update<R>(s, ua);
+                if (e != hipSuccess) return e;
+            }
+            if (ydst == nbuf[nb_i]) nb_i ^= 1;
+            ncur = ydst; s_ncur = sN; ld_ncur = W; xc_ncur = K0;
+            in_narrow = true;
         }
         // outer update: every column from the matrix before the outer panel, the panel's
         // columns from the narrow copy; the composite row map gathers rows and pivot rows
