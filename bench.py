@@ -38,8 +38,10 @@ WORKLOAD_DESC = {
 
 def model_flops(wl, iters_L, iters_R, n_solves=1, shared=False):
     """Algorithmic flops of one step.  U = 8 b^3 (one complex b x b x b product
-    or one complex inverse).  RGF for G^R + G^<: 8 U per slab per point (forward:
-    inverse + g X g^dagger; backward: P = L G, G = g + P R, T = P Q, L G^< L^dagger).
+    or one complex inverse).  RGF for G^R + G^<: 7 U per slab per point (forward:
+    inverse, g X, then (g X) g^dagger of which only the anti-Hermitian half is
+    formed; backward: P = L G, G = g + P R, T = P Q, W = L G^<, and the
+    anti-Hermitian half of W L^dagger).
     Sancho-Rubio: 7 U per decimation step per lead (1 inverse + 6 products)
     plus 3 U per lead for the final surface inverse and tau g tau^dagger; with
     the shared decimation (h01_L = h01_R^dagger) one run of max(iters) steps
@@ -48,7 +50,7 @@ def model_flops(wl, iters_L, iters_R, n_solves=1, shared=False):
     b = wl.nb
     U = 8.0 * b ** 3
     counts = np.diff(wl.slab_offset)
-    rgf = 8.0 * U * float(np.sum(counts)) * wl.n_k * wl.n_e * n_solves
+    rgf = 7.0 * U * float(np.sum(counts)) * wl.n_k * wl.n_e * n_solves
     steps = float(np.sum(np.maximum(iters_L, iters_R))) if shared else float(np.sum(iters_L)) + float(np.sum(iters_R))
     lead = U * (7.0 * steps + 3.0 * 2 * wl.n_k * wl.n_e)
     return rgf, lead
@@ -108,6 +110,8 @@ def main():
     ap.add_argument("--samples", type=int, default=None, help="C4: number of alloy samples (default 128)")
     ap.add_argument("--scba-iters", type=int, default=None, help="C3: SCBA iterations (default 20)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tune", default="auto", choices=["auto", "default"],
+                    help="kernel shapes: measured on this GPU before timing (auto) or the library defaults")
     ap.add_argument("--cpu-points", type=int, default=4)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of this many MiB (counter calibration)")
@@ -141,7 +145,8 @@ def main():
     print(f"[bench] workload {args.workload}: nb={wl.nb} samples={wl.n_samples} slabs={wl.total_slabs} "
           f"n_k={wl.n_k} n_e={wl.n_e} precision={args.precision}", file=sys.stderr, flush=True)
     adj_seg = -1 if args.workload == "C5" else 0
-    solver = RGFSolver(wl, precision=args.precision, capacity=args.capacity, adjoint_segment=adj_seg)
+    solver = RGFSolver(wl, precision=args.precision, capacity=args.capacity, adjoint_segment=adj_seg,
+                       tune="auto" if args.tune == "auto" else None)
     print(f"[bench] capacity={solver.capacity} points/batch, workspace "
           f"{N.negf_workspace_bytes(solver.ctx) / 2**30:.1f} GiB", file=sys.stderr, flush=True)
     n_iter = (args.scba_iters or wl.n_scba) if args.workload == "C3" else 1
@@ -208,6 +213,7 @@ def main():
         "model_flops_per_step": {"rgf": rgf_f, "leads": lead_f},
         "lead_iterations_mean": float((iters_L.mean() + iters_R.mean()) / 2),
         "lead_shared_decimation": bool(solver.lead_dual),
+        "kernel_shapes": solver.tuning,
         "roofline": {"bound": "mfma", "kernel": "batched complex GEMM (negf::gemm_kernel)",
                      "achieved": achieved / 1e12 if achieved else None, "peak": peak / 1e12,
                      "unit": "TFLOP/s", "frac": (achieved / peak) if achieved else None,

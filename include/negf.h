@@ -276,6 +276,27 @@ int negf_mixed_stats(negf_ctx* ctx, void* stream, long long* n_fallback, double*
 int negf_gemm_timing_enable(negf_ctx* ctx, int enable);
 int negf_gemm_timing(negf_ctx* ctx, void* stream, long long* launches, double* ms, double* flops);
 
+/*
+ * Kernel shape choices of a context (the batching form picks tile shapes by
+ * measurement, not by a fixed table).
+ *   gemm_prefetch  K slices of the batched GEMM in flight: 1 or 2 (default 2)
+ *   inv_outer      outer panel width of the two-level block inverse: 0 (one
+ *                  level) or a multiple of 32 in [64, 256] (default 128)
+ * negf_autotune times every candidate on the context's own workspace (block nb,
+ * batch = capacity, the context's precision) with synthetic well-conditioned
+ * blocks, `reps` launches each, applies the fastest and returns it.  It
+ * synchronises `stream` and overwrites the workspace: call it between solves,
+ * never inside a graph capture.  Results depend only on (device, nb, capacity,
+ * precision), so callers may cache them and apply them with negf_set_tuning.
+ * Errors: NEGF_EINVAL (bad values), NEGF_EHIP. */
+typedef struct {
+    int gemm_prefetch;
+    int inv_outer;
+} negf_tuning;
+int negf_get_tuning(const negf_ctx* ctx, negf_tuning* out);
+int negf_set_tuning(negf_ctx* ctx, const negf_tuning* tuning);
+int negf_autotune(negf_ctx* ctx, void* stream, int reps, negf_tuning* out);
+
 #ifdef __cplusplus
 }
 #endif

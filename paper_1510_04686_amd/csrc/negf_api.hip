@@ -82,6 +82,9 @@ struct negf_ctx {
     double* scba_partial_d = nullptr;
     double* trans_d = nullptr;
 
+    // tuning choices (negf_set_tuning / negf_autotune)
+    negf_tuning tune{2, 128};
+
     // forward state
     bool fwd_done = false;
     int fwd_p0 = -1, fwd_np = 0, fwd_flags = 0;
@@ -146,14 +149,18 @@ hipEvent_t get_event(negf_ctx* c) {
 hipError_t run_gemm(negf_ctx* c, hipStream_t s, GemmTypes ty, int opa, int opb, int epi, const GemmArgs& g,
                     long long active) {
     if (g.np <= 0 || active <= 0) return hipSuccess;
-    if (!c->timing) return gemm_launch(s, ty, opa, opb, epi, g);
+    GemmArgs gt = g;
+    gt.pf = c->tune.gemm_prefetch;
+    if (!c->timing) return gemm_launch(s, ty, opa, opb, epi, gt);
     if ((int)c->pending.size() >= EV_POOL) {
         hipError_t e = drain_timing(c);
         if (e != hipSuccess) return e;
     }
-    TimedLaunch t{get_event(c), get_event(c), 8.0 * (double)g.n * g.n * g.n * (double)active};
+    const double tl = (double)((g.n + 63) / 64);
+    const double frac = (double)gemm_tiles(g.n, epi) / (tl * tl);   // executed share of the full product
+    TimedLaunch t{get_event(c), get_event(c), 8.0 * (double)g.n * g.n * g.n * (double)active * frac};
     hipEventRecord(t.a, s);
-    hipError_t e = gemm_launch(s, ty, opa, opb, epi, g);
+    hipError_t e = gemm_launch(s, ty, opa, opb, epi, gt);
     hipEventRecord(t.b, s);
     c->pending.push_back(t);
     return e;
@@ -215,7 +222,22 @@ SandArgs sand_base(const negf_ctx* c, int p0, const Active& act, int np) {
 
 InvWork invwork(negf_ctx* c, void* partner) {
     return InvWork{partner, c->invE, c->invP, c->rowsrc, c->piv, c->coldst, c->status,
-                   c->invN0, c->invN1, c->invComp};
+                   c->invN0, c->invN1, c->invComp, c->invN0 ? c->tune.inv_outer : 0};
+}
+
+// Synthetic well-conditioned blocks for timing: entries in [-1, 1) from an
+// integer hash, plus `diag` on the diagonal.
+template <typename C>
+__global__ void tune_fill_kernel(C* M, long long nn, int n, long long total, double diag) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    unsigned long long h = (unsigned long long)i * 0x9E3779B97F4A7C15ull;
+    h ^= h >> 29; h *= 0xBF58476D1CE4E5B9ull; h ^= h >> 32;
+    const double re = (double)(h & 0xFFFFF) / 524288.0 - 1.0, im = (double)((h >> 20) & 0xFFFFF) / 524288.0 - 1.0;
+    const long long e = i % nn;
+    const int r = (int)(e / n), c = (int)(e - (long long)r * n);
+    C v; v.x = re + (r == c ? diag : 0.0); v.y = im;
+    M[i] = v;
 }
 
 __global__ void fill_int_kernel(int* p, int v, int n) {
@@ -309,13 +331,13 @@ int negf_create(const negf_config* cfg, negf_ctx** out) {
     for (int i = 0; ok && i < NTMP; ++i) ok = dev_alloc(c, &c->tmp[i], cap * nn * sizeof(double2), c->allocs);
     ok = ok && dev_alloc(c, &c->invE, cap * c->nb * NBMAX_INV * sizeof(double2), c->allocs) &&
          dev_alloc(c, &c->invP, cap * c->nb * NBMAX_INV * sizeof(double2), c->allocs) &&
-         (c->nb <= INV_W || (dev_alloc(c, &c->invN0, cap * c->nb * INV_W * sizeof(double2), c->allocs) &&
-                             dev_alloc(c, &c->invN1, cap * c->nb * INV_W * sizeof(double2), c->allocs) &&
-                             dev_alloc(c, &c->invComp, cap * c->nb * sizeof(int), c->allocs))) &&
+         (c->nb <= 64 || (dev_alloc(c, &c->invN0, cap * c->nb * INV_WMAX * sizeof(double2), c->allocs) &&
+                          dev_alloc(c, &c->invN1, cap * c->nb * INV_WMAX * sizeof(double2), c->allocs) &&
+                          dev_alloc(c, &c->invComp, cap * c->nb * sizeof(int), c->allocs))) &&
          dev_alloc(c, &c->rowsrc, cap * c->nb * sizeof(int), c->allocs) &&
          dev_alloc(c, &c->piv, cap * c->nb * sizeof(int), c->allocs) &&
          dev_alloc(c, &c->coldst, cap * c->nb * sizeof(int), c->allocs) &&
-         dev_alloc(c, &c->bond_partial, cap * 8 * sizeof(double), c->allocs) &&
+         dev_alloc(c, &c->bond_partial, cap * BOND_NWB * sizeof(double), c->allocs) &&
          dev_alloc(c, &c->sr_flags, cap * sizeof(int), c->allocs) &&
          dev_alloc(c, &c->sr_iters, cap * sizeof(int), c->allocs) &&
          dev_alloc(c, &c->sr_ref, cap * sizeof(double), c->allocs) &&
@@ -632,7 +654,7 @@ int negf_rgf_forward(negf_ctx* c, void* stream, int p0, int np, const negf_c128*
         G.A = slot(c, c->gst, i); G.sA = sst; G.B = c->tmp[1]; G.sB = nn; G.C = c->tmp[2]; G.sC = nn;
         NEGF_HIP_CHECK(run_gemm(c, s, TS, OP_N, OP_N, EPI_STORE, G, cnt));
         G.A = c->tmp[2]; G.sA = nn; G.B = slot(c, c->gst, i); G.sB = sst; G.C = slot(c, c->glst, i); G.sC = sst;
-        NEGF_HIP_CHECK(run_gemm(c, s, TS, OP_N, OP_C, EPI_STORE, G, cnt));
+        NEGF_HIP_CHECK(run_gemm(c, s, TS, OP_N, OP_C, EPI_STORE_AH, G, cnt));   // anti-Hermitian
         if (wantT) {
             // left-column chain G_{i,1} = g_i H_{i,i-1} G_{i-1,1}
             if (i == 0) {
@@ -727,13 +749,14 @@ int negf_rgf_backward(negf_ctx* c, void* stream, int p0, int np, negf_c128* GR, 
             // G^<_s = g^<_s + W L^dagger + T - T^dagger
             G.A = c->tmp[7]; G.B = c->tmp[0]; G.C = GLb[cur]; G.D = slot(c, c->glst, st); G.sD = sst;
             G.T = c->tmp[6]; G.sT = nn;
-            NEGF_HIP_CHECK(run_gemm(c, s, TS, OP_N, OP_C, EPI_ADD_TTD, G, cB));
+            NEGF_HIP_CHECK(run_gemm(c, s, TS, OP_N, OP_C, EPI_ADD_TTD_AH, G, cB));   // anti-Hermitian
             if (bond_j) {
                 BondArgs b{};
                 b.hup = reinterpret_cast<const double2*>(c->sys.h_up);
                 b.hup_k = c->sys.h_up_k_stride;
                 b.ub = c->sys.up_block; b.slab = st;
                 b.G = Gb[nxt]; b.GL = GLb[nxt]; b.Q = c->tmp[3]; b.L = c->tmp[0]; b.sM = nn;
+                b.gls = slot(c, c->glst, st); b.s_gls = sst;
                 b.partial = c->bond_partial; b.n = n; b.np = hiB; b.act = aB; b.ps = ps;
                 NEGF_HIP_CHECK(bond_launch(s, sdt, b, bond_j, slab_stride));
             }
@@ -938,7 +961,7 @@ int negf_rgf_adjoint(negf_ctx* c, void* stream, int p0, int np, const double* w_
                 NEGF_HIP_CHECK(mm(OP_N, OP_N, EPI_ADD, tP, nn, tR, nn, Gb[cur], nn, slot(c, c->gst, st), sst));
                 NEGF_HIP_CHECK(mm(OP_N, OP_N, EPI_STORE, tP, nn, tQ, nn, tT, nn));
                 NEGF_HIP_CHECK(mm(OP_N, OP_N, EPI_STORE, tL, nn, GLb[nxt], nn, tW, nn));
-                NEGF_HIP_CHECK(mm(OP_N, OP_C, EPI_ADD_TTD, tW, nn, tL, nn, GLb[cur], nn, slot(c, c->glst, st), sst, tT));
+                NEGF_HIP_CHECK(mm(OP_N, OP_C, EPI_ADD_TTD_AH, tW, nn, tL, nn, GLb[cur], nn, slot(c, c->glst, st), sst, tT));
                 // (2,3) level: Y_i = y + R^dag (G^dag R_y + Y R) + L_y G R
                 NEGF_HIP_CHECK(mm(OP_N, OP_N, EPI_STORE, Gb[nxt], nn, tR, nn, tGR, nn));
                 NEGF_HIP_CHECK(mm(OP_C, OP_N, EPI_STORE, Gb[nxt], nn, tRy, nn, tK1, nn));
@@ -1002,6 +1025,91 @@ int negf_gemm_timing_enable(negf_ctx* c, int enable) {
     if (!c) return NEGF_EINVAL;
     c->timing = enable != 0;
     if (c->timing) { c->t_launches = 0; c->t_ms = 0; c->t_flops = 0; }
+    return NEGF_OK;
+}
+
+int negf_get_tuning(const negf_ctx* c, negf_tuning* out) {
+    if (!c || !out) return NEGF_EINVAL;
+    *out = c->tune;
+    return NEGF_OK;
+}
+
+int negf_set_tuning(negf_ctx* c, const negf_tuning* t) {
+    if (!c || !t) return NEGF_EINVAL;
+    if (t->gemm_prefetch != 1 && t->gemm_prefetch != 2) return NEGF_EINVAL;
+    if (t->inv_outer != 0 && (t->inv_outer < 64 || t->inv_outer > INV_WMAX || t->inv_outer % 32 != 0)) return NEGF_EINVAL;
+    c->tune = *t;
+    return NEGF_OK;
+}
+
+int negf_autotune(negf_ctx* c, void* stream, int reps, negf_tuning* out) {
+    if (!c) return NEGF_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    reps = std::max(1, std::min(reps, 100));
+    const int n = c->nb, np = c->cap, dt = c->sdt;
+    const long long nn = (long long)n * n, total = nn * np;
+    const bool was_timing = c->timing;
+    c->timing = false;
+    hipEvent_t e0, e1;
+    NEGF_HIP_CHECK(hipEventCreate(&e0));
+    NEGF_HIP_CHECK(hipEventCreate(&e1));
+    auto fill = [&](void* M, double diag) {
+        const unsigned blocks = (unsigned)((total + 255) / 256);
+        if (dt == DT_C128)
+            hipLaunchKernelGGL(tune_fill_kernel<double2>, dim3(blocks), dim3(256), 0, s, (double2*)M, nn, n, total, diag);
+        else
+            hipLaunchKernelGGL(tune_fill_kernel<float2>, dim3(blocks), dim3(256), 0, s, (float2*)M, nn, n, total, diag);
+        return hipGetLastError();
+    };
+    auto elapsed = [&](float* ms) {
+        hipError_t e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+        return e;
+    };
+    negf_tuning best = c->tune;
+    hipError_t err = hipSuccess;
+    Active all{nullptr, 0, 0, PRED_ALL, nullptr};
+    // batched GEMM: K slices in flight
+    if ((err = fill(c->tmp[0], 0.0)) == hipSuccess) err = fill(c->tmp[1], 0.0);
+    float best_ms = 0.0f;
+    for (int pf = 1; pf <= 2 && err == hipSuccess; ++pf) {
+        GemmArgs G = gargs(n, np, all);
+        G.A = c->tmp[0]; G.sA = nn; G.B = c->tmp[1]; G.sB = nn; G.C = c->tmp[2]; G.sC = nn; G.pf = pf;
+        const GemmTypes ty{dt, dt, dt, dt};
+        err = gemm_launch(s, ty, OP_N, OP_N, EPI_STORE, G);
+        if (err == hipSuccess) err = hipEventRecord(e0, s);
+        for (int r = 0; r < reps && err == hipSuccess; ++r) err = gemm_launch(s, ty, OP_N, OP_N, EPI_STORE, G);
+        float ms = 0.0f;
+        if (err == hipSuccess) err = elapsed(&ms);
+        if (err == hipSuccess && (pf == 1 || ms < best_ms)) { best_ms = ms; best.gemm_prefetch = pf; }
+    }
+    // block inverse: outer panel width (0: one level)
+    const int cands[] = {0, 64, 96, 128, 160, 192, 256};
+    best_ms = 0.0f;
+    bool first = true;
+    for (int W : cands) {
+        if (err != hipSuccess) break;
+        if (W != 0 && (!c->invN0 || W >= n)) continue;
+        InvWork w = invwork(c, c->tmp[5]);
+        w.W = W;
+        float ms = 0.0f;
+        for (int r = 0; r <= reps && err == hipSuccess; ++r) {   // r == 0 warms up
+            err = fill(c->tmp[3], (double)n);
+            if (err == hipSuccess) err = hipEventRecord(e0, s);
+            if (err == hipSuccess) err = inverse_launch(s, dt, c->tmp[3], nn, c->tmp[4], nn, n, np, all, w);
+            float one = 0.0f;
+            if (err == hipSuccess) err = elapsed(&one);
+            if (r > 0) ms += one;
+        }
+        if (err == hipSuccess && (first || ms < best_ms)) { best_ms = ms; best.inv_outer = W; first = false; }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    c->timing = was_timing;
+    if (err != hipSuccess) return NEGF_EHIP;
+    c->tune = best;
+    if (out) *out = best;
     return NEGF_OK;
 }
 

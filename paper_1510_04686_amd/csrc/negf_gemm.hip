@@ -12,18 +12,41 @@
 
 namespace negf {
 
-template <typename TA, typename TB, typename TC, typename Acc, int OPA, int OPB, int EPI>
+static_assert(BM == 64, "gemm_tiles() assumes 64-wide tiles");
+
+template <typename Acc>
+__device__ inline void mma_tile(Acc (*As)[BK][LP], Acc (*Bs)[BK][LP], int lane, int wm, int wn, int nmi, int nnj,
+                                typename MF<Acc>::V (&cr)[2][2], typename MF<Acc>::V (&ci)[2][2]) {
+    if (nmi == 2 && nnj == 2) mma_slice<Acc, 2, 2>(As, Bs, lane, wm, wn, cr, ci);
+    else if (nmi == 2 && nnj == 1) mma_slice<Acc, 2, 1>(As, Bs, lane, wm, wn, cr, ci);
+    else if (nmi == 1 && nnj == 2) mma_slice<Acc, 1, 2>(As, Bs, lane, wm, wn, cr, ci);
+    else if (nmi == 1 && nnj == 1) mma_slice<Acc, 1, 1>(As, Bs, lane, wm, wn, cr, ci);
+}
+
+template <typename TA, typename TB, typename TC, typename Acc, int OPA, int OPB, int EPI, int PF>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     __shared__ Acc As[2][2][BK][LP];
     __shared__ Acc Bs[2][2][BK][LP];
+    constexpr bool AH = (EPI == EPI_STORE_AH || EPI == EPI_ADD_TTD_AH);
     const int n = g.n;
     const int tiles = (n + BM - 1) / BM;
-    const int tpp = tiles * tiles;
+    const int tpp = AH ? tiles * (tiles + 1) / 2 : tiles * tiles;
     const int lid = xcd_remap(blockIdx.x, gridDim.x);
     const int q = lid / tpp;
     if (q >= g.np || !g.act(q)) return;
     const int t = lid - q * tpp;
-    const int m0 = (t / tiles) * BM, n0 = (t % tiles) * BM;
+    int ti, tj;
+    if (AH) {
+        // t -> (ti, tj), tj <= ti, row-major over the lower triangle of tiles
+        ti = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+        while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+        while (ti * (ti + 1) / 2 > t) --ti;
+        tj = t - ti * (ti + 1) / 2;
+    } else {
+        ti = t / tiles;
+        tj = t - ti * tiles;
+    }
+    const int m0 = ti * BM, n0 = tj * BM;
     const TA* __restrict__ A = (const TA*)g.A + q * g.sA;
     const TB* __restrict__ B = (const TB*)g.B + q * g.sB;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -44,30 +67,61 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     // op(B) slice: OPB = N -> rows k (pattern Y); C -> rows n, contiguous k (pattern X)
     constexpr bool AK = (OPA == OP_C);
     constexpr bool BKR = (OPB == OP_N);
-    TA ra[4];
-    TB rb[4];
     const int nkt = (n + BK - 1) / BK;
-    load_slice<TA, AK>(A, n, m0, 0, tid, ra);
-    load_slice<TB, BKR>(B, n, n0, 0, tid, rb);
-    store_slice<Acc, TA, AK, OPA == OP_C>(As[0], tid, ra);
-    store_slice<Acc, TB, BKR, OPB == OP_C>(Bs[0], tid, rb);
-    __syncthreads();
-    for (int kt = 0; kt < nkt; ++kt) {
-        const int buf = kt & 1;
-        const bool more = kt + 1 < nkt;
-        if (more) {
-            load_slice<TA, AK>(A, n, m0, (kt + 1) * BK, tid, ra);
-            load_slice<TB, BKR>(B, n, n0, (kt + 1) * BK, tid, rb);
-        }
-        if (nmi == 2 && nnj == 2) mma_slice<Acc, 2, 2>(As[buf], Bs[buf], lane, wm, wn, cr, ci);
-        else if (nmi == 2 && nnj == 1) mma_slice<Acc, 2, 1>(As[buf], Bs[buf], lane, wm, wn, cr, ci);
-        else if (nmi == 1 && nnj == 2) mma_slice<Acc, 1, 2>(As[buf], Bs[buf], lane, wm, wn, cr, ci);
-        else if (nmi == 1 && nnj == 1) mma_slice<Acc, 1, 1>(As[buf], Bs[buf], lane, wm, wn, cr, ci);
-        if (more) {
-            store_slice<Acc, TA, AK, OPA == OP_C>(As[buf ^ 1], tid, ra);
-            store_slice<Acc, TB, BKR, OPB == OP_C>(Bs[buf ^ 1], tid, rb);
-        }
+    if constexpr (PF == 1) {
+        TA ra[4];
+        TB rb[4];
+        load_slice<TA, AK>(A, n, m0, 0, tid, ra);
+        load_slice<TB, BKR>(B, n, n0, 0, tid, rb);
+        store_slice<Acc, TA, AK, OPA == OP_C>(As[0], tid, ra);
+        store_slice<Acc, TB, BKR, OPB == OP_C>(Bs[0], tid, rb);
         __syncthreads();
+        for (int kt = 0; kt < nkt; ++kt) {
+            const int buf = kt & 1;
+            const bool more = kt + 1 < nkt;
+            if (more) {
+                load_slice<TA, AK>(A, n, m0, (kt + 1) * BK, tid, ra);
+                load_slice<TB, BKR>(B, n, n0, (kt + 1) * BK, tid, rb);
+            }
+            mma_tile<Acc>(As[buf], Bs[buf], lane, wm, wn, nmi, nnj, cr, ci);
+            if (more) {
+                store_slice<Acc, TA, AK, OPA == OP_C>(As[buf ^ 1], tid, ra);
+                store_slice<Acc, TB, BKR, OPB == OP_C>(Bs[buf ^ 1], tid, rb);
+            }
+            __syncthreads();
+        }
+    } else {
+        // two slices in flight: slice kt + 2 is read into registers while slice kt is
+        // multiplied and slice kt + 1 (read one step earlier) moves into LDS
+        TA ra[2][4];
+        TB rb[2][4];
+        load_slice<TA, AK>(A, n, m0, 0, tid, ra[0]);
+        load_slice<TB, BKR>(B, n, n0, 0, tid, rb[0]);
+        if (nkt > 1) {
+            load_slice<TA, AK>(A, n, m0, BK, tid, ra[1]);
+            load_slice<TB, BKR>(B, n, n0, BK, tid, rb[1]);
+        }
+        store_slice<Acc, TA, AK, OPA == OP_C>(As[0], tid, ra[0]);
+        store_slice<Acc, TB, BKR, OPB == OP_C>(Bs[0], tid, rb[0]);
+        __syncthreads();
+#define NEGF_GEMM_STEP(KT, CUR, NXT)                                                                      \
+    {                                                                                                     \
+        if ((KT) + 2 < nkt) {                                                                             \
+            load_slice<TA, AK>(A, n, m0, ((KT) + 2) * BK, tid, ra[CUR]);                                  \
+            load_slice<TB, BKR>(B, n, n0, ((KT) + 2) * BK, tid, rb[CUR]);                                 \
+        }                                                                                                 \
+        mma_tile<Acc>(As[CUR], Bs[CUR], lane, wm, wn, nmi, nnj, cr, ci);                                  \
+        if ((KT) + 1 < nkt) {                                                                             \
+            store_slice<Acc, TA, AK, OPA == OP_C>(As[NXT], tid, ra[NXT]);                                 \
+            store_slice<Acc, TB, BKR, OPB == OP_C>(Bs[NXT], tid, rb[NXT]);                                \
+        }                                                                                                 \
+        __syncthreads();                                                                                  \
+    }
+        for (int kt = 0; kt < nkt; kt += 2) {
+            NEGF_GEMM_STEP(kt, 0, 1)
+            if (kt + 1 < nkt) NEGF_GEMM_STEP(kt + 1, 1, 0)
+        }
+#undef NEGF_GEMM_STEP
     }
 
     TC* __restrict__ C = (TC*)g.C + q * g.sC;
@@ -84,17 +138,17 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = rowbase + mi * 16 + out_row<Acc>(lane, r);
-                if (row < n && col < n) {
+                if (row < n && col < n && !(AH && m0 == n0 && row < col)) {
                     const long long idx = (long long)row * n + col;
                     double vr = (double)cr[mi][nj][r], vi = (double)ci[mi][nj][r];
                     TC out;
-                    if (EPI == EPI_STORE) {
+                    if (EPI == EPI_STORE || EPI == EPI_STORE_AH) {
                         out.x = vr; out.y = vi; C[idx] = out;
                     } else if (EPI == EPI_ADD || EPI == EPI_SUB) {
                         TC d = D[idx];
                         double s = (EPI == EPI_ADD) ? 1.0 : -1.0;
                         out.x = (double)d.x + s * vr; out.y = (double)d.y + s * vi; C[idx] = out;
-                    } else if (EPI == EPI_ADD_TTD) {
+                    } else if (EPI == EPI_ADD_TTD || EPI == EPI_ADD_TTD_AH) {
                         TC d = D[idx], t1 = T[idx], t2 = T[(long long)col * n + row];
                         out.x = (double)d.x + vr + (double)t1.x - (double)t2.x;
                         out.y = (double)d.y + vi + (double)t1.y + (double)t2.y;
@@ -106,6 +160,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
                     } else if (EPI == EPI_IMINUS) {
                         out.x = (row == col ? 1.0 : 0.0) - vr; out.y = -vi; C[idx] = out;
                     }
+                    if (AH && row != col) {
+                        TC m; m.x = -out.x; m.y = out.y;
+                        C[(long long)col * n + row] = m;
+                    }
                 }
             }
         }
@@ -115,8 +173,15 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
 template <typename TA, typename TB, typename TC, typename Acc, int OPA, int OPB>
 static hipError_t launch_epi(hipStream_t s, int epi, const GemmArgs& g, dim3 grid) {
     switch (epi) {
-#define NEGF_EPI(E) case E: hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, Acc, OPA, OPB, E>), grid, dim3(256), 0, s, g); break;
+#define NEGF_EPI(E)                                                                                       \
+    case E:                                                                                               \
+        if (g.pf != 1)                                                                                    \
+            hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, Acc, OPA, OPB, E, 2>), grid, dim3(256), 0, s, g); \
+        else                                                                                              \
+            hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, Acc, OPA, OPB, E, 1>), grid, dim3(256), 0, s, g); \
+        break;
         NEGF_EPI(EPI_STORE) NEGF_EPI(EPI_ADD) NEGF_EPI(EPI_ADD_TTD) NEGF_EPI(EPI_DUAL) NEGF_EPI(EPI_IMINUS) NEGF_EPI(EPI_SUB)
+        NEGF_EPI(EPI_STORE_AH) NEGF_EPI(EPI_ADD_TTD_AH)
 #undef NEGF_EPI
         default: return hipErrorInvalidValue;
     }
@@ -133,8 +198,7 @@ static hipError_t launch_ops(hipStream_t s, int opa, int opb, int epi, const Gem
 
 hipError_t gemm_launch(hipStream_t s, GemmTypes ty, int opa, int opb, int epi, const GemmArgs& g) {
     if (g.np <= 0 || g.n <= 0) return hipSuccess;
-    const int tiles = (g.n + BM - 1) / BM;
-    dim3 grid((unsigned)((long long)g.np * tiles * tiles));
+    dim3 grid((unsigned)((long long)g.np * gemm_tiles(g.n, epi)));
     if (ty.ta == DT_C128 && ty.tb == DT_C128 && ty.tc == DT_C128 && ty.acc == DT_C128)
         return launch_ops<double2, double2, double2, double>(s, opa, opb, epi, g, grid);
     if (ty.ta == DT_C64 && ty.tb == DT_C64 && ty.tc == DT_C64 && ty.acc == DT_C64)
@@ -142,14 +206,14 @@ hipError_t gemm_launch(hipStream_t s, GemmTypes ty, int opa, int opb, int epi, c
     // Mixed-precision refinement: FP64 residual R = I - A X0 with X0 in FP32.
     if (ty.ta == DT_C128 && ty.tb == DT_C64 && ty.tc == DT_C128 && ty.acc == DT_C128 &&
         opa == OP_N && opb == OP_N && epi == EPI_IMINUS) {
-        hipLaunchKernelGGL((gemm_kernel<double2, float2, double2, double, OP_N, OP_N, EPI_IMINUS>),
+        hipLaunchKernelGGL((gemm_kernel<double2, float2, double2, double, OP_N, OP_N, EPI_IMINUS, 2>),
                            grid, dim3(256), 0, s, g);
         return hipGetLastError();
     }
     // Mixed-precision correction X1 = X0 + X0 R in FP32 with R read in FP64.
     if (ty.ta == DT_C64 && ty.tb == DT_C128 && ty.tc == DT_C64 && ty.acc == DT_C64 &&
         opa == OP_N && opb == OP_N && epi == EPI_ADD) {
-        hipLaunchKernelGGL((gemm_kernel<float2, double2, float2, float, OP_N, OP_N, EPI_ADD>),
+        hipLaunchKernelGGL((gemm_kernel<float2, double2, float2, float, OP_N, OP_N, EPI_ADD, 2>),
                            grid, dim3(256), 0, s, g);
         return hipGetLastError();
     }

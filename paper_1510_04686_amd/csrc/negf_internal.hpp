@@ -13,6 +13,11 @@ enum Epi : int {
     EPI_DUAL = 3,      // C += op(A) op(B);  C2 += op(A) op(B)
     EPI_IMINUS = 4,    // C = I - op(A) op(B)
     EPI_SUB = 5,       // C = D - op(A) op(B)
+    // Anti-Hermitian results: only the tiles on and below the diagonal are
+    // computed; each element below the diagonal is also written, as -conj, to
+    // its mirror above it.
+    EPI_STORE_AH = 6,    // C = op(A) op(B)
+    EPI_ADD_TTD_AH = 7,  // C = D + op(A) op(B) + T - T^dagger
 };
 enum Dt : int { DT_C128 = 0, DT_C64 = 1 };
 
@@ -28,12 +33,20 @@ struct GemmArgs {
     int n;
     int np;
     Active act;
+    int pf;              // K slices in flight: 1 or 2 (0: 2)
 };
 
 struct GemmTypes {
     int ta, tb, tc;   // Dt of A, B and of C/D/T/C2
     int acc;          // DT_C128: FP64 MFMA, DT_C64: FP32 MFMA
 };
+
+// Output tiles a launch computes per point (BM-wide tiles; the anti-Hermitian
+// epilogues cover the lower triangle of tiles only).
+inline long long gemm_tiles(int n, int epi) {
+    const long long t = (n + 63) / 64;
+    return (epi == EPI_STORE_AH || epi == EPI_ADD_TTD_AH) ? t * (t + 1) / 2 : t * t;
+}
 
 // Launches C = op(A) op(B) (+ epilogue).  Returns hipError_t.
 hipError_t gemm_launch(hipStream_t s, GemmTypes ty, int opa, int opb, int epi, const GemmArgs& g);
@@ -47,13 +60,14 @@ struct InvWork {
     int* piv;            // [np][n]
     int* coldst;         // [np][n]
     int* status;
-    void* N0; void* N1;  // narrow ping-pong copies of an outer panel, [np][n][INV_W] each (NULL: one level)
+    void* N0; void* N1;  // narrow ping-pong copies of an outer panel, [np][n][INV_WMAX] each (NULL: one level)
     int* comp;           // [np][n] composite row source of an outer panel
+    int W;               // outer panel width (a multiple of 32, <= INV_WMAX), 0: one level
 };
 // dst = src^-1 for every active point (Gauss-Jordan, partial pivoting).  src
 // is destroyed.  dt = DT_C128 or DT_C64 (matrix and arithmetic type).
 constexpr int INV_NMAX = 2048;   // largest block the inverse handles
-constexpr int INV_W = 128;       // outer panel width of the two-level inverse
+constexpr int INV_WMAX = 256;    // widest outer panel of the two-level inverse
 hipError_t inverse_init();
 hipError_t inverse_launch(hipStream_t s, int dt, void* src, long long s_src, void* dst, long long s_dst,
                           int n, int np, const Active& act, const InvWork& w);

@@ -19,21 +19,20 @@
 // After the last panel the column permutation of the recorded row swaps is
 // applied while writing the result, giving A^-1 = X P.
 //
-// Blocks wider than INV_W columns use two levels: inside an outer panel of
-// INV_W columns the inner steps update only that panel (a narrow n x INV_W
-// copy, ping-pong), and the rest of the matrix receives the composite
-// transform of the outer panel in one rank-INV_W update.  Because Gauss-Jordan
+// Blocks wider than the outer panel width W (a tuning choice, a multiple of
+// 32) use two levels: inside an outer panel of W columns the inner steps
+// update only that panel (a narrow n x W copy), and the rest of the matrix
+// receives the composite transform of the outer panel in one rank-W update.  Because Gauss-Jordan
 // transforms a column using only that column and the panel's transform, the
 // outer panel's columns evolve exactly as in the one-level scheme; the other
 // columns receive the same composite transform in one pass instead of
-// INV_W / nbk passes, which cuts the full-matrix HBM sweeps by that factor.
+// W / nbk passes, which cuts the full-matrix HBM sweeps by that factor.
 #include "negf_internal.hpp"
 #include "negf_mfma.hpp"
 
 namespace negf {
 
 constexpr int NBMAX = 32;          // widest panel (E / pivot-row buffers are sized for it)
-static_assert(INV_W % 32 == 0 && INV_W % 16 == 0, "outer panel width must be a multiple of every panel width");
 
 struct PanelArgs {
     const void* X; long long sX;   // current matrix: global columns [xcol0, ..) with row stride ldX
@@ -165,30 +164,61 @@ __global__ __launch_bounds__(NT) void gj_panel(PanelArgs a) {
 #pragma unroll
                 for (int jj = 1; jj < NB; ++jj) rowP[jj] = v[t][jj];
                 const C p = v[t][0];
-                const R dd = p.x * p.x + p.y * p.y;
-                C inv; inv.x = p.x / dd; inv.y = -p.y / dd;
+                const R rd = (R)1 / (p.x * p.x + p.y * p.y);
+                C inv; inv.x = p.x * rd; inv.y = -p.y * rd;
                 sh_inv = inv;
             }
         }
         __syncthreads();                                           // B2
         const C inv = sh_inv;
+        C g[RPT];
+        bool isp[RPT];
 #pragma unroll
         for (int t = 0; t < RPT; ++t) {
-            const bool isp = pos[t] == pv;
+            isp[t] = pos[t] == pv;
             C f = v[t][0];
-            f.x -= isp ? (R)1 : (R)0;
-            const C g = cmul(f, inv);
+            f.x -= isp[t] ? (R)1 : (R)0;
+            g[t] = cmul(f, inv);
+        }
+        // v[jj - 1] = v[jj] - g w[jj] for jj = 1 .. NB-1, the pivot row read from LDS
+        // in groups of 8 with the next group's reads in flight (LDS latency, not
+        // the arithmetic, bounds this loop otherwise)
+        constexpr int GW = 8;
+        constexpr int NG = (NB - 1 + GW - 1) / GW;
+        C wb[2][GW];
 #pragma unroll
-            for (int jj = 1; jj < NB; ++jj) {
-                const C w = rowP[jj];
-                C o;
-                o.x = v[t][jj].x - (g.x * w.x - g.y * w.y);
-                o.y = v[t][jj].y - (g.x * w.y + g.y * w.x);
-                v[t][jj - 1] = o;
+        for (int u = 0; u < GW; ++u) if (1 + u < NB) wb[0][u] = rowP[1 + u];
+#pragma unroll
+        for (int gi = 0; gi < NG; ++gi) {
+            if (gi + 1 < NG) {
+#pragma unroll
+                for (int u = 0; u < GW; ++u) {
+                    const int jj = 1 + (gi + 1) * GW + u;
+                    if (jj < NB) wb[(gi + 1) & 1][u] = rowP[jj];
+                }
             }
-            C e; e.x = -g.x + (isp ? (R)1 : (R)0); e.y = -g.y;
+#pragma unroll
+            for (int u = 0; u < GW; ++u) {
+                const int jj = 1 + gi * GW + u;
+                if (jj < NB) {
+                    const C w = wb[gi & 1][u];
+#pragma unroll
+                    for (int t = 0; t < RPT; ++t) {
+                        C o;
+                        o.x = fma(-g[t].x, w.x, v[t][jj].x);
+                        o.x = fma(g[t].y, w.y, o.x);
+                        o.y = fma(-g[t].x, w.y, v[t][jj].y);
+                        o.y = fma(-g[t].y, w.x, o.y);
+                        v[t][jj - 1] = o;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < RPT; ++t) {
+            C e; e.x = -g[t].x + (isp[t] ? (R)1 : (R)0); e.y = -g[t].y;
             v[t][NB - 1] = e;
-            pos[t] = isp ? c : (pos[t] == c ? pv : pos[t]);
+            pos[t] = isp[t] ? c : (pos[t] == c ? pv : pos[t]);
         }
     }
 
@@ -225,22 +255,38 @@ __global__ __launch_bounds__(NT) void gj_panel(PanelArgs a) {
 #pragma unroll
             for (int jj = 0; jj < NB; ++jj) v[0][jj].x -= (p == k0 + jj) ? (R)1 : (R)0;
         }
+        // Chunks of CW columns, skipping the panel itself; the next chunk's global reads
+        // are issued before the current chunk's arithmetic.
         const int cend = a.uc0 + a.unc;
-        for (int cc = a.uc0; cc < cend; cc += CW) {
-            if (cc >= k0 && cc + CW <= k0 + NB) continue;          // the panel itself
-            __syncthreads();                                        // Pch reuse
-            for (int idx = tid; idx < NB * CW; idx += NT) {
-                const int jr = idx / CW, c2 = idx - jr * CW, col = cc + c2;
-                C val; val.x = 0; val.y = 0;
-                if (col < cend) val = X[(long long)rsrc[k0 + jr] * a.ldX + (col - a.xcol0)];
-                Pch[jr][c2] = val;
-            }
-            C acc[CW];
+        auto next_chunk = [&](int cc) {
+            cc += CW;
+            if (cc >= k0 && cc < k0 + NB) cc = k0 + NB;
+            return cc;
+        };
+        int cc = a.uc0;
+        if (cc >= k0 && cc < k0 + NB) cc = k0 + NB;
+        const int prow = tid / CW, pc2 = tid - (tid / CW) * CW;   // this thread's element of the pivot tile
+        const bool pown = tid < NB * CW;
+        C pv_n, xa_n[CW];
+        auto fetch = [&](int c0) {
+            pv_n.x = 0; pv_n.y = 0;
+            if (pown && c0 + pc2 < cend) pv_n = X[(long long)rsrc[k0 + prow] * a.ldX + (c0 + pc2 - a.xcol0)];
 #pragma unroll
             for (int c2 = 0; c2 < CW; ++c2) {
-                acc[c2].x = 0; acc[c2].y = 0;
-                if (r < n && cc + c2 < cend) acc[c2] = X[(long long)rsrc[p] * a.ldX + (cc + c2 - a.xcol0)];
+                xa_n[c2].x = 0; xa_n[c2].y = 0;
+                if (r < n && c0 + c2 < cend) xa_n[c2] = X[(long long)rsrc[p] * a.ldX + (c0 + c2 - a.xcol0)];
             }
+        };
+        static_assert(NB * CW <= NT, "one pivot-tile element per thread");
+        if (cc < cend) fetch(cc);
+        while (cc < cend) {
+            __syncthreads();                                        // Pch reuse
+            if (pown) Pch[prow][pc2] = pv_n;
+            C acc[CW];
+#pragma unroll
+            for (int c2 = 0; c2 < CW; ++c2) acc[c2] = xa_n[c2];
+            const int cn = next_chunk(cc);
+            if (cn < cend) fetch(cn);
             __syncthreads();                                        // every read of the chunk is done
 #pragma unroll
             for (int jj = 0; jj < NB; ++jj) {
@@ -260,12 +306,10 @@ __global__ __launch_bounds__(NT) void gj_panel(PanelArgs a) {
             }
             if (r < n) {
 #pragma unroll
-                for (int c2 = 0; c2 < CW; ++c2) {
-                    const int col = cc + c2;
-                    if (col < cend && (col < k0 || col >= k0 + NB))
-                        Y[(long long)p * a.ldY + (col - a.ycol0)] = acc[c2];
-                }
+                for (int c2 = 0; c2 < CW; ++c2)
+                    if (cc + c2 < cend) Y[(long long)p * a.ldY + (cc + c2 - a.ycol0)] = acc[c2];
             }
+            cc = cn;
         }
     } else {
         // The transform columns sit in registers NB-nbk .. NB-1.
@@ -325,7 +369,7 @@ struct UpdArgs {
 template <typename R>
 __global__ __launch_bounds__(256) void gj_update(UpdArgs a) {
     typedef cplx<R> C;
-    __shared__ R Es[2][2][BK][LP];   // [K slice][re/im][k][m]
+    __shared__ R Es[2][2][BK][LP];   // [buffer][re/im][k][m]
     __shared__ R Ps[2][2][BK][LP];
     const int n = a.n;
     const int tm = (n + BM - 1) / BM, tn = (a.nc + BM - 1) / BM;
@@ -349,7 +393,65 @@ __global__ __launch_bounds__(256) void gj_update(UpdArgs a) {
     const int* rs = a.rowsrc + (long long)q * n;
     const int ldX = a.ldX, xc = a.xcol0;
 
-    // Issue the gathered reads of the old matrix first: they do not depend on the product.
+    typename MF<R>::V cr[2][2], ci[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) { cr[x][y][r] = 0; ci[x][y][r] = 0; }
+    // K slices double-buffered through LDS, the next slice's reads in flight during
+    // the current slice's products.  E tile: rows m0.., k (pattern X); pivot-row
+    // tile: k rows, cols n0.. (pattern Y).
+    const int eo = tid >> 2, ek = (tid & 3) * 4, erow = m0 + eo;
+    const int pk = tid >> 4, poc = (tid & 15) * 4;
+    C re[4], rp[4];
+    auto load = [&](int s) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int kk = s * BK + ek + j;
+            re[j].x = 0; re[j].y = 0;
+            if (erow < n && kk < nbk) {
+                re[j] = E[(long long)erow * a.ldE + kk];
+                if (erow == k0 + kk) re[j].x -= (R)1;
+            }
+        }
+        const int kk = s * BK + pk;
+        const C* prow = nullptr;
+        if (kk < nbk) prow = Pr ? Pr + (long long)kk * a.ldP - a.pc0 : X + (long long)rs[k0 + kk] * ldX - xc;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int col = n0 + poc + j;
+            rp[j].x = 0; rp[j].y = 0;
+            if (prow && col < cend) rp[j] = prow[col];
+        }
+    };
+    auto store = [&](int b) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            Es[b][0][ek + j][eo] = re[j].x;
+            Es[b][1][ek + j][eo] = re[j].y;
+            Ps[b][0][pk][poc + j] = rp[j].x;
+            Ps[b][1][pk][poc + j] = rp[j].y;
+        }
+    };
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int s = 0; s < nsl; ++s) {
+        const int b = s & 1;
+        const bool more = s + 1 < nsl;
+        if (more) load(s + 1);
+        if (nmi == 2 && nnj == 2) mma_slice<R, 2, 2>(Es[b], Ps[b], lane, wm, wn, cr, ci);
+        else if (nmi == 2 && nnj == 1) mma_slice<R, 2, 1>(Es[b], Ps[b], lane, wm, wn, cr, ci);
+        else if (nmi == 1 && nnj == 2) mma_slice<R, 1, 2>(Es[b], Ps[b], lane, wm, wn, cr, ci);
+        else if (nmi == 1 && nnj == 1) mma_slice<R, 1, 1>(Es[b], Ps[b], lane, wm, wn, cr, ci);
+        if (more) store(b ^ 1);
+        __syncthreads();
+    }
+
+    // Gathered rows of the old matrix (read after the products: holding them through the
+    // K loop would halve the wavefronts per SIMD).
     C xo[2][2][4];
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
@@ -368,53 +470,6 @@ __global__ __launch_bounds__(256) void gj_update(UpdArgs a) {
                 }
             }
         }
-    typename MF<R>::V cr[2][2], ci[2][2];
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) { cr[x][y][r] = 0; ci[x][y][r] = 0; }
-    for (int s0 = 0; s0 < nsl; s0 += 2) {
-        if (s0) __syncthreads();
-        // E tile: rows m0.., k (pattern X); pivot-row tile: k rows, cols n0.. (pattern Y)
-        for (int s = s0; s < nsl && s < s0 + 2; ++s) {
-            const int b = s - s0;
-            int o = tid >> 2, k = (tid & 3) * 4, row = m0 + o;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int kk = s * BK + k + j;
-                C v; v.x = 0; v.y = 0;
-                if (row < n && kk < nbk) {
-                    v = E[(long long)row * a.ldE + kk];
-                    if (row == k0 + kk) v.x -= (R)1;
-                }
-                Es[b][0][k + j][o] = v.x;
-                Es[b][1][k + j][o] = v.y;
-            }
-            int kr = tid >> 4, oc = (tid & 15) * 4;
-            const int kk = s * BK + kr;
-            const C* prow = nullptr;
-            if (kk < nbk) prow = Pr ? Pr + (long long)kk * a.ldP - a.pc0 : X + (long long)rs[k0 + kk] * ldX - xc;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                C v; v.x = 0; v.y = 0;
-                int col = n0 + oc + j;
-                if (prow && col < cend) v = prow[col];
-                Ps[b][0][kr][oc + j] = v.x;
-                Ps[b][1][kr][oc + j] = v.y;
-            }
-        }
-        __syncthreads();
-        for (int s = s0; s < nsl && s < s0 + 2; ++s) {
-            const int b = s - s0;
-            if (nmi == 2 && nnj == 2) mma_slice<R, 2, 2>(Es[b], Ps[b], lane, wm, wn, cr, ci);
-            else if (nmi == 2 && nnj == 1) mma_slice<R, 2, 1>(Es[b], Ps[b], lane, wm, wn, cr, ci);
-            else if (nmi == 1 && nnj == 2) mma_slice<R, 1, 2>(Es[b], Ps[b], lane, wm, wn, cr, ci);
-            else if (nmi == 1 && nnj == 1) mma_slice<R, 1, 1>(Es[b], Ps[b], lane, wm, wn, cr, ci);
-        }
-    }
-
     C* Y = reinterpret_cast<C*>(a.Y) + q * a.sY;
     const int* cd = a.coldst + (long long)q * n;
 #pragma unroll
@@ -502,7 +557,7 @@ static hipError_t inverse_typed(hipStream_t s, void* src, long long s_src, void*
     void* cur = src;
     void* other = w.pa;
     long long s_cur = s_src, s_other = nn;
-    const bool two = n > INV_W && w.N0 && w.N1 && w.comp;
+    const bool two = w.W > 0 && w.W % 32 == 0 && w.W <= INV_WMAX && n > w.W && w.N0 && w.N1 && w.comp;
     if (!two) {
         for (int k0 = 0; k0 < n; k0 += ps.nb) {
             const int nbk = (n - k0 < ps.nb) ? (n - k0) : ps.nb;
@@ -521,8 +576,8 @@ static hipError_t inverse_typed(hipStream_t s, void* src, long long s_src, void*
         }
         return hipSuccess;
     }
-    for (int K0 = 0; K0 < n; K0 += INV_W) {
-        const int W = (n - K0 < INV_W) ? (n - K0) : INV_W;
+    for (int K0 = 0; K0 < n; K0 += w.W) {
+        const int W = (n - K0 < w.W) ? (n - K0) : w.W;
         const int lastK = (K0 + W == n);
         const long long sN = (long long)n * W;
         // inner steps: the outer panel's columns, full matrix -> narrow copy.  A full-width

@@ -20,6 +20,50 @@ __device__ inline double fermi_d(double E, double mu, double kT) {
 // base (mode 2, lesser):    diag(Sigma^<_scat) + 2 i eta f_L I (if filled)
 //                           - f_L (Sigma_L - Sigma_L^dagger)(i=0) - f_R (Sigma_R - Sigma_R^dagger)(i=N-1)
 // ---------------------------------------------------------------------------
+// Adds the mode's base term to element (gr, gc) of the assembled block.
+__device__ inline void sandwich_base(const SandArgs& a, double2& z, int gr, int gc, int ik, int ie, int ns,
+                                     long long gslab, double E) {
+    const int n = a.n;
+    if (a.mode == 1) {
+        const double2* H = a.hdiag + ik * a.hdiag_k + gslab * (long long)n * n;
+        double2 h = H[(long long)gr * n + gc];
+        z.x -= h.x; z.y -= h.y;
+        if (gr == gc) {
+            z.x += E; z.y += a.eta;
+            if (a.v) z.x -= a.v[gslab * n + gr];
+            if (a.scat) { double2 s = a.scat[((long long)ie * a.total + gslab) * n + gr]; z.x -= s.x; z.y -= s.y; }
+        }
+        const long long lo = ((long long)ik * a.n_e + ie) * n * n;
+        if (a.slab == 0) { double2 s = a.sigL[lo + (long long)gr * n + gc]; z.x -= s.x; z.y -= s.y; }
+        if (a.slab == ns - 1) { double2 s = a.sigR[lo + (long long)gr * n + gc]; z.x -= s.x; z.y -= s.y; }
+    } else if (a.mode == 3) {
+        // adjoint source: the cotangent weights W_i on the diagonal
+        if (gr == gc) z.x += a.wdiag[gslab * n + gr];
+    } else if (a.mode == 2) {
+        // lesser_ref: subtract the equilibrium source at the right-lead
+        // occupation, i f_R (Gamma_L + Gamma_R + Gamma_scat + 2 eta); the
+        // remaining source drives only the non-equilibrium part of G^<.
+        const double fR = a.lesser_ref ? fermi_d(E, a.muR, a.kT) : 0.0;
+        if (gr == gc) {
+            if (a.scat) { double2 s = a.scat[((long long)ie * a.total + gslab) * n + gr]; z.x += s.x; z.y += s.y; }
+            if (a.lesser_ref && a.scat2) z.y += 2.0 * fR * a.scat2[((long long)ie * a.total + gslab) * n + gr].y;
+            if (a.eta_fill) z.y += 2.0 * a.eta * fermi_d(E, a.muL, a.kT);
+            z.y -= 2.0 * a.eta * fR;
+        }
+        const long long lo = ((long long)ik * a.n_e + ie) * n * n;
+        if (a.slab == 0) {
+            double f = fermi_d(E, a.muL, a.kT) - fR;
+            double2 s1 = a.sigL[lo + (long long)gr * n + gc], s2 = a.sigL[lo + (long long)gc * n + gr];
+            z.x -= f * (s1.x - s2.x); z.y -= f * (s1.y + s2.y);
+        }
+        if (a.slab == ns - 1) {
+            double f = fermi_d(E, a.muR, a.kT) - fR;
+            double2 s1 = a.sigR[lo + (long long)gr * n + gc], s2 = a.sigR[lo + (long long)gc * n + gr];
+            z.x -= f * (s1.x - s2.x); z.y -= f * (s1.y + s2.y);
+        }
+    }
+}
+
 template <typename TX, typename TO>
 __global__ __launch_bounds__(256) void sandwich_kernel(SandArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -96,45 +140,85 @@ __global__ __launch_bounds__(256) void sandwich_kernel(SandArgs a) {
             }
             z.x *= a.sign; z.y *= a.sign;
         }
-        if (a.mode == 1) {
-            const double2* H = a.hdiag + ik * a.hdiag_k + gslab * (long long)n * n;
-            double2 h = H[(long long)gr * n + gc];
-            z.x -= h.x; z.y -= h.y;
-            if (gr == gc) {
-                z.x += E; z.y += a.eta;
-                if (a.v) z.x -= a.v[gslab * n + gr];
-                if (a.scat) { double2 s = a.scat[((long long)ie * a.total + gslab) * n + gr]; z.x -= s.x; z.y -= s.y; }
-            }
-            const long long lo = ((long long)ik * a.n_e + ie) * n * n;
-            if (a.slab == 0) { double2 s = a.sigL[lo + (long long)gr * n + gc]; z.x -= s.x; z.y -= s.y; }
-            if (a.slab == ns - 1) { double2 s = a.sigR[lo + (long long)gr * n + gc]; z.x -= s.x; z.y -= s.y; }
-        } else if (a.mode == 3) {
-            // adjoint source: the cotangent weights W_i on the diagonal
-            if (gr == gc) z.x += a.wdiag[gslab * n + gr];
-        } else if (a.mode == 2) {
-            // lesser_ref: subtract the equilibrium source at the right-lead
-            // occupation, i f_R (Gamma_L + Gamma_R + Gamma_scat + 2 eta); the
-            // remaining source drives only the non-equilibrium part of G^<.
-            const double fR = a.lesser_ref ? fermi_d(E, a.muR, a.kT) : 0.0;
-            if (gr == gc) {
-                if (a.scat) { double2 s = a.scat[((long long)ie * a.total + gslab) * n + gr]; z.x += s.x; z.y += s.y; }
-                if (a.lesser_ref && a.scat2) z.y += 2.0 * fR * a.scat2[((long long)ie * a.total + gslab) * n + gr].y;
-                if (a.eta_fill) z.y += 2.0 * a.eta * fermi_d(E, a.muL, a.kT);
-                z.y -= 2.0 * a.eta * fR;
-            }
-            const long long lo = ((long long)ik * a.n_e + ie) * n * n;
-            if (a.slab == 0) {
-                double f = fermi_d(E, a.muL, a.kT) - fR;
-                double2 s1 = a.sigL[lo + (long long)gr * n + gc], s2 = a.sigL[lo + (long long)gc * n + gr];
-                z.x -= f * (s1.x - s2.x); z.y -= f * (s1.y + s2.y);
-            }
-            if (a.slab == ns - 1) {
-                double f = fermi_d(E, a.muR, a.kT) - fR;
-                double2 s1 = a.sigR[lo + (long long)gr * n + gc], s2 = a.sigR[lo + (long long)gc * n + gr];
-                z.x -= f * (s1.x - s2.x); z.y -= f * (s1.y + s2.y);
-            }
-        }
+        sandwich_base(a, z, gr, gc, ik, ie, ns, gslab, E);
         O[(long long)gr * n + gc] = cconv<TO>(z);
+    }
+}
+
+// The same operation without LDS, for ub <= 16: one thread per (block row of
+// ub rows, column c).  It forms Y = X opR(U) for its ub rows at column c (ub^2
+// reads of X shared, through L1, by the ub threads of a column block), then
+// O = opL(U) Y in registers and writes ub coalesced outputs.
+template <typename TX, typename TO, int UBM>
+__global__ __launch_bounds__(256) void sandwich_cols_kernel(SandArgs a) {
+    const int n = a.n, ub = a.ub;
+    const int nblk = n / ub;
+    const long long work = (long long)nblk * n, per = (work + 255) / 256;
+    const int q = (int)(blockIdx.x / per);
+    if (q >= a.np || !a.act(q)) return;
+    const long long idx = (blockIdx.x - (long long)q * per) * 256 + threadIdx.x;
+    if (idx >= work) return;
+    const int blk = (int)(idx / n), c = (int)(idx - (long long)blk * n);
+    const int rb = blk * ub, cb = (c / ub) * ub;
+    const int4 d = a.ps.desc[a.ps.p0 + q];
+    const int ik = d.y, ie = d.z, ns = d.w;
+    const long long sfirst = a.ps.slab_off[d.x];
+    double2 y[UBM];
+#pragma unroll
+    for (int i = 0; i < UBM; ++i) y[i] = make_double2(0, 0);
+    if (a.X) {
+        const TX* X = reinterpret_cast<const TX*>(a.X) + q * a.sX;
+        const double2* U = a.hup + ik * a.hup_k + (sfirst + a.uslab) * (long long)n * n;
+        if (a.opR) {
+            double2 uc[UBM];   // opR(U)[cb + j][c]
+#pragma unroll
+            for (int j = 0; j < UBM; ++j)
+                if (j < ub) uc[j] = (a.opR == 1) ? U[(long long)(cb + j) * n + c] : cconj(U[(long long)c * n + cb + j]);
+#pragma unroll
+            for (int i = 0; i < UBM; ++i) {
+                if (i < ub) {
+                    const TX* xr = X + (long long)(rb + i) * n + cb;
+#pragma unroll
+                    for (int j = 0; j < UBM; ++j)
+                        if (j < ub) cfma(y[i], cconv<double2>(xr[j]), uc[j]);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < UBM; ++i)
+                if (i < ub) y[i] = cconv<double2>(X[(long long)(rb + i) * n + c]);
+        }
+        if (a.opL) {
+            double2 z[UBM];
+#pragma unroll
+            for (int i = 0; i < UBM; ++i) {
+                z[i] = make_double2(0, 0);
+                if (i < ub) {
+#pragma unroll
+                    for (int k = 0; k < UBM; ++k) {
+                        if (k < ub) {
+                            const double2 u = (a.opL == 1) ? U[(long long)(rb + i) * n + rb + k]
+                                                           : cconj(U[(long long)(rb + k) * n + rb + i]);
+                            cfma(z[i], u, y[k]);
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < UBM; ++i) y[i] = z[i];
+        }
+    }
+    TO* O = reinterpret_cast<TO*>(a.O) + q * a.sO;
+    const long long gslab = sfirst + a.slab;
+    const double E = a.energy ? a.energy[ie] : 0.0;
+#pragma unroll
+    for (int i = 0; i < UBM; ++i) {
+        if (i < ub) {
+            double2 z = y[i];
+            z.x *= a.sign; z.y *= a.sign;
+            sandwich_base(a, z, rb + i, c, ik, ie, ns, gslab, E);
+            O[(long long)(rb + i) * n + c] = cconv<TO>(z);
+        }
     }
 }
 
@@ -154,8 +238,26 @@ hipError_t sandwich_init() {
     return hipSuccess;
 }
 
+template <typename TX, typename TO>
+static bool sandwich_cols_launch(hipStream_t s, const SandArgs& a) {
+    if (a.ub > 16) return false;
+    const long long work = (long long)(a.n / a.ub) * a.n;
+    dim3 grid((unsigned)((long long)a.np * ((work + 255) / 256)));
+    if (a.ub <= 4) hipLaunchKernelGGL((sandwich_cols_kernel<TX, TO, 4>), grid, dim3(256), 0, s, a);
+    else if (a.ub <= 8) hipLaunchKernelGGL((sandwich_cols_kernel<TX, TO, 8>), grid, dim3(256), 0, s, a);
+    else if (a.ub <= 12) hipLaunchKernelGGL((sandwich_cols_kernel<TX, TO, 12>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((sandwich_cols_kernel<TX, TO, 16>), grid, dim3(256), 0, s, a);
+    return true;
+}
+
 hipError_t sandwich_launch(hipStream_t s, int xdt, int odt, const SandArgs& a) {
     if (a.np <= 0) return hipSuccess;
+    bool done;
+    if (xdt == DT_C128 && odt == DT_C128) done = sandwich_cols_launch<double2, double2>(s, a);
+    else if (xdt == DT_C64 && odt == DT_C128) done = sandwich_cols_launch<float2, double2>(s, a);
+    else if (xdt == DT_C128 && odt == DT_C64) done = sandwich_cols_launch<double2, float2>(s, a);
+    else done = sandwich_cols_launch<float2, float2>(s, a);
+    if (done) return hipGetLastError();
     const int tiles = (a.n + a.tile - 1) / a.tile;
     dim3 grid((unsigned)((long long)a.np * tiles * tiles));
     size_t lds = sandwich_lds(a.ub);
@@ -260,16 +362,75 @@ hipError_t extract_launch(hipStream_t s, int dt, const ExtArgs& a) {
 // ---------------------------------------------------------------------------
 // Bond current  j_i = 2 Re Tr[H_{i,i+1} G^<_{i+1,i}]  with
 //   G^<_{i+1,i} = G_{i+1} H_{i+1,i} g^<_i + G^<_{i+1} L^dagger,  L = g_i H_{i,i+1},
-// so  j_i = 2 Re[ sum_ab (U G)_ab Q_ba + sum_ab (U G^<)_ab conj(L_ab) ],
-// U = H_{i,i+1} (block-diagonal), Q = U^dagger g^<_i.  Each of NW workgroups
-// per point reduces a row range to a partial (fixed order); a second kernel
-// adds the partials in order.
+// U = H_{i,i+1} (block-diagonal with ub x ub blocks):
+//   j_i = 2 Re[ Tr(U G U^dagger g^<_i) + sum_ab (U G^<)_ab conj(L_ab) ].
+// g^<_i is anti-Hermitian, so Tr(U G U^dagger g^<) = -sum_ab (U G)_ab conj((g^< U)_ab):
+// every factor is then read row-major, in the order the threads walk b.
+// One workgroup per (point, group of atom blocks) keeps the ub rows of G and
+// G^< it needs in registers; the partials are added in a fixed order.
 // ---------------------------------------------------------------------------
-constexpr int TRACE_NW = 8;
+template <typename TI, int UBM>
+__global__ __launch_bounds__(256) void bond_rows_kernel(BondArgs a) {
+    const int q = blockIdx.x / BOND_NWB, w = blockIdx.x - q * BOND_NWB;
+    if (q >= a.np || !a.act(q)) return;
+    const int n = a.n, ub = a.ub, tid = threadIdx.x;
+    const int nblk = n / ub;
+    const int4 d = a.ps.desc[a.ps.p0 + q];
+    const long long sfirst = a.ps.slab_off[d.x];
+    const double2* U = a.hup + d.y * a.hup_k + (sfirst + a.slab) * (long long)n * n;
+    const TI* G = reinterpret_cast<const TI*>(a.G) + q * a.sM;
+    const TI* GL = reinterpret_cast<const TI*>(a.GL) + q * a.sM;
+    const TI* L = reinterpret_cast<const TI*>(a.L) + q * a.sM;
+    const TI* GS = reinterpret_cast<const TI*>(a.gls) + q * a.s_gls;
+    double acc = 0.0;
+    for (int A = w; A < nblk; A += BOND_NWB) {
+        const int r0 = A * ub;
+        for (int b = tid; b < n; b += 256) {
+            const int bb = (b / ub) * ub;
+            double2 gc[UBM], glc[UBM], uc[UBM];
+#pragma unroll
+            for (int j = 0; j < UBM; ++j) {
+                if (j < ub) {
+                    gc[j] = cconv<double2>(G[(long long)(r0 + j) * n + b]);
+                    glc[j] = cconv<double2>(GL[(long long)(r0 + j) * n + b]);
+                    uc[j] = U[(long long)(bb + j) * n + b];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < UBM; ++i) {
+                if (i < ub) {
+                    const long long r = r0 + i;
+                    double2 ug = make_double2(0, 0), ugl = make_double2(0, 0), gu = make_double2(0, 0);
+#pragma unroll
+                    for (int j = 0; j < UBM; ++j) {
+                        if (j < ub) {
+                            const double2 u = U[r * n + r0 + j];
+                            cfma(ug, u, gc[j]);
+                            cfma(ugl, u, glc[j]);
+                            cfma(gu, cconv<double2>(GS[r * n + bb + j]), uc[j]);
+                        }
+                    }
+                    const double2 l = cconv<double2>(L[r * n + b]);
+                    acc += (ugl.x * l.x + ugl.y * l.y) - (ug.x * gu.x + ug.y * gu.y);
+                }
+            }
+        }
+    }
+    __shared__ double red[256];
+    red[tid] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o) red[tid] += red[tid + o];
+        __syncthreads();
+    }
+    if (tid == 0) a.partial[(long long)q * BOND_NWB + w] = red[0];
+}
 
+// Blocks wider than the register path: j_i = 2 Re[ sum_ab (U G)_ab Q_ba + (U G^<)_ab conj(L_ab) ]
+// with Q = U^dagger g^<_i, rows split over BOND_NWB workgroups.
 template <typename TI>
 __global__ __launch_bounds__(256) void bond_partial_kernel(BondArgs a) {
-    const int q = blockIdx.x / TRACE_NW, w = blockIdx.x - q * TRACE_NW;
+    const int q = blockIdx.x / BOND_NWB, w = blockIdx.x - q * BOND_NWB;
     if (q >= a.np || !a.act(q)) return;
     const int n = a.n, ub = a.ub, tid = threadIdx.x;
     const int4 d = a.ps.desc[a.ps.p0 + q];
@@ -279,8 +440,8 @@ __global__ __launch_bounds__(256) void bond_partial_kernel(BondArgs a) {
     const TI* GL = reinterpret_cast<const TI*>(a.GL) + q * a.sM;
     const TI* Q = reinterpret_cast<const TI*>(a.Q) + q * a.sM;
     const TI* L = reinterpret_cast<const TI*>(a.L) + q * a.sM;
-    const int rows = (n + TRACE_NW - 1) / TRACE_NW;
-    const int a0 = w * rows, a1 = min(n, a0 + rows);
+    const int rows = (n + BOND_NWB - 1) / BOND_NWB;
+    const int a0 = min(n, w * rows), a1 = min(n, a0 + rows);
     double acc = 0.0;
     for (long long idx = (long long)a0 * n + tid; idx < (long long)a1 * n; idx += 256) {
         const int r = (int)(idx / n), b = (int)(idx - (long long)r * n);
@@ -303,7 +464,7 @@ __global__ __launch_bounds__(256) void bond_partial_kernel(BondArgs a) {
         if (tid < o) red[tid] += red[tid + o];
         __syncthreads();
     }
-    if (tid == 0) a.partial[(long long)q * TRACE_NW + w] = red[0];
+    if (tid == 0) a.partial[(long long)q * BOND_NWB + w] = red[0];
 }
 
 __global__ void bond_final_kernel(const double* partial, double* out, int slab_stride, int slab, int p0, int np,
@@ -311,15 +472,24 @@ __global__ void bond_final_kernel(const double* partial, double* out, int slab_s
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= np || !act(q)) return;
     double s = 0.0;
-    for (int w = 0; w < TRACE_NW; ++w) s += partial[(long long)q * TRACE_NW + w];
+    for (int w = 0; w < BOND_NWB; ++w) s += partial[(long long)q * BOND_NWB + w];
     out[(long long)(p0 + q) * slab_stride + slab] = 2.0 * s;
+}
+
+template <typename TI>
+static void bond_dispatch(hipStream_t s, const BondArgs& a, dim3 grid) {
+    if (a.gls && a.ub <= 4) hipLaunchKernelGGL((bond_rows_kernel<TI, 4>), grid, dim3(256), 0, s, a);
+    else if (a.gls && a.ub <= 8) hipLaunchKernelGGL((bond_rows_kernel<TI, 8>), grid, dim3(256), 0, s, a);
+    else if (a.gls && a.ub <= 12) hipLaunchKernelGGL((bond_rows_kernel<TI, 12>), grid, dim3(256), 0, s, a);
+    else if (a.gls && a.ub <= 16) hipLaunchKernelGGL((bond_rows_kernel<TI, 16>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(bond_partial_kernel<TI>, grid, dim3(256), 0, s, a);
 }
 
 hipError_t bond_launch(hipStream_t s, int dt, const BondArgs& a, double* out, int slab_stride) {
     if (a.np <= 0) return hipSuccess;
-    dim3 grid((unsigned)(a.np * TRACE_NW));
-    if (dt == DT_C128) hipLaunchKernelGGL(bond_partial_kernel<double2>, grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(bond_partial_kernel<float2>, grid, dim3(256), 0, s, a);
+    dim3 grid((unsigned)(a.np * BOND_NWB));
+    if (dt == DT_C128) bond_dispatch<double2>(s, a, grid);
+    else bond_dispatch<float2>(s, a, grid);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(bond_final_kernel, dim3((a.np + 255) / 256), dim3(256), 0, s, a.partial, out, slab_stride,

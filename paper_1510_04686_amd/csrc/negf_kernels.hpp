@@ -41,7 +41,8 @@ struct BondArgs {
     const double2* hup; long long hup_k;
     int ub, slab;
     const void* G; const void* GL; const void* Q; const void* L; long long sM;
-    double* partial;                    // [np][8]
+    const void* gls; long long s_gls;   // g^<_i (anti-Hermitian) per point
+    double* partial;                    // [np][BOND_NWB]
     int n, np;
     Active act;
     PointSet ps;
@@ -79,6 +80,7 @@ struct ObsArgs {
     double* orb_tmp; double* n_out; double* J; double* jE;
 };
 
+constexpr int BOND_NWB = 64;            // partials per point of the bond-current reduction
 int sandwich_tile(int ub);
 size_t sandwich_lds(int ub);
 hipError_t sandwich_init();

@@ -37,6 +37,10 @@ class negf_config(ctypes.Structure):
                 ("adjoint_segment", c_int)]
 
 
+class negf_tuning(ctypes.Structure):
+    _fields_ = [("gemm_prefetch", c_int), ("inv_outer", c_int)]
+
+
 class negf_system(ctypes.Structure):
     _fields_ = [
         ("nb", c_int), ("n_samples", c_int), ("slab_offset", POINTER(c_longlong)),
@@ -52,7 +56,7 @@ EXPORTS = [
     "negf_create", "negf_destroy", "negf_workspace_bytes", "negf_sync_status", "negf_error_string",
     "negf_bind", "negf_lead_selfenergy", "negf_lead_selfenergy_pair", "negf_rgf_forward", "negf_rgf_backward",
     "negf_scba_selfenergy", "negf_observables", "negf_rgf_adjoint", "negf_zgemm_batched", "negf_zinv_batched", "negf_mixed_stats",
-    "negf_gemm_timing_enable", "negf_gemm_timing",
+    "negf_gemm_timing_enable", "negf_gemm_timing", "negf_get_tuning", "negf_set_tuning", "negf_autotune",
 ]
 
 
@@ -84,6 +88,9 @@ def lib():
         "negf_mixed_stats": (i, [vp, vp, POINTER(ll), POINTER(d)]),
         "negf_gemm_timing_enable": (i, [vp, i]),
         "negf_gemm_timing": (i, [vp, vp, POINTER(ll), POINTER(d), POINTER(d)]),
+        "negf_get_tuning": (i, [vp, POINTER(negf_tuning)]),
+        "negf_set_tuning": (i, [vp, POINTER(negf_tuning)]),
+        "negf_autotune": (i, [vp, vp, i, POINTER(negf_tuning)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -282,3 +289,23 @@ def negf_gemm_timing(ctx, stream=None):
     _check("negf_gemm_timing", lib().negf_gemm_timing(ctx.handle, _stream(stream), ctypes.byref(n),
                                                        ctypes.byref(ms), ctypes.byref(fl)))
     return int(n.value), float(ms.value), float(fl.value)
+
+
+def negf_get_tuning(ctx):
+    t = negf_tuning()
+    _check("negf_get_tuning", lib().negf_get_tuning(ctx.handle, ctypes.byref(t)))
+    return {"gemm_prefetch": int(t.gemm_prefetch), "inv_outer": int(t.inv_outer)}
+
+
+def negf_set_tuning(ctx, gemm_prefetch, inv_outer):
+    t = negf_tuning(int(gemm_prefetch), int(inv_outer))
+    _check("negf_set_tuning", lib().negf_set_tuning(ctx.handle, ctypes.byref(t)))
+
+
+def negf_autotune(ctx, reps=3, stream=None):
+    """Times the kernel-shape candidates on the context's workspace, applies the
+    fastest and returns it as a dict."""
+    t = negf_tuning()
+    _check("negf_autotune", lib().negf_autotune(ctx.handle, _stream(stream), int(reps), ctypes.byref(t)))
+    return {"gemm_prefetch": int(t.gemm_prefetch), "inv_outer": int(t.inv_outer)}
+

@@ -8,7 +8,9 @@ allocates device buffers and sequences calls.
 """
 from __future__ import annotations
 
+import json
 import math
+import os
 
 import numpy as np
 import torch
@@ -26,7 +28,11 @@ def _dev(a, dtype, device):
 class RGFSolver:
     """Batched RGF over every (sample, k, E) point of a workload on one GPU."""
 
-    def __init__(self, wl, precision="fp64", capacity=None, device="cuda", mem_fraction=0.6, adjoint_segment=0):
+    def __init__(self, wl, precision="fp64", capacity=None, device="cuda", mem_fraction=0.6, adjoint_segment=0,
+                 tune=None):
+        """tune: None keeps the library's default kernel shapes; "auto" measures
+        them on this context once (negf_autotune) and caches the choice per
+        (device, block, capacity, precision); a dict sets them explicitly."""
         self.wl = wl
         self.device = torch.device(device)
         self.prec = N.NEGF_MIXED if precision == "mixed" else N.NEGF_FP64
@@ -55,16 +61,48 @@ class RGFSolver:
         self.lead_h01_R, self.lead_tau_R = rep(wl.lead_h01_R), rep(wl.lead_tau_R)
         if capacity is None:
             ce = 8 if self.prec == N.NEGF_MIXED else 16
-            per_point = 2 * self.n_slab_max * nb * nb * ce + 24 * nb * nb * 16 + (64 + 256) * nb * 16
+            per_point = 2 * self.n_slab_max * nb * nb * ce + 24 * nb * nb * 16 + (64 + 2 * 256 + 64) * nb * 16
             free, _ = torch.cuda.mem_get_info(self.device)
             capacity = int(max(1, min(self.n_points, 256, (free * mem_fraction) // per_point)))
         self.capacity = int(capacity)
         self.ctx = N.negf_create(nb, self.n_slab_max, self.capacity, self.prec, adjoint_segment)
+        self.tuning = self._tune(tune, precision)
         self._last_fwd = None
         self.eta_fill = 0
         self._bind()
         self.sigma_L = self.sigma_R = None
         self.lead_dual = 0
+
+    def _tune(self, tune, precision):
+        if tune is None:
+            return N.negf_get_tuning(self.ctx)
+        if isinstance(tune, dict):
+            N.negf_set_tuning(self.ctx, tune["gemm_prefetch"], tune["inv_outer"])
+            return N.negf_get_tuning(self.ctx)
+        if tune != "auto":
+            raise ValueError(f"tune must be None, 'auto' or a dict, not {tune!r}")
+        path = os.environ.get("NEGF_TUNING_CACHE",
+                              os.path.join(os.path.expanduser("~"), ".cache", "paper_1510_04686_amd", "tuning.json"))
+        key = f"{torch.cuda.get_device_name(self.device)}|nb={self.wl.nb}|cap={self.capacity}|{precision}"
+        cache = {}
+        try:
+            with open(path) as fh:
+                cache = json.load(fh)
+        except (OSError, ValueError):
+            cache = {}
+        if key in cache:
+            t = cache[key]
+            N.negf_set_tuning(self.ctx, t["gemm_prefetch"], t["inv_outer"])
+            return N.negf_get_tuning(self.ctx)
+        t = N.negf_autotune(self.ctx, reps=3)
+        cache[key] = t
+        try:
+            os.makedirs(os.path.dirname(path), exist_ok=True)
+            with open(path, "w") as fh:
+                json.dump(cache, fh, indent=1, sort_keys=True)
+        except OSError:
+            pass
+        return t
 
     def _bind(self):
         wl = self.wl

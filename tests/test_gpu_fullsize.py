@@ -1,0 +1,100 @@
+"""GPU at the full block and device sizes of the headline workloads, in the
+launch configuration the benchmark times (256-point batches, measured kernel
+shapes): sampled points against the oracle one by one, and properties that
+hold at any size (current conservation with the eta sink, positivity of the
+spectral function and of the occupation, G^> = G^< + G^R - G^A) on every
+point.  The block-1200 device is checked through the adjoint's consistency
+with finite differences of the GPU forward path (its oracle would take minutes
+per point)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from synth import make_workload
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.max(np.abs(a - b)) / max(float(np.max(np.abs(b))), 1e-300))
+
+
+def test_block400_70_slabs_bench_configuration():
+    from paper_1510_04686_amd.runtime import RGFSolver
+    _say("C2 geometry (block 400, 70 slabs, 8 k) x 64 E in 256-point batches")
+    wl = make_workload("C2", n_e=64)
+    s = RGFSolver(wl, capacity=256, tune="auto")
+    out = s.solve(want_T=True)
+    torch.cuda.synchronize()
+    assert s.status() == 0 and s.lead_status == 0 and s.lead_dual == 1
+    N = wl.total_slabs
+    GR, GL, GG = (out[k].cpu().numpy() for k in ("GR", "GL", "GG"))
+    bond, T = out["bond"].cpu().numpy(), out["T"].cpu().numpy()
+    assert np.all(np.isfinite(GR)) and np.all(np.isfinite(GL)) and np.all(np.isfinite(bond))
+
+    # properties on every point
+    scale_g = np.max(np.abs(GR))
+    assert np.min(-GR.imag) > -1e-10 * scale_g                      # spectral function >= 0
+    assert np.min(GL.imag) > -1e-10 * np.max(np.abs(GL))             # occupation >= 0
+    assert np.max(np.abs(GG - (GL + GR - GR.conj()))) < 1e-12 * scale_g
+    assert np.min(T) > -1e-8
+    # j_{i-1} - j_i = 2 eta Tr(-i G^<_ii) at every interior slab (exact at any eta)
+    sink = 2 * wl.eta * GL.imag.sum(axis=2)                           # [P, N]
+    lhs = bond[:, :N - 2] - bond[:, 1:N - 1]
+    jscale = max(np.max(np.abs(bond[:, :N - 1])), 1e-300)
+    assert np.max(np.abs(lhs - sink[:, 1:N - 1])) < 1e-8 * jscale
+
+    # three sampled points against the oracle, tolerance from the point's own conditioning
+    rng = np.random.default_rng(1510)
+    pts = [tuple(int(x) for x in s.points[p]) for p in rng.choice(s.n_points, size=3, replace=False)]
+    idx = [s.index[p] for p in pts]
+    ref = O.solve_points(wl, pts, transmission=True)
+    alt = O.solve_points(wl, pts, variant="alt", transmission=True)
+    d = lambda x: np.diagonal(x, axis1=1, axis2=2)
+    for p, r, a in zip(idx, ref, alt):
+        spread = max(_rel(a[k], r[k]) for k in ("GR", "GL", "GG"))
+        tol = max(1e-10, 20 * spread)
+        _say(f"  point {s.points[p].tolist()} tol {tol:.1e}")
+        assert _rel(GR[p], d(r["GR"])) < tol
+        assert _rel(GL[p], d(r["GL"])) < tol
+        assert _rel(GG[p], d(r["GG"])) < tol
+        ref_scale = max(np.max(np.abs(r["bond"])), 1e-6 * np.max(np.abs(d(r["GL"]))))
+        assert np.max(np.abs(bond[p, :N - 1] - r["bond"])) < tol * 10 * ref_scale
+        assert abs(T[p] - r["T"]) < tol * max(1.0, abs(r["T"]))
+
+
+def test_block1200_200_slabs_adjoint_against_gpu_differences():
+    from paper_1510_04686_amd.runtime import RGFSolver
+    _say("C5 geometry (block 1200, 200 slabs) x 2 E: adjoint vs central differences")
+    wl = make_workload("C5", n_e=2)
+    s = RGFSolver(wl, adjoint_segment=-1, tune="auto")
+    n0 = s.density().cpu().numpy()
+    assert s.status() == 0 and np.all(np.isfinite(n0)) and np.min(n0) > -1e-12
+    rng = np.random.default_rng(5)
+    w = rng.normal(size=n0.shape)
+    g = s.density_vjp(torch.from_numpy(w)).cpu().numpy()
+    assert np.all(np.isfinite(g))
+    # directional derivative along a smooth random potential change
+    delta = rng.normal(size=n0.shape)
+    h = 1e-5
+    v0 = s.v.clone()
+    opa = wl.orbs_per_atom
+    dv = torch.from_numpy(np.repeat(delta, opa, axis=1)).to(v0.device)
+
+    def objective(sign):
+        s.set_potential(v0 + sign * h * dv)
+        return float(np.sum(w * s.density().cpu().numpy()))
+
+    fd = (objective(+1) - objective(-1)) / (2 * h)
+    s.set_potential(v0)
+    ad = float(np.sum(g * delta))
+    _say(f"  adjoint {ad:.9e}  differences {fd:.9e}")
+    assert abs(fd - ad) < 1e-6 * max(abs(ad), np.max(np.abs(g)))

@@ -114,3 +114,67 @@ def test_zinv_rejects_oversized(ctx):
     A = torch.zeros((1, 420, 420), dtype=torch.complex128, device="cuda")
     with pytest.raises(negf.NegfError):
         negf.negf_zinv_batched(ctx, A, torch.zeros_like(A))
+
+
+def test_tuning_validation_and_roundtrip(ctx):
+    from paper_1510_04686_amd import negf
+    _say("tuning set/get")
+    old = negf.negf_get_tuning(ctx)
+    for bad in ((0, 128), (3, 128), (2, 32), (2, 100), (2, 288)):
+        with pytest.raises(negf.NegfError):
+            negf.negf_set_tuning(ctx, *bad)
+    negf.negf_set_tuning(ctx, 1, 64)
+    assert negf.negf_get_tuning(ctx) == {"gemm_prefetch": 1, "inv_outer": 64}
+    negf.negf_set_tuning(ctx, old["gemm_prefetch"], old["inv_outer"])
+
+
+@pytest.mark.parametrize("W", [0, 64, 96, 192, 256])
+def test_zinv_every_outer_width(ctx, W):
+    """Each outer panel width (and the one-level scheme) gives the same inverse."""
+    from paper_1510_04686_amd import negf
+    _say(f"zinv outer width {W}")
+    old = negf.negf_get_tuning(ctx)
+    rng = np.random.default_rng(3000 + W)
+    n = 400
+    A = _rand(rng, (3, n, n))
+    A[1][np.diag_indices(n)] = 0
+    ref = np.linalg.inv(A)
+    try:
+        negf.negf_set_tuning(ctx, old["gemm_prefetch"], W)
+        dX = torch.zeros((3, n, n), dtype=torch.complex128, device="cuda")
+        negf.negf_zinv_batched(ctx, torch.from_numpy(A.copy()).cuda(), dX)
+        assert negf.negf_sync_status(ctx) == 0
+    finally:
+        negf.negf_set_tuning(ctx, old["gemm_prefetch"], old["inv_outer"])
+    X = dX.cpu().numpy()
+    for b in range(3):
+        err = np.max(np.abs(X[b] - ref[b])) / np.max(np.abs(ref[b]))
+        assert err < 1e-14 * np.linalg.cond(A[b]) * n + 1e-13, (b, err)
+
+
+@pytest.mark.parametrize("pf", [1, 2])
+@pytest.mark.parametrize("n", [17, 100, 400])
+def test_zgemm_prefetch_depths_agree(ctx, pf, n):
+    from paper_1510_04686_amd import negf
+    _say(f"zgemm prefetch {pf} n={n}")
+    old = negf.negf_get_tuning(ctx)
+    rng = np.random.default_rng(4000 + n)
+    A, B = _rand(rng, (2, n, n)), _rand(rng, (2, n, n))
+    dC = torch.zeros((2, n, n), dtype=torch.complex128, device="cuda")
+    try:
+        negf.negf_set_tuning(ctx, pf, old["inv_outer"])
+        negf.negf_zgemm_batched(ctx, torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), dC, 0, 1)
+    finally:
+        negf.negf_set_tuning(ctx, old["gemm_prefetch"], old["inv_outer"])
+    ref = A @ B.conj().transpose(0, 2, 1)
+    assert np.max(np.abs(dC.cpu().numpy() - ref)) / np.max(np.abs(ref)) < 1e-13 * np.sqrt(n)
+
+
+def test_autotune_returns_a_valid_choice():
+    from paper_1510_04686_amd import negf
+    _say("autotune")
+    c = negf.negf_create(nb=200, n_slab_max=1, capacity=4)
+    t = negf.negf_autotune(c, reps=1)
+    assert t["gemm_prefetch"] in (1, 2)
+    assert t["inv_outer"] == 0 or (64 <= t["inv_outer"] < 200 and t["inv_outer"] % 32 == 0)
+    assert negf.negf_get_tuning(c) == t
