@@ -110,6 +110,8 @@ def main():
     ap.add_argument("--samples", type=int, default=None, help="C4: number of alloy samples (default 128)")
     ap.add_argument("--scba-iters", type=int, default=None, help="C3: SCBA iterations (default 20)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--lanes", type=int, default=1,
+                    help="batches in flight at once, each on its own context and stream")
     ap.add_argument("--tune", default="auto", choices=["auto", "default"],
                     help="kernel shapes: measured on this GPU before timing (auto) or the library defaults")
     ap.add_argument("--cpu-points", type=int, default=4)
@@ -146,9 +148,9 @@ def main():
           f"n_k={wl.n_k} n_e={wl.n_e} precision={args.precision}", file=sys.stderr, flush=True)
     adj_seg = -1 if args.workload == "C5" else 0
     solver = RGFSolver(wl, precision=args.precision, capacity=args.capacity, adjoint_segment=adj_seg,
-                       tune="auto" if args.tune == "auto" else None)
+                       tune="auto" if args.tune == "auto" else None, lanes=args.lanes)
     print(f"[bench] capacity={solver.capacity} points/batch, workspace "
-          f"{N.negf_workspace_bytes(solver.ctx) / 2**30:.1f} GiB", file=sys.stderr, flush=True)
+          f"{sum(N.negf_workspace_bytes(c) for c in solver.ctxs) / 2**30:.1f} GiB", file=sys.stderr, flush=True)
     n_iter = (args.scba_iters or wl.n_scba) if args.workload == "C3" else 1
     out = solver.alloc_outputs(want=("GR", "GL", "GG", "bond"))
 
@@ -168,7 +170,8 @@ def main():
         print(f"[bench] warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
 
     timed_gemm = args.workload != "C3"   # event records cannot sit inside the captured SCBA graph
-    N.negf_gemm_timing_enable(solver.ctx, timed_gemm)
+    for c in solver.ctxs:
+        N.negf_gemm_timing_enable(c, timed_gemm)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -177,8 +180,11 @@ def main():
         print(f"[bench] step {k + 1}/{args.steps} done at {time.perf_counter() - t0:.1f} s", file=sys.stderr,
               flush=True)
     dt = time.perf_counter() - t0
-    launches, gemm_ms, gemm_flops = N.negf_gemm_timing(solver.ctx)
-    N.negf_gemm_timing_enable(solver.ctx, False)
+    launches, gemm_ms, gemm_flops = 0, 0.0, 0.0
+    for c in solver.ctxs:
+        l_, m_, f_ = N.negf_gemm_timing(c)
+        launches, gemm_ms, gemm_flops = launches + l_, gemm_ms + m_, gemm_flops + f_
+        N.negf_gemm_timing_enable(c, False)
     st = solver.status()
     iters_L = solver.iters_L.cpu().numpy()
     iters_R = solver.iters_R.cpu().numpy()
@@ -207,7 +213,7 @@ def main():
         "config": {"workload": f"{args.workload}: {WORKLOAD_DESC[args.workload]}",
                    "points_per_step": solver.n_points, "block": wl.nb, "slabs": int(wl.total_slabs),
                    "samples": wl.n_samples, "n_e": wl.n_e, "n_k": wl.n_k,
-                   "batch_capacity": solver.capacity, "precision": args.precision,
+                   "batch_capacity": solver.capacity, "lanes": solver.lanes, "precision": args.precision,
                    "parallelism": "single GPU, batched (sample,k,E) points"},
         "model_tflops": (rgf_f + lead_f) * args.steps / dt / 1e12,
         "model_flops_per_step": {"rgf": rgf_f, "leads": lead_f},
@@ -228,7 +234,8 @@ def main():
         res["config"]["scba_iterations"] = n_iter
         res["roofline"]["note"] = "GEMM events are not recorded inside the captured SCBA graph"
     if args.precision == "mixed":
-        nfb, maxres = N.negf_mixed_stats(solver.ctx)
+        stats = [N.negf_mixed_stats(c) for c in solver.ctxs]
+        nfb, maxres = sum(x[0] for x in stats), max(x[1] for x in stats)
         res["mixed"] = {"fp64_fallback_inverses": nfb, "max_newton_schulz_residual": maxres}
     if args.workload == "C5":
         # adjoint dn/dV: one VJP with a seeded cotangent over all atoms

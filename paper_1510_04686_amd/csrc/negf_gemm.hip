@@ -142,7 +142,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
                     const long long idx = (long long)row * n + col;
                     double vr = (double)cr[mi][nj][r], vi = (double)ci[mi][nj][r];
                     TC out;
-                    if (EPI == EPI_STORE || EPI == EPI_STORE_AH) {
+                    if (EPI == EPI_STORE_AH) {
+                        out.x = (row == col) ? 0.0 : vr; out.y = vi; C[idx] = out;
+                    } else if (EPI == EPI_STORE) {
                         out.x = vr; out.y = vi; C[idx] = out;
                     } else if (EPI == EPI_ADD || EPI == EPI_SUB) {
                         TC d = D[idx];
@@ -152,6 +154,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
                         TC d = D[idx], t1 = T[idx], t2 = T[(long long)col * n + row];
                         out.x = (double)d.x + vr + (double)t1.x - (double)t2.x;
                         out.y = (double)d.y + vi + (double)t1.y + (double)t2.y;
+                        if (EPI == EPI_ADD_TTD_AH && row == col) out.x = 0.0;
                         C[idx] = out;
                     } else if (EPI == EPI_DUAL) {
                         TC c1 = C[idx], c2 = C2[idx];

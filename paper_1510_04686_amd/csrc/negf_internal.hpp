@@ -15,7 +15,10 @@ enum Epi : int {
     EPI_SUB = 5,       // C = D - op(A) op(B)
     // Anti-Hermitian results: only the tiles on and below the diagonal are
     // computed; each element below the diagonal is also written, as -conj, to
-    // its mirror above it.
+    // its mirror above it, and the diagonal keeps only its imaginary part.  A
+    // rounding-level real part left on the diagonal would be carried forward
+    // by the next sandwich g (.) g^dagger with positive weights |g_am|^2 and
+    // grow slab after slab; with the exact symmetry there is nothing to grow.
     EPI_STORE_AH = 6,    // C = op(A) op(B)
     EPI_ADD_TTD_AH = 7,  // C = D + op(A) op(B) + T - T^dagger
 };

@@ -29,10 +29,14 @@ class RGFSolver:
     """Batched RGF over every (sample, k, E) point of a workload on one GPU."""
 
     def __init__(self, wl, precision="fp64", capacity=None, device="cuda", mem_fraction=0.6, adjoint_segment=0,
-                 tune=None):
+                 tune=None, lanes=1):
         """tune: None keeps the library's default kernel shapes; "auto" measures
         them on this context once (negf_autotune) and caches the choice per
-        (device, block, capacity, precision); a dict sets them explicitly."""
+        (device, block, capacity, precision); a dict sets them explicitly.
+        lanes: batches in flight at once, each on its own context and HIP
+        stream (default priority), so the latency-bound phases of one batch
+        (the inverse's panels) overlap the matrix-core phases of another;
+        `capacity` is then the points per batch of each lane."""
         self.wl = wl
         self.device = torch.device(device)
         self.prec = N.NEGF_MIXED if precision == "mixed" else N.NEGF_FP64
@@ -63,10 +67,19 @@ class RGFSolver:
             ce = 8 if self.prec == N.NEGF_MIXED else 16
             per_point = 2 * self.n_slab_max * nb * nb * ce + 24 * nb * nb * 16 + (64 + 2 * 256 + 64) * nb * 16
             free, _ = torch.cuda.mem_get_info(self.device)
-            capacity = int(max(1, min(self.n_points, 256, (free * mem_fraction) // per_point)))
+            lanes = max(1, int(lanes))
+            capacity = int(max(1, min(-(-self.n_points // lanes), 256 // lanes,
+                                      (free * mem_fraction) // (per_point * lanes))))
         self.capacity = int(capacity)
-        self.ctx = N.negf_create(nb, self.n_slab_max, self.capacity, self.prec, adjoint_segment)
+        self.lanes = max(1, int(lanes))
+        # the adjoint runs on the first lane only
+        self.ctxs = [N.negf_create(nb, self.n_slab_max, self.capacity, self.prec, adjoint_segment if i == 0 else 0)
+                     for i in range(self.lanes)]
+        self.ctx = self.ctxs[0]
+        self.streams = [torch.cuda.Stream(self.device) for _ in range(self.lanes)] if self.lanes > 1 else None
         self.tuning = self._tune(tune, precision)
+        for c in self.ctxs[1:]:
+            N.negf_set_tuning(c, self.tuning["gemm_prefetch"], self.tuning["inv_outer"])
         self._last_fwd = None
         self.eta_fill = 0
         self._bind()
@@ -106,8 +119,9 @@ class RGFSolver:
 
     def _bind(self):
         wl = self.wl
-        N.negf_bind(self.ctx, wl.nb, wl.slab_offset, wl.n_k, wl.n_e, self.h_diag, self.h_up, 0, wl.up_block,
-                    self.v, self.energy, wl.eta, wl.mu_L, wl.mu_R, wl.kT, self.eta_fill, self.points)
+        for c in self.ctxs:
+            N.negf_bind(c, wl.nb, wl.slab_offset, wl.n_k, wl.n_e, self.h_diag, self.h_up, 0, wl.up_block,
+                        self.v, self.energy, wl.eta, wl.mu_L, wl.mu_R, wl.kT, self.eta_fill, self.points)
 
     def set_eta_fill(self, on: bool):
         self.eta_fill = int(bool(on))
@@ -153,12 +167,23 @@ class RGFSolver:
 
     def run_batches(self, out, full_blocks=False, want_T=False, scat_R=None, scat_L=None, stream=None):
         flags = N.NEGF_WANT_TRANSMISSION if want_T else 0
-        for p0 in range(0, self.n_points, self.capacity):
+        base = torch.cuda.current_stream(self.device) if stream is None else stream
+        if self.lanes > 1:
+            for ls in self.streams:          # fork (also inside a graph capture)
+                ls.wait_stream(base)
+        for b, p0 in enumerate(range(0, self.n_points, self.capacity)):
             np_ = min(self.capacity, self.n_points - p0)
-            N.negf_rgf_forward(self.ctx, p0, np_, self.sigma_L, self.sigma_R, scat_R, scat_L, flags, stream=stream)
-            self._last_fwd = (p0, np_)
-            N.negf_rgf_backward(self.ctx, p0, np_, out.get("GR"), out.get("GL"), out.get("GG"),
-                                int(full_blocks), self.slab_stride, out.get("bond"), out.get("T"), stream=stream)
+            lane = b % self.lanes
+            ctx = self.ctxs[lane]
+            st = base if self.lanes == 1 else self.streams[lane]
+            N.negf_rgf_forward(ctx, p0, np_, self.sigma_L, self.sigma_R, scat_R, scat_L, flags, stream=st)
+            if lane == 0:
+                self._last_fwd = (p0, np_)
+            N.negf_rgf_backward(ctx, p0, np_, out.get("GR"), out.get("GL"), out.get("GG"),
+                                int(full_blocks), self.slab_stride, out.get("bond"), out.get("T"), stream=st)
+        if self.lanes > 1:
+            for ls in self.streams:          # join
+                base.wait_stream(ls)
 
     def solve(self, full_blocks=False, want=("GR", "GL", "GG", "bond"), want_T=False, scat_R=None, scat_L=None):
         if self.sigma_L is None:
@@ -208,7 +233,8 @@ class RGFSolver:
         return g
 
     def status(self):
-        return N.negf_sync_status(self.ctx)
+        codes = [N.negf_sync_status(c) for c in self.ctxs]
+        return max(codes)
 
     # ------------------------------------------------------------------ SCBA
     def scba(self, n_iter=None, graph=True):

@@ -279,3 +279,23 @@ def test_scba_matches_oracle(graph):
     assert _rel(GR, ref["GRd"]) < TOL
     assert _rel(GL, ref["GLd"]) < TOL
     assert np.allclose(hist, ref["hist"], rtol=1e-8, atol=1e-14)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_two_lanes_match_one_lane(graph):
+    """Batches spread over two contexts and streams give the results of one
+    context (the same kernels, per point), in eager mode and inside the
+    captured SCBA iteration."""
+    _say(f"two lanes, graph={graph}")
+    wl = make_workload("C3", n_slab=5, n_e=40, n_k=2, n_z=1, n_y=2)
+    wl.n_scba = 3
+    one = _solver(wl, capacity=16)
+    two = _solver(wl, capacity=16, lanes=2)
+    o1, h1 = one.scba(graph=graph)
+    o2, h2 = two.scba(graph=graph)
+    torch.cuda.synchronize()
+    assert one.status() == 0 and two.status() == 0
+    for k in ("GR", "GL", "bond"):
+        a, b = o1[k].cpu().numpy(), o2[k].cpu().numpy()
+        assert np.array_equal(a, b), (k, np.max(np.abs(a - b)))
+    assert h1 == h2
