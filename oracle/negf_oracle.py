@@ -163,8 +163,13 @@ def _lesser_sources(N, b, sigL, sigR, fL, fR, scatL, eta, eta_fill):
     return S
 
 
+def _m3(a, b, c, right):
+    """a b c, associated (a b) c, or a (b c) when ``right``."""
+    return a @ (b @ c) if right else (a @ b) @ c
+
+
 def rgf(hd, hu, E, eta, sigL, sigR, fL, fR, v=None, scatR=None, scatL=None,
-        eta_fill=None, transmission=False):
+        eta_fill=None, transmission=False, assoc_right=False):
     """Diagonal blocks of G^R, G^<, G^> plus bond currents (and optionally the
     Caroli transmission) of one (sample, k, E) point by recursive Green's
     functions.
@@ -187,8 +192,11 @@ def rgf(hd, hu, E, eta, sigL, sigR, fL, fR, v=None, scatR=None, scatL=None,
     Transmission: T = Tr[Gamma_R G_{N1} Gamma_L G_{N1}^dagger] with the left
     column chain G_{i,1} = g_i H_{i,i-1} G_{i-1,1}.
     Pinned by: dense inversion (``dense``), Landauer, eta-sink current identity,
-    spectral identity, reciprocity, integer transmission of ordered strips."""
+    spectral identity, reciprocity, integer transmission of ordered strips.
+    ``assoc_right`` associates every triple product the other way; it only serves
+    the reproducibility estimate (two correct FP64 evaluations of one point)."""
     N = len(hd)
+    ar = assoc_right
     b = hd[0].shape[0]
     z = E + 1j * eta
     A = _assemble(hd, z, sigL, sigR, v, scatR)
@@ -197,11 +205,11 @@ def rgf(hd, hu, E, eta, sigL, sigR, fL, fR, v=None, scatR=None, scatL=None,
     g = [None] * N
     gl = [None] * N
     g[0] = inv(A[0])
-    gl[0] = g[0] @ S[0] @ dag(g[0])
+    gl[0] = _m3(g[0], S[0], dag(g[0]), ar)
     for i in range(1, N):
         hl = dag(hu[i - 1])            # H_{i,i-1}
-        g[i] = inv(A[i] - hl @ g[i - 1] @ hu[i - 1])
-        gl[i] = g[i] @ (S[i] + hl @ gl[i - 1] @ hu[i - 1]) @ dag(g[i])
+        g[i] = inv(A[i] - _m3(hl, g[i - 1], hu[i - 1], ar))
+        gl[i] = _m3(g[i], S[i] + _m3(hl, gl[i - 1], hu[i - 1], ar), dag(g[i]), ar)
 
     GR = [None] * N
     GL = [None] * N
@@ -212,10 +220,10 @@ def rgf(hd, hu, E, eta, sigL, sigR, fL, fR, v=None, scatR=None, scatL=None,
         hr = dag(hu[i])                # H_{i+1,i}
         L = g[i] @ hu[i]
         P = L @ GR[i + 1]
-        GR[i] = g[i] + P @ hr @ g[i]
-        T = P @ hr @ gl[i]
-        GL[i] = gl[i] + L @ GL[i + 1] @ dag(L) + T - dag(T)
-        gl_10 = GR[i + 1] @ hr @ gl[i] + GL[i + 1] @ dag(L)
+        GR[i] = g[i] + _m3(P, hr, g[i], ar)
+        T = _m3(P, hr, gl[i], ar)
+        GL[i] = gl[i] + _m3(L, GL[i + 1], dag(L), ar) + T - dag(T)
+        gl_10 = _m3(GR[i + 1], hr, gl[i], ar) + GL[i + 1] @ dag(L)
         bond[i] = 2.0 * np.real(np.trace(hu[i] @ gl_10))
     GR = np.array(GR)
     GL = np.array(GL)
@@ -329,7 +337,9 @@ def lead_tables(wl, tol=1e-14, max_iter=100, ks=None, es=None, variant=None):
 
 def solve_points(wl, points, leads=None, scatR=None, scatL=None, transmission=False, eta_fill=None,
                  variant=None):
-    """RGF for a list of (sample, ik, ie) points.  scatR/scatL: [n_e, total_slabs, b]."""
+    """RGF for a list of (sample, ik, ie) points.  scatR/scatL: [n_e, total_slabs, b].
+    variant="alt": the reproducibility estimate, with the lead decimation and every
+    triple product of the recursion associated the other way."""
     if leads is None:
         leads = lead_tables(wl, ks=sorted({int(p[1]) for p in points}),
                             es=sorted({int(p[2]) for p in points}), variant=variant)
@@ -345,7 +355,7 @@ def solve_points(wl, points, leads=None, scatR=None, scatL=None, transmission=Fa
         sl = None if scatL is None else scatL[ie, a0:a1]
         ef = None if eta_fill is None else float(fermi(E, eta_fill, wl.kT))
         res.append(rgf(hd, hu, E, wl.eta, sL, sR, fL, fR, v=v, scatR=sr, scatL=sl,
-                       transmission=transmission, eta_fill=ef))
+                       transmission=transmission, eta_fill=ef, assoc_right=(variant == "alt")))
     return res
 
 

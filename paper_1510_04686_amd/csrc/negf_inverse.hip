@@ -576,8 +576,14 @@ static hipError_t inverse_typed(hipStream_t s, void* src, long long s_src, void*
         }
         return hipSuccess;
     }
-    for (int K0 = 0; K0 < n; K0 += w.W) {
-        const int W = (n - K0 < w.W) ? (n - K0) : w.W;
+    int Wk = w.W;
+    for (int K0 = 0; K0 < n; K0 += Wk) {
+        // a remainder narrower than half an outer panel joins the current one (one
+        // full-matrix sweep less), as long as the widened panel fits its buffers
+        Wk = (n - K0 < w.W) ? (n - K0) : w.W;
+        const int rest = n - K0 - Wk;
+        if (rest > 0 && 2 * rest < w.W && n - K0 <= INV_WMAX) Wk = n - K0;
+        const int W = Wk;
         const int lastK = (K0 + W == n);
         const long long sN = (long long)n * W;
         // inner steps: the outer panel's columns, full matrix -> narrow copy.  A full-width

@@ -145,80 +145,67 @@ __global__ __launch_bounds__(256) void sandwich_kernel(SandArgs a) {
     }
 }
 
-// The same operation without LDS, for ub <= 16: one thread per (block row of
-// ub rows, column c).  It forms Y = X opR(U) for its ub rows at column c (ub^2
-// reads of X shared, through L1, by the ub threads of a column block), then
-// O = opL(U) Y in registers and writes ub coalesced outputs.
-template <typename TX, typename TO, int UBM>
+// The same operation without LDS, for the common block sizes (1, 2, 4, 8, 10, 16): one thread per
+// (block row of UB rows, column c).  It forms Y = X U for its UB rows at
+// column c (UB^2 reads of X shared, through L1, by the UB threads of a column
+// block), then O = U^dagger Y in registers and writes UB coalesced outputs.
+// UB and the operand forms are compile-time, so the loops carry no guards and
+// every read of a row group can be in flight at once.
+template <typename TX, typename TO, int UB, int OPL, int OPR>
 __global__ __launch_bounds__(256) void sandwich_cols_kernel(SandArgs a) {
-    const int n = a.n, ub = a.ub;
-    const int nblk = n / ub;
+    const int n = a.n;
+    const int nblk = n / UB;
     const long long work = (long long)nblk * n, per = (work + 255) / 256;
     const int q = (int)(blockIdx.x / per);
     if (q >= a.np || !a.act(q)) return;
     const long long idx = (blockIdx.x - (long long)q * per) * 256 + threadIdx.x;
     if (idx >= work) return;
     const int blk = (int)(idx / n), c = (int)(idx - (long long)blk * n);
-    const int rb = blk * ub, cb = (c / ub) * ub;
+    const int rb = blk * UB, cb = (c / UB) * UB;
     const int4 d = a.ps.desc[a.ps.p0 + q];
     const int ik = d.y, ie = d.z, ns = d.w;
     const long long sfirst = a.ps.slab_off[d.x];
-    double2 y[UBM];
+    double2 y[UB];
 #pragma unroll
-    for (int i = 0; i < UBM; ++i) y[i] = make_double2(0, 0);
+    for (int i = 0; i < UB; ++i) y[i] = make_double2(0, 0);
     if (a.X) {
         const TX* X = reinterpret_cast<const TX*>(a.X) + q * a.sX;
         const double2* U = a.hup + ik * a.hup_k + (sfirst + a.uslab) * (long long)n * n;
-        if (a.opR) {
-            double2 uc[UBM];   // opR(U)[cb + j][c]
+        if constexpr (OPR == 1) {
+            double2 uc[UB];   // U[cb + j][c]
 #pragma unroll
-            for (int j = 0; j < UBM; ++j)
-                if (j < ub) uc[j] = (a.opR == 1) ? U[(long long)(cb + j) * n + c] : cconj(U[(long long)c * n + cb + j]);
+            for (int j = 0; j < UB; ++j) uc[j] = U[(long long)(cb + j) * n + c];
 #pragma unroll
-            for (int i = 0; i < UBM; ++i) {
-                if (i < ub) {
-                    const TX* xr = X + (long long)(rb + i) * n + cb;
+            for (int i = 0; i < UB; ++i) {
+                const TX* xr = X + (long long)(rb + i) * n + cb;
 #pragma unroll
-                    for (int j = 0; j < UBM; ++j)
-                        if (j < ub) cfma(y[i], cconv<double2>(xr[j]), uc[j]);
-                }
+                for (int j = 0; j < UB; ++j) cfma(y[i], cconv<double2>(xr[j]), uc[j]);
             }
         } else {
 #pragma unroll
-            for (int i = 0; i < UBM; ++i)
-                if (i < ub) y[i] = cconv<double2>(X[(long long)(rb + i) * n + c]);
+            for (int i = 0; i < UB; ++i) y[i] = cconv<double2>(X[(long long)(rb + i) * n + c]);
         }
-        if (a.opL) {
-            double2 z[UBM];
+        if constexpr (OPL == 2) {
+            double2 z[UB];
 #pragma unroll
-            for (int i = 0; i < UBM; ++i) {
+            for (int i = 0; i < UB; ++i) {
                 z[i] = make_double2(0, 0);
-                if (i < ub) {
 #pragma unroll
-                    for (int k = 0; k < UBM; ++k) {
-                        if (k < ub) {
-                            const double2 u = (a.opL == 1) ? U[(long long)(rb + i) * n + rb + k]
-                                                           : cconj(U[(long long)(rb + k) * n + rb + i]);
-                            cfma(z[i], u, y[k]);
-                        }
-                    }
-                }
+                for (int k = 0; k < UB; ++k) cfma(z[i], cconj(U[(long long)(rb + k) * n + rb + i]), y[k]);
             }
 #pragma unroll
-            for (int i = 0; i < UBM; ++i) y[i] = z[i];
+            for (int i = 0; i < UB; ++i) y[i] = z[i];
         }
     }
     TO* O = reinterpret_cast<TO*>(a.O) + q * a.sO;
     const long long gslab = sfirst + a.slab;
     const double E = a.energy ? a.energy[ie] : 0.0;
 #pragma unroll
-    for (int i = 0; i < UBM; ++i) {
-        if (i < ub) {
-            double2 z = y[i];
-            z.x *= a.sign; z.y *= a.sign;
-            sandwich_base(a, z, rb + i, c, ik, ie, ns, gslab, E);
-            O[(long long)(rb + i) * n + c] = cconv<TO>(z);
-        }
+    for (int i = 0; i < UB; ++i) {
+        double2 z = y[i];
+        z.x *= a.sign; z.y *= a.sign;
+        sandwich_base(a, z, rb + i, c, ik, ie, ns, gslab, E);
+        O[(long long)(rb + i) * n + c] = cconv<TO>(z);
     }
 }
 
@@ -238,16 +225,29 @@ hipError_t sandwich_init() {
     return hipSuccess;
 }
 
+template <typename TX, typename TO, int UB>
+static bool sandwich_cols_ops(hipStream_t s, const SandArgs& a, dim3 grid) {
+    if (a.opL == 0 && a.opR == 1) hipLaunchKernelGGL((sandwich_cols_kernel<TX, TO, UB, 0, 1>), grid, dim3(256), 0, s, a);
+    else if (a.opL == 2 && a.opR == 0) hipLaunchKernelGGL((sandwich_cols_kernel<TX, TO, UB, 2, 0>), grid, dim3(256), 0, s, a);
+    else if (a.opL == 2 && a.opR == 1) hipLaunchKernelGGL((sandwich_cols_kernel<TX, TO, UB, 2, 1>), grid, dim3(256), 0, s, a);
+    else if (a.opL == 0 && a.opR == 0) hipLaunchKernelGGL((sandwich_cols_kernel<TX, TO, UB, 0, 0>), grid, dim3(256), 0, s, a);
+    else return false;
+    return true;
+}
+
 template <typename TX, typename TO>
 static bool sandwich_cols_launch(hipStream_t s, const SandArgs& a) {
-    if (a.ub > 16) return false;
     const long long work = (long long)(a.n / a.ub) * a.n;
     dim3 grid((unsigned)((long long)a.np * ((work + 255) / 256)));
-    if (a.ub <= 4) hipLaunchKernelGGL((sandwich_cols_kernel<TX, TO, 4>), grid, dim3(256), 0, s, a);
-    else if (a.ub <= 8) hipLaunchKernelGGL((sandwich_cols_kernel<TX, TO, 8>), grid, dim3(256), 0, s, a);
-    else if (a.ub <= 12) hipLaunchKernelGGL((sandwich_cols_kernel<TX, TO, 12>), grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((sandwich_cols_kernel<TX, TO, 16>), grid, dim3(256), 0, s, a);
-    return true;
+    switch (a.ub) {
+        case 1: return sandwich_cols_ops<TX, TO, 1>(s, a, grid);
+        case 2: return sandwich_cols_ops<TX, TO, 2>(s, a, grid);
+        case 4: return sandwich_cols_ops<TX, TO, 4>(s, a, grid);
+        case 8: return sandwich_cols_ops<TX, TO, 8>(s, a, grid);
+        case 10: return sandwich_cols_ops<TX, TO, 10>(s, a, grid);
+        case 16: return sandwich_cols_ops<TX, TO, 16>(s, a, grid);
+        default: return false;
+    }
 }
 
 hipError_t sandwich_launch(hipStream_t s, int xdt, int odt, const SandArgs& a) {
@@ -369,12 +369,12 @@ hipError_t extract_launch(hipStream_t s, int dt, const ExtArgs& a) {
 // One workgroup per (point, group of atom blocks) keeps the ub rows of G and
 // G^< it needs in registers; the partials are added in a fixed order.
 // ---------------------------------------------------------------------------
-template <typename TI, int UBM>
+template <typename TI, int UB>
 __global__ __launch_bounds__(256) void bond_rows_kernel(BondArgs a) {
     const int q = blockIdx.x / BOND_NWB, w = blockIdx.x - q * BOND_NWB;
     if (q >= a.np || !a.act(q)) return;
-    const int n = a.n, ub = a.ub, tid = threadIdx.x;
-    const int nblk = n / ub;
+    const int n = a.n, tid = threadIdx.x;
+    const int nblk = n / UB;
     const int4 d = a.ps.desc[a.ps.p0 + q];
     const long long sfirst = a.ps.slab_off[d.x];
     const double2* U = a.hup + d.y * a.hup_k + (sfirst + a.slab) * (long long)n * n;
@@ -384,35 +384,29 @@ __global__ __launch_bounds__(256) void bond_rows_kernel(BondArgs a) {
     const TI* GS = reinterpret_cast<const TI*>(a.gls) + q * a.s_gls;
     double acc = 0.0;
     for (int A = w; A < nblk; A += BOND_NWB) {
-        const int r0 = A * ub;
+        const int r0 = A * UB;
         for (int b = tid; b < n; b += 256) {
-            const int bb = (b / ub) * ub;
-            double2 gc[UBM], glc[UBM], uc[UBM];
+            const int bb = (b / UB) * UB;
+            double2 gc[UB], glc[UB], uc[UB];
 #pragma unroll
-            for (int j = 0; j < UBM; ++j) {
-                if (j < ub) {
-                    gc[j] = cconv<double2>(G[(long long)(r0 + j) * n + b]);
-                    glc[j] = cconv<double2>(GL[(long long)(r0 + j) * n + b]);
-                    uc[j] = U[(long long)(bb + j) * n + b];
-                }
+            for (int j = 0; j < UB; ++j) {
+                gc[j] = cconv<double2>(G[(long long)(r0 + j) * n + b]);
+                glc[j] = cconv<double2>(GL[(long long)(r0 + j) * n + b]);
+                uc[j] = U[(long long)(bb + j) * n + b];
             }
 #pragma unroll
-            for (int i = 0; i < UBM; ++i) {
-                if (i < ub) {
-                    const long long r = r0 + i;
-                    double2 ug = make_double2(0, 0), ugl = make_double2(0, 0), gu = make_double2(0, 0);
+            for (int i = 0; i < UB; ++i) {
+                const long long r = r0 + i;
+                double2 ug = make_double2(0, 0), ugl = make_double2(0, 0), gu = make_double2(0, 0);
 #pragma unroll
-                    for (int j = 0; j < UBM; ++j) {
-                        if (j < ub) {
-                            const double2 u = U[r * n + r0 + j];
-                            cfma(ug, u, gc[j]);
-                            cfma(ugl, u, glc[j]);
-                            cfma(gu, cconv<double2>(GS[r * n + bb + j]), uc[j]);
-                        }
-                    }
-                    const double2 l = cconv<double2>(L[r * n + b]);
-                    acc += (ugl.x * l.x + ugl.y * l.y) - (ug.x * gu.x + ug.y * gu.y);
+                for (int j = 0; j < UB; ++j) {
+                    const double2 u = U[r * n + r0 + j];
+                    cfma(ug, u, gc[j]);
+                    cfma(ugl, u, glc[j]);
+                    cfma(gu, cconv<double2>(GS[r * n + bb + j]), uc[j]);
                 }
+                const double2 l = cconv<double2>(L[r * n + b]);
+                acc += (ugl.x * l.x + ugl.y * l.y) - (ug.x * gu.x + ug.y * gu.y);
             }
         }
     }
@@ -478,10 +472,13 @@ __global__ void bond_final_kernel(const double* partial, double* out, int slab_s
 
 template <typename TI>
 static void bond_dispatch(hipStream_t s, const BondArgs& a, dim3 grid) {
-    if (a.gls && a.ub <= 4) hipLaunchKernelGGL((bond_rows_kernel<TI, 4>), grid, dim3(256), 0, s, a);
-    else if (a.gls && a.ub <= 8) hipLaunchKernelGGL((bond_rows_kernel<TI, 8>), grid, dim3(256), 0, s, a);
-    else if (a.gls && a.ub <= 12) hipLaunchKernelGGL((bond_rows_kernel<TI, 12>), grid, dim3(256), 0, s, a);
-    else if (a.gls && a.ub <= 16) hipLaunchKernelGGL((bond_rows_kernel<TI, 16>), grid, dim3(256), 0, s, a);
+    const bool rows = a.gls != nullptr;
+    if (rows && a.ub == 1) hipLaunchKernelGGL((bond_rows_kernel<TI, 1>), grid, dim3(256), 0, s, a);
+    else if (rows && a.ub == 2) hipLaunchKernelGGL((bond_rows_kernel<TI, 2>), grid, dim3(256), 0, s, a);
+    else if (rows && a.ub == 4) hipLaunchKernelGGL((bond_rows_kernel<TI, 4>), grid, dim3(256), 0, s, a);
+    else if (rows && a.ub == 8) hipLaunchKernelGGL((bond_rows_kernel<TI, 8>), grid, dim3(256), 0, s, a);
+    else if (rows && a.ub == 10) hipLaunchKernelGGL((bond_rows_kernel<TI, 10>), grid, dim3(256), 0, s, a);
+    else if (rows && a.ub == 16) hipLaunchKernelGGL((bond_rows_kernel<TI, 16>), grid, dim3(256), 0, s, a);
     else hipLaunchKernelGGL(bond_partial_kernel<TI>, grid, dim3(256), 0, s, a);
 }
 

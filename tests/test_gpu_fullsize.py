@@ -61,7 +61,7 @@ def test_block400_70_slabs_bench_configuration():
     d = lambda x: np.diagonal(x, axis1=1, axis2=2)
     for p, r, a in zip(idx, ref, alt):
         spread = max(_rel(a[k], r[k]) for k in ("GR", "GL", "GG"))
-        tol = max(1e-10, 20 * spread)
+        tol = max(1e-10, 100 * spread)   # as in test_gpu_rgf: 100 x the oracle's own drift
         _say(f"  point {s.points[p].tolist()} tol {tol:.1e}")
         assert _rel(GR[p], d(r["GR"])) < tol
         assert _rel(GL[p], d(r["GL"])) < tol

@@ -12,6 +12,7 @@ from synth import make_workload, random_tiny
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-10   # relative, FP64 path
+SPREAD = 100  # x the oracle's own two-evaluation drift, for points that cannot meet TOL in FP64
 
 
 def _say(msg):
@@ -29,10 +30,12 @@ def _rel(a, b):
 
 
 def _ref_and_tol(wl, pts, **kw):
-    """Oracle results plus a per-point tolerance: 1e-10 relative, or 20 x the
+    """Oracle results plus a per-point tolerance: 1e-10 relative, or SPREAD x the
     drift between two correct FP64 evaluations of the point by the oracle itself
-    (default vs alternate association in the lead decimation) where that drift
-    is larger -- the point's own conditioning, measured without the GPU."""
+    (default vs alternate association in the lead decimation and the recursion)
+    where that drift is larger -- the point's own conditioning, measured without
+    the GPU.  One pair of evaluations samples the rounding only once, so the
+    factor is wide."""
     ref = O.solve_points(wl, pts, **kw)
     alt = O.solve_points(wl, pts, variant="alt", **kw)
     tols = []
@@ -40,7 +43,7 @@ def _ref_and_tol(wl, pts, **kw):
         spread = max(_rel(a[k], r[k]) for k in ("GR", "GL", "GG"))
         if "T" in r:
             spread = max(spread, abs(a["T"] - r["T"]) / max(1.0, abs(r["T"])))
-        tols.append(max(TOL, 20.0 * spread))
+        tols.append(max(TOL, SPREAD * spread))
     return ref, tols
 
 
@@ -85,8 +88,8 @@ def test_lead_selfenergy_matches_oracle(nb, seed):
         rR, itR, _ = O.lead_selfenergy(wl.lead_h00[0], wl.lead_h01_R, wl.lead_tau_R, z)
         aL, _, _ = O.lead_selfenergy(wl.lead_h00[0], wl.lead_h01_L, wl.lead_tau_L, z, variant="alt")
         aR, _, _ = O.lead_selfenergy(wl.lead_h00[0], wl.lead_h01_R, wl.lead_tau_R, z, variant="alt")
-        tL = max(TOL, 20 * _rel(aL, rL))
-        tR = max(TOL, 20 * _rel(aR, rR))
+        tL = max(TOL, SPREAD * _rel(aL, rL))
+        tR = max(TOL, SPREAD * _rel(aR, rR))
         assert _rel(sL[0, ie].cpu().numpy(), rL) < tL
         assert _rel(sR[0, ie].cpu().numpy(), rR) < tR
         assert abs(int(s.iters_L[0, ie]) - itL) <= 1 and abs(int(s.iters_R[0, ie]) - itR) <= 1
@@ -113,7 +116,7 @@ def test_lead_pair_shared_decimation(complex_h):
                                                   ("R", wl.lead_h01_R, wl.lead_tau_R, sR, itR, qR)):
                 r, itr, _ = O.lead_selfenergy(wl.lead_h00[ik], h01, tau, z)
                 a, _, _ = O.lead_selfenergy(wl.lead_h00[ik], h01, tau, z, variant="alt")
-                tol = max(TOL, 20 * _rel(a, r))
+                tol = max(TOL, SPREAD * _rel(a, r))
                 g = got[ik, ie].cpu().numpy()
                 assert _rel(g, r) < tol, (side, ik, ie, _rel(g, r))
                 assert _rel(g, sep[ik, ie].cpu().numpy()) < tol, (side, "vs separate")
