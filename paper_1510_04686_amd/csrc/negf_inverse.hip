@@ -392,6 +392,20 @@ __global__ __launch_bounds__(256) void gj_update(UpdArgs a) {
     const C* Pr = a.Prow ? reinterpret_cast<const C*>(a.Prow) + (long long)q * NBMAX * a.ldP : nullptr;
     const int* rs = a.rowsrc + (long long)q * n;
     const int ldX = a.ldX, xc = a.xcol0;
+    // Row sources read ahead: the pivot row this thread loads in the next K slice (when
+    // gathered from X) and the tile rows it gathers at the end, so no global read of
+    // the matrix waits on an index read.
+    const int pk = tid >> 4, poc = (tid & 15) * 4;
+    auto row_of = [&](int s) { const int kk = s * BK + pk; return (!Pr && kk < nbk) ? rs[k0 + kk] : 0; };
+    int src_next = row_of(0);   // pivot-row source of the slice loaded next (read one slice ahead)
+    int rsr[2][4];
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = rowbase + mi * 16 + out_row<R>(lane, r);
+            rsr[mi][r] = (row < n) ? rs[row] : 0;
+        }
 
     typename MF<R>::V cr[2][2], ci[2][2];
 #pragma unroll
@@ -404,7 +418,6 @@ __global__ __launch_bounds__(256) void gj_update(UpdArgs a) {
     // the current slice's products.  E tile: rows m0.., k (pattern X); pivot-row
     // tile: k rows, cols n0.. (pattern Y).
     const int eo = tid >> 2, ek = (tid & 3) * 4, erow = m0 + eo;
-    const int pk = tid >> 4, poc = (tid & 15) * 4;
     C re[4], rp[4];
     auto load = [&](int s) {
 #pragma unroll
@@ -418,7 +431,9 @@ __global__ __launch_bounds__(256) void gj_update(UpdArgs a) {
         }
         const int kk = s * BK + pk;
         const C* prow = nullptr;
-        if (kk < nbk) prow = Pr ? Pr + (long long)kk * a.ldP - a.pc0 : X + (long long)rs[k0 + kk] * ldX - xc;
+        const int src = src_next;
+        src_next = row_of(s + 1);
+        if (kk < nbk) prow = Pr ? Pr + (long long)kk * a.ldP - a.pc0 : X + (long long)src * ldX - xc;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int col = n0 + poc + j;
@@ -435,41 +450,47 @@ __global__ __launch_bounds__(256) void gj_update(UpdArgs a) {
             Ps[b][1][pk][poc + j] = rp[j].y;
         }
     };
-    load(0);
-    store(0);
-    __syncthreads();
-    for (int s = 0; s < nsl; ++s) {
-        const int b = s & 1;
-        const bool more = s + 1 < nsl;
-        if (more) load(s + 1);
+    // Gathered rows of the old matrix (or the transform columns inside the K range),
+    // read while the last slice's products run.
+    C xo[2][2][4];
+    auto gather = [&]() {
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+            for (int nj = 0; nj < 2; ++nj) {
+                const int col = colbase + nj * 16 + (lane & 15);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = rowbase + mi * 16 + out_row<R>(lane, r);
+                    const bool in = mi < nmi && nj < nnj && row < n && col < cend;
+                    const bool inK = col >= k0 && col < k0 + nbk;
+                    xo[mi][nj][r].x = 0; xo[mi][nj][r].y = 0;
+                    if (in) {
+                        if (inK) xo[mi][nj][r] = E[(long long)row * a.ldE + (col - k0)];
+                        else xo[mi][nj][r] = X[(long long)rsr[mi][r] * ldX + (col - xc)];
+                    }
+                }
+            }
+    };
+    auto mma = [&](int b) {
         if (nmi == 2 && nnj == 2) mma_slice<R, 2, 2>(Es[b], Ps[b], lane, wm, wn, cr, ci);
         else if (nmi == 2 && nnj == 1) mma_slice<R, 2, 1>(Es[b], Ps[b], lane, wm, wn, cr, ci);
         else if (nmi == 1 && nnj == 2) mma_slice<R, 1, 2>(Es[b], Ps[b], lane, wm, wn, cr, ci);
         else if (nmi == 1 && nnj == 1) mma_slice<R, 1, 1>(Es[b], Ps[b], lane, wm, wn, cr, ci);
-        if (more) store(b ^ 1);
+    };
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int s = 0; s + 1 < nsl; ++s) {
+        const int b = s & 1;
+        load(s + 1);
+        mma(b);
+        store(b ^ 1);
         __syncthreads();
     }
+    mma((nsl - 1) & 1);
+    gather();   // behind the last products, which are still in flight
 
-    // Gathered rows of the old matrix (read after the products: holding them through the
-    // K loop would halve the wavefronts per SIMD).
-    C xo[2][2][4];
-#pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-        for (int nj = 0; nj < 2; ++nj) {
-            const int col = colbase + nj * 16 + (lane & 15);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = rowbase + mi * 16 + out_row<R>(lane, r);
-                const bool in = mi < nmi && nj < nnj && row < n && col < cend;
-                const bool inK = col >= k0 && col < k0 + nbk;
-                xo[mi][nj][r].x = 0; xo[mi][nj][r].y = 0;
-                if (in) {
-                    if (inK) xo[mi][nj][r] = E[(long long)row * a.ldE + (col - k0)];
-                    else xo[mi][nj][r] = X[(long long)rs[row] * ldX + (col - xc)];
-                }
-            }
-        }
     C* Y = reinterpret_cast<C*>(a.Y) + q * a.sY;
     const int* cd = a.coldst + (long long)q * n;
 #pragma unroll
