@@ -2,12 +2,13 @@
 
 Reads the FETCH_SIZE and WRITE_SIZE databases that these commands write (one
 counter per run, each run also copies a known 256 MiB buffer first so the
-counters can be calibrated):
+counters can be calibrated; both use the library's default kernel shapes so
+the two runs dispatch the same kernels):
 
     rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_FETCH_SIZE -o run -- \
-        python3 bench.py --n-e 16 --no-cpu-baseline --copy-calibration 256 > gpurun_out/pmc_FETCH_SIZE.log
+        python3 bench.py --n-e 16 --no-cpu-baseline --tune default --copy-calibration 256 > gpurun_out/pmc_FETCH_SIZE.log
     rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_WRITE_SIZE -o run -- \
-        python3 bench.py --n-e 16 --no-cpu-baseline --copy-calibration 256 > gpurun_out/pmc_WRITE_SIZE.log
+        python3 bench.py --n-e 16 --no-cpu-baseline --tune default --copy-calibration 256 > gpurun_out/pmc_WRITE_SIZE.log
 
 and writes profiles/gemm_traffic_C2.json (read by bench.py for the roofline's
 `traffic`, valid while the GEMM sources keep the recorded SHA-1) and a short
@@ -75,9 +76,9 @@ def main(base):
         "calibration": {"copy_bytes": COPY_BYTES, "FETCH_SIZE_factor": ff, "WRITE_SIZE_factor": fw},
         "commands": [
             "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_FETCH_SIZE -o run -- python3 bench.py --n-e 16 "
-            "--no-cpu-baseline --copy-calibration 256",
+            "--no-cpu-baseline --tune default --copy-calibration 256",
             "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_WRITE_SIZE -o run -- python3 bench.py --n-e 16 "
-            "--no-cpu-baseline --copy-calibration 256",
+            "--no-cpu-baseline --tune default --copy-calibration 256",
         ],
     }
     with open(os.path.join(ROOT, "profiles", "gemm_traffic_C2.json"), "w") as fh:
