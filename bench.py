@@ -110,6 +110,8 @@ def main():
     ap.add_argument("--samples", type=int, default=None, help="C4: number of alloy samples (default 128)")
     ap.add_argument("--scba-iters", type=int, default=None, help="C3: SCBA iterations (default 20)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--point-redo", type=float, default=0.03,
+                    help="mixed precision: redo points whose block-refinement residual exceeds this in FP64 (inf: off)")
     ap.add_argument("--lanes", type=int, default=1,
                     help="batches in flight at once, each on its own context and stream")
     ap.add_argument("--tune", default="auto", choices=["auto", "default"],
@@ -148,7 +150,7 @@ def main():
           f"n_k={wl.n_k} n_e={wl.n_e} precision={args.precision}", file=sys.stderr, flush=True)
     adj_seg = -1 if args.workload == "C5" else 0
     solver = RGFSolver(wl, precision=args.precision, capacity=args.capacity, adjoint_segment=adj_seg,
-                       tune="auto" if args.tune == "auto" else None, lanes=args.lanes)
+                       tune="auto" if args.tune == "auto" else None, lanes=args.lanes, point_redo=args.point_redo)
     print(f"[bench] capacity={solver.capacity} points/batch, workspace "
           f"{sum(N.negf_workspace_bytes(c) for c in solver.ctxs) / 2**30:.1f} GiB", file=sys.stderr, flush=True)
     n_iter = (args.scba_iters or wl.n_scba) if args.workload == "C3" else 1
@@ -236,7 +238,8 @@ def main():
     if args.precision == "mixed":
         stats = [N.negf_mixed_stats(c) for c in solver.ctxs]
         nfb, maxres = sum(x[0] for x in stats), max(x[1] for x in stats)
-        res["mixed"] = {"fp64_fallback_inverses": nfb, "max_newton_schulz_residual": maxres}
+        res["mixed"] = {"fp64_fallback_inverses": nfb, "max_block_refinement_residual": maxres,
+                        "point_redo_bound": solver.point_redo, "points_redone_per_step": solver.points_redone}
     if args.workload == "C5":
         # adjoint dn/dV: one VJP with a seeded cotangent over all atoms
         wv = torch.from_numpy(np.random.default_rng(1510046865).normal(
@@ -250,23 +253,28 @@ def main():
         res["adjoint"] = {"ms": t_adj * 1e3, "forward_ms": t_fwd * 1e3, "cost_ratio": t_adj / t_fwd,
                           "checkpoint_segment": int(np.ceil(np.sqrt(wl.total_slabs))),
                           "grad_norm": float(torch.linalg.norm(g))}
-    if args.workload == "C4" and args.precision == "mixed":
-        # per-sample density error of the mixed path against the FP64 GPU path
-        n_mix = n.cpu().numpy()
+    if args.workload in ("C2", "C4") and args.precision == "mixed":
+        # per-sample density and current error of the mixed path against the FP64
+        # GPU path (outside the timed region)
+        n_mix, J_mix = n.cpu().numpy(), J.cpu().numpy()
         del solver
         torch.cuda.empty_cache()
         ref = RGFSolver(wl, precision="fp64", capacity=args.capacity)
         o64 = ref.alloc_outputs(want=("GL", "bond"))
         ref.lead_selfenergies()
         ref.run_batches(o64)
-        n64, _, _ = ref.observables(o64["GL"], o64["bond"])
-        n64 = n64.cpu().numpy()
-        errs = []
+        n64, J64, _ = ref.observables(o64["GL"], o64["bond"])
+        n64, J64 = n64.cpu().numpy(), J64.cpu().numpy()
+        errs, jerrs = [], []
         for s_ in range(wl.n_samples):
             a0, a1 = int(wl.slab_offset[s_]), int(wl.slab_offset[s_ + 1])
             errs.append(float(np.max(np.abs(n_mix[a0:a1] - n64[a0:a1])) / np.max(np.abs(n64[a0:a1]))))
+            jerrs.append(float(np.max(np.abs(J_mix[a0:a1] - J64[a0:a1])) / np.max(np.abs(J64[a0:a1]))))
+        ref_note = "FP64 GPU path (oracle-checked)"
         res["mixed"]["per_sample_density_rel_err"] = {"max": max(errs), "median": float(np.median(errs)),
-                                                     "reference": "FP64 GPU path (oracle-checked)"}
+                                                     "reference": ref_note}
+        res["mixed"]["per_sample_current_rel_err"] = {"max": max(jerrs), "median": float(np.median(jerrs)),
+                                                     "reference": ref_note}
     if not args.no_cpu_baseline and args.cpu_points > 0:
         res["cpu_baseline"] = cpu_baseline(wl, args.cpu_points)
     print(json.dumps(res), flush=True)

@@ -264,9 +264,27 @@ int negf_zgemm_batched(negf_ctx* ctx, void* stream, int n, int batch, int opa, i
 int negf_zinv_batched(negf_ctx* ctx, void* stream, int n, int batch, void* A, void* Ainv, int dtype);
 
 /* Mixed-precision diagnostics of the last forward sweeps since the previous call:
- * number of block inverses redone in FP64 and the largest Newton-Schulz
- * residual ||I - A X0||_max seen (host outputs; synchronises `stream`). */
+ * number of block inverses redone in FP64 and the largest refinement residual
+ * ||I - A X0||_F seen (host outputs; synchronises `stream`). */
 int negf_mixed_stats(negf_ctx* ctx, void* stream, long long* n_fallback, double* max_residual);
+
+/* Mixed precision: the residual ||I - A X0||_F of the FP32 block inverse X0
+ * above which that block inverse is redone in FP64 (default 1e-2).  Below it the
+ * one Newton-Schulz step leaves a relative inverse error of at most thr^2 plus
+ * FP32 rounding, since the Frobenius norm bounds the spectral norm.  0 redoes
+ * every block inverse in FP64; +infinity never does (non-finite residuals
+ * still do).  Applies to later forward sweeps of the context.
+ * Errors: NEGF_EINVAL for a NULL context, a negative or NaN threshold. */
+int negf_set_mixed_threshold(negf_ctx* ctx, double thr);
+
+/* Mixed precision: for each of the first n points of the last forward sweep
+ * (batch order, n <= its np), the largest ||I - A X0||_F over that point's slabs,
+ * written to the DEVICE array out[n] on `stream`.  The FP32 recursion loses
+ * about this factor times its rounding unit on ill-conditioned points, so a
+ * caller can redo points above a bound in FP64.
+ * Errors: NEGF_EINVAL (NULL, n < 1), NEGF_ESTATE (not a mixed context, or no
+ * forward sweep yet), NEGF_ESHAPE (n larger than the sweep). */
+int negf_mixed_point_residuals(negf_ctx* ctx, void* stream, int n, double* out);
 
 /* Kernel timing of the dominant kernel family (the batched complex GEMM):
  * enable = 1 records a HIP event pair around every GEMM launch on the launch

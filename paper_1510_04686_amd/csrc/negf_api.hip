@@ -53,10 +53,11 @@ struct negf_ctx {
     double* dual_partial = nullptr;
     int* d_count = nullptr;
     int* status = nullptr;
-    double* ns_res = nullptr;     // [cap] mixed-precision residual per point
+    double* ns_res = nullptr;     // [cap] largest refinement residual of each point in the last forward sweep
     int* ns_flag = nullptr;       // [cap] fallback flag per point
     int* ns_count = nullptr;      // device fallback counter
     double* ns_max = nullptr;     // device: per-point max residual history (max)
+    double ns_thr = 1e-2;         // ||I - M X0||_F above which a block inverse is redone in FP64
     int adj_K = 0, adj_nseg = 0;  // adjoint checkpoint segment length and count
     double2* adj_yseg = nullptr;  // [cap][K][nb][nb]  y of the segment being swept
     double2* adj_xseg = nullptr;  // [cap][K][nb][nb]  x of the segment being swept
@@ -250,8 +251,10 @@ __global__ void copy_d_kernel(const double* a, double* b, int n) {
     if (i < n) b[i] = a[i];
 }
 
-// Mixed precision: per-point max |R_ij| of the refinement residual; flags a
-// fallback when it exceeds `thr`.
+// Mixed precision: per-point Frobenius norm of the refinement residual
+// R = I - M X0; flags a fallback when it exceeds `thr`.  ||R||_F bounds the
+// spectral norm, so below the threshold one Newton-Schulz step X1 = X0 + X0 R
+// leaves a relative inverse error of at most ||R||_F^2 (plus FP32 rounding).
 __global__ __launch_bounds__(256) void ns_check_kernel(const double2* R, long long sR, int n, int np, Active act,
                                                        double thr, double* res, int* flag, int* count, double* histmax,
                                                        int* status) {
@@ -264,19 +267,19 @@ __global__ __launch_bounds__(256) void ns_check_kernel(const double2* R, long lo
         const double2* X = R + q * sR;
         for (long long i = threadIdx.x; i < (long long)n * n; i += 256) {
             double2 v = X[i];
-            double a = fmax(fabs(v.x), fabs(v.y));
-            if (!(a <= m)) m = (a == a) ? a : INFINITY;
+            m = fma(v.x, v.x, fma(v.y, v.y, m));
         }
     }
     red[threadIdx.x] = m;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        double r = on ? red[0] : 0.0;
-        res[q] = r;
+        double r = on ? sqrt(red[0]) : 0.0;
+        if (!(r == r)) r = INFINITY;
+        if (on && r > res[q]) res[q] = r;
         int f = (on && !(r <= thr)) ? 1 : 0;
         flag[q] = f;
         if (f) { atomicAdd(count, 1); raise_status(status, ST_FALLBACK); }
@@ -607,6 +610,10 @@ int negf_rgf_forward(negf_ctx* c, void* stream, int p0, int np, const negf_c128*
     const bool wantT = (flags & NEGF_WANT_TRANSMISSION) != 0;
     const double2* sL = reinterpret_cast<const double2*>(sigma_L);
     const double2* sR = reinterpret_cast<const double2*>(sigma_R);
+    if (mixed) {
+        hipLaunchKernelGGL(zero_d_kernel, dim3((np + 255) / 256), dim3(256), 0, s, c->ns_res, np);
+        NEGF_HIP_CHECK(hipGetLastError());
+    }
     for (int i = 0; i < maxN; ++i) {
         int hi;
         long long cnt;
@@ -632,13 +639,13 @@ int negf_rgf_forward(negf_ctx* c, void* stream, int p0, int np, const negf_c128*
             GemmArgs G = gargs(n, hi, act);
             G.A = c->tmp[0]; G.sA = nn; G.B = c->tmp[2]; G.sB = nn; G.C = c->tmp[1]; G.sC = nn;
             NEGF_HIP_CHECK(run_gemm(c, s, GemmTypes{DT_C128, DT_C64, DT_C128, DT_C128}, OP_N, OP_N, EPI_IMINUS, G, cnt));
-            hipLaunchKernelGGL(ns_check_kernel, dim3(hi), dim3(256), 0, s, c->tmp[1], nn, n, hi, all, 1e-2,
+            hipLaunchKernelGGL(ns_check_kernel, dim3(hi), dim3(256), 0, s, c->tmp[1], nn, n, hi, all, c->ns_thr,
                                c->ns_res, c->ns_flag, c->ns_count, c->ns_max, c->status);
             NEGF_HIP_CHECK(hipGetLastError());
             G.A = c->tmp[2]; G.B = c->tmp[1]; G.D = c->tmp[2]; G.sD = nn; G.C = slot(c, c->gst, i); G.sC = sst;
             NEGF_HIP_CHECK(run_gemm(c, s, GemmTypes{DT_C64, DT_C128, DT_C64, DT_C64}, OP_N, OP_N, EPI_ADD, G, cnt));
             // FP64 fallback for flagged points (M is still in tmp[0]).
-            Active fb{c->desc_d, p0, i, PRED_FLAG, c->ns_flag};
+            Active fb{c->desc_d, p0, i, PRED_SET, c->ns_flag};
             NEGF_HIP_CHECK(inverse_launch(s, DT_C128, c->tmp[0], nn, c->tmp[1], nn, n, hi, fb, invwork(c, c->tmp[3])));
             NEGF_HIP_CHECK(copy_launch(s, DT_C128, DT_C64, c->tmp[1], nn, slot(c, c->gst, i), sst, nn, hi, fb));
         }
@@ -1018,6 +1025,21 @@ int negf_mixed_stats(negf_ctx* c, void* stream, long long* n_fallback, double* m
     hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, s, c->ns_count, 0, 1);
     hipLaunchKernelGGL(zero_d_kernel, dim3((c->cap + 255) / 256), dim3(256), 0, s, c->ns_max, c->cap);
     NEGF_HIP_CHECK(hipGetLastError());
+    return NEGF_OK;
+}
+
+int negf_mixed_point_residuals(negf_ctx* c, void* stream, int n, double* out) {
+    if (!c || !out || n < 1) return NEGF_EINVAL;
+    if (c->prec != NEGF_MIXED || !c->fwd_done) return NEGF_ESTATE;
+    if (n > c->fwd_np) return NEGF_ESHAPE;
+    hipLaunchKernelGGL(copy_d_kernel, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, c->ns_res, out, n);
+    NEGF_HIP_CHECK(hipGetLastError());
+    return NEGF_OK;
+}
+
+int negf_set_mixed_threshold(negf_ctx* c, double thr) {
+    if (!c || !(thr >= 0.0)) return NEGF_EINVAL;
+    c->ns_thr = thr;
     return NEGF_OK;
 }
 

@@ -64,6 +64,7 @@ enum Pred : int {
     PRED_BWD = 2,       // backward recursion step: step < n_slab - 1
     PRED_FLAG = 3,      // flags[q] == 0 (lead decimation not yet converged)
     PRED_INIT = 4,      // last slab of the point: step == n_slab - 1
+    PRED_SET = 5,       // flags[q] != 0 (mixed precision: block inverse to redo in FP64)
 };
 
 struct Active {
@@ -75,6 +76,7 @@ struct Active {
     __device__ inline bool operator()(int q) const {
         if (mode == PRED_ALL) return true;
         if (mode == PRED_FLAG) return flags[q] == 0;
+        if (mode == PRED_SET) return flags[q] != 0;
         int ns = desc[p0 + q].w;
         if (mode == PRED_FWD) return step < ns;
         if (mode == PRED_BWD) return step < ns - 1;

@@ -21,6 +21,7 @@ _lib = None
 NEGF_FP64 = 0
 NEGF_MIXED = 1
 NEGF_WANT_TRANSMISSION = 1
+NEGF_WNOCONV, NEGF_WSINGULAR, NEGF_WNONFINITE, NEGF_WFALLBACK = 1, 2, 3, 4
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "ENOMEM", -4: "EHIP", -5: "ESTATE",
           1: "WNOCONV", 2: "WSINGULAR", 3: "WNONFINITE", 4: "WFALLBACK"}
@@ -56,7 +57,7 @@ EXPORTS = [
     "negf_create", "negf_destroy", "negf_workspace_bytes", "negf_sync_status", "negf_error_string",
     "negf_bind", "negf_lead_selfenergy", "negf_lead_selfenergy_pair", "negf_rgf_forward", "negf_rgf_backward",
     "negf_scba_selfenergy", "negf_observables", "negf_rgf_adjoint", "negf_zgemm_batched", "negf_zinv_batched", "negf_mixed_stats",
-    "negf_gemm_timing_enable", "negf_gemm_timing", "negf_get_tuning", "negf_set_tuning", "negf_autotune",
+    "negf_set_mixed_threshold", "negf_mixed_point_residuals", "negf_gemm_timing_enable", "negf_gemm_timing", "negf_get_tuning", "negf_set_tuning", "negf_autotune",
 ]
 
 
@@ -86,6 +87,8 @@ def lib():
         "negf_zgemm_batched": (i, [vp, vp, i, i, i, i, vp, vp, vp, i]),
         "negf_zinv_batched": (i, [vp, vp, i, i, vp, vp, i]),
         "negf_mixed_stats": (i, [vp, vp, POINTER(ll), POINTER(d)]),
+        "negf_set_mixed_threshold": (i, [vp, d]),
+        "negf_mixed_point_residuals": (i, [vp, vp, i, vp]),
         "negf_gemm_timing_enable": (i, [vp, i]),
         "negf_gemm_timing": (i, [vp, vp, POINTER(ll), POINTER(d), POINTER(d)]),
         "negf_get_tuning": (i, [vp, POINTER(negf_tuning)]),
@@ -276,6 +279,20 @@ def negf_mixed_stats(ctx, stream=None):
     mr = c_double()
     _check("negf_mixed_stats", lib().negf_mixed_stats(ctx.handle, _stream(stream), ctypes.byref(nf), ctypes.byref(mr)))
     return int(nf.value), float(mr.value)
+
+
+def negf_set_mixed_threshold(ctx, thr):
+    """Refinement residual ||I - A X0||_F above which a mixed-precision block
+    inverse is redone in FP64 (0: always, inf: only non-finite residuals)."""
+    _check("negf_set_mixed_threshold", lib().negf_set_mixed_threshold(ctx.handle, float(thr)))
+
+
+def negf_mixed_point_residuals(ctx, out, n=None, stream=None):
+    """Per-point largest refinement residual of the last mixed forward sweep
+    into the float64 device tensor `out` (first n points of the batch)."""
+    n = out.numel() if n is None else int(n)
+    _check("negf_mixed_point_residuals",
+           lib().negf_mixed_point_residuals(ctx.handle, _stream(stream), n, _ptr(out, torch.float64, "out")))
 
 
 def negf_gemm_timing_enable(ctx, enable=True):

@@ -29,14 +29,20 @@ class RGFSolver:
     """Batched RGF over every (sample, k, E) point of a workload on one GPU."""
 
     def __init__(self, wl, precision="fp64", capacity=None, device="cuda", mem_fraction=0.6, adjoint_segment=0,
-                 tune=None, lanes=1):
+                 tune=None, lanes=1, point_redo=0.03):
         """tune: None keeps the library's default kernel shapes; "auto" measures
         them on this context once (negf_autotune) and caches the choice per
         (device, block, capacity, precision); a dict sets them explicitly.
         lanes: batches in flight at once, each on its own context and HIP
         stream (default priority), so the latency-bound phases of one batch
         (the inverse's panels) overlap the matrix-core phases of another;
-        `capacity` is then the points per batch of each lane."""
+        `capacity` is then the points per batch of each lane.
+        point_redo (mixed precision only): after each pass, every point whose
+        largest block-refinement residual ||I - M X0||_F exceeds this bound is
+        solved again on an FP64 context and its outputs replaced.  The FP32
+        recursion loses roughly that residual in relative accuracy on a point
+        (its conditioning), so the bound trades accuracy against the share of
+        points redone; math.inf turns the redo off."""
         self.wl = wl
         self.device = torch.device(device)
         self.prec = N.NEGF_MIXED if precision == "mixed" else N.NEGF_FP64
@@ -82,6 +88,11 @@ class RGFSolver:
             N.negf_set_tuning(c, self.tuning["gemm_prefetch"], self.tuning["inv_outer"])
         self._last_fwd = None
         self.eta_fill = 0
+        mixed = self.prec == N.NEGF_MIXED
+        self.point_redo = float(point_redo) if mixed else math.inf
+        self.resid = torch.zeros(self.n_points, dtype=torch.float64, device=self.device) if mixed else None
+        self.redo_ctx = None
+        self.points_redone = 0
         self._bind()
         self.sigma_L = self.sigma_R = None
         self.lead_dual = 0
@@ -179,11 +190,46 @@ class RGFSolver:
             N.negf_rgf_forward(ctx, p0, np_, self.sigma_L, self.sigma_R, scat_R, scat_L, flags, stream=st)
             if lane == 0:
                 self._last_fwd = (p0, np_)
+            if self.resid is not None:
+                N.negf_mixed_point_residuals(ctx, self.resid[p0:p0 + np_], stream=st)
             N.negf_rgf_backward(ctx, p0, np_, out.get("GR"), out.get("GL"), out.get("GG"),
                                 int(full_blocks), self.slab_stride, out.get("bond"), out.get("T"), stream=st)
         if self.lanes > 1:
             for ls in self.streams:          # join
                 base.wait_stream(ls)
+        if math.isfinite(self.point_redo) and not torch.cuda.is_current_stream_capturing():
+            self._redo(out, full_blocks, want_T, scat_R, scat_L, base)
+
+    def _redo(self, out, full_blocks, want_T, scat_R, scat_L, stream):
+        """FP64 pass over the points whose mixed-precision residual exceeded
+        `point_redo`; their outputs replace the mixed ones in place."""
+        with torch.cuda.stream(stream):
+            idx = torch.nonzero(self.resid > self.point_redo).flatten()
+        self.points_redone = int(idx.numel())          # synchronises the stream
+        if self.points_redone == 0:
+            return
+        wl, nb = self.wl, self.wl.nb
+        if self.redo_ctx is None:
+            per_point = 2 * self.n_slab_max * nb * nb * 16 + 24 * nb * nb * 16 + (64 + 2 * 256 + 64) * nb * 16
+            free, _ = torch.cuda.mem_get_info(self.device)
+            cap = int(max(1, min(64, self.capacity, (free // 2) // per_point)))
+            self.redo_ctx = N.negf_create(nb, self.n_slab_max, cap, N.NEGF_FP64, 0)
+            self.redo_cap = cap
+        pts = self.points[idx.cpu().numpy()]
+        N.negf_bind(self.redo_ctx, wl.nb, wl.slab_offset, wl.n_k, wl.n_e, self.h_diag, self.h_up, 0, wl.up_block,
+                    self.v, self.energy, wl.eta, wl.mu_L, wl.mu_R, wl.kT, self.eta_fill, pts)
+        R = len(pts)
+        sub = {k: torch.zeros((R,) + tuple(v.shape[1:]), dtype=v.dtype, device=self.device) for k, v in out.items()}
+        flags = N.NEGF_WANT_TRANSMISSION if want_T else 0
+        for q0 in range(0, R, self.redo_cap):
+            nq = min(self.redo_cap, R - q0)
+            N.negf_rgf_forward(self.redo_ctx, q0, nq, self.sigma_L, self.sigma_R, scat_R, scat_L, flags,
+                               stream=stream)
+            N.negf_rgf_backward(self.redo_ctx, q0, nq, sub.get("GR"), sub.get("GL"), sub.get("GG"),
+                                int(full_blocks), self.slab_stride, sub.get("bond"), sub.get("T"), stream=stream)
+        with torch.cuda.stream(stream):
+            for k, v in out.items():
+                v.index_copy_(0, idx, sub[k])
 
     def solve(self, full_blocks=False, want=("GR", "GL", "GG", "bond"), want_T=False, scat_R=None, scat_L=None):
         if self.sigma_L is None:
@@ -233,7 +279,13 @@ class RGFSolver:
         return g
 
     def status(self):
-        codes = [N.negf_sync_status(c) for c in self.ctxs]
+        """Most severe device status over the contexts (non-finite pivot, zero
+        pivot, then mixed-precision fallback), cleared by the call."""
+        ctxs = self.ctxs + ([self.redo_ctx] if self.redo_ctx is not None else [])
+        codes = [N.negf_sync_status(c) for c in ctxs]
+        for code in (N.NEGF_WNONFINITE, N.NEGF_WSINGULAR, N.NEGF_WFALLBACK):
+            if code in codes:
+                return code
         return max(codes)
 
     # ------------------------------------------------------------------ SCBA
@@ -245,6 +297,8 @@ class RGFSolver:
         wl = self.wl
         assert wl.n_samples == 1
         n_iter = wl.n_scba if n_iter is None else n_iter
+        if math.isfinite(self.point_redo):
+            graph = False      # the mixed-precision point redo decides on the host after every pass
         if self.sigma_L is None:
             self.lead_selfenergies()
         Ns = wl.total_slabs

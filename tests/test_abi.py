@@ -61,6 +61,7 @@ def test_calls_reject_null_context(lib):
     assert lib.negf_observables(None, None, None, None, 1, None, None, 2.0, 1, None, None, None) == -1
     assert lib.negf_zgemm_batched(None, None, 4, 1, 0, 0, None, None, None, 0) == -1
     assert lib.negf_zinv_batched(None, None, 4, 1, None, None, 0) == -1
+    assert lib.negf_set_mixed_threshold(None, ctypes.c_double(1e-2)) == -1
 
 
 def test_error_strings(lib):

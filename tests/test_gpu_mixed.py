@@ -2,6 +2,7 @@
 FP64-residual Newton-Schulz step per block inverse, FP64 leads and FP64
 accumulation of density and current) against the FP64 oracle at the 1e-4
 relative bound on densities and currents."""
+import math
 import sys
 
 import numpy as np
@@ -28,6 +29,8 @@ def _run(wl, precision, **kw):
     n, J, _ = s.observables(out["GL"], out["bond"])
     torch.cuda.synchronize()
     stats = N.negf_mixed_stats(s.ctx) if precision == "mixed" else (0, 0.0)
+    if precision == "mixed" and s.redo_ctx is not None:
+        assert s.status() in (0, N.NEGF_WFALLBACK)
     return s, out, n.cpu().numpy(), J.cpu().numpy(), stats
 
 
@@ -45,7 +48,8 @@ def test_mixed_density_and_current_within_1e4(case):
         wl = random_tiny(20, 5, n_e=6, seed=31, up_block=10, eta=1e-3)
     else:
         wl = make_workload("C2", n_slab=6, n_e=4, n_k=2)
-    s, out, n, J, (nfb, maxres) = _run(wl, "mixed")
+    # the FP32 recursion alone: no point is handed to the FP64 redo
+    s, out, n, J, (nfb, maxres) = _run(wl, "mixed", point_redo=math.inf)
     _say(f"  fallbacks={nfb} max NS residual={maxres:.2e}")
     pts = [tuple(p) for p in s.points]
     ref, rn, rJ = _oracle_obs(wl, pts)
@@ -62,6 +66,83 @@ def test_mixed_matches_fp64_gpu_path_and_reports_stats():
     _say("mixed vs fp64 gpu")
     wl = make_workload("C2", n_slab=8, n_e=6, n_k=1)
     _, _, n64, J64, _ = _run(wl, "fp64")
-    s, _, n32, J32, (nfb, maxres) = _run(wl, "mixed")
+    s, _, n32, J32, (nfb, maxres) = _run(wl, "mixed", point_redo=math.inf)
     assert maxres < 1e-2 or nfb > 0
     assert np.max(np.abs(n32 - n64)) / np.max(np.abs(n64)) < TOL_MIXED
+
+
+def test_mixed_fallback_redoes_the_flagged_inverse_in_fp64():
+    """A slab cut off from its neighbours whose block has condition number
+    ~1e8 at one energy (one eigenvalue 1e5, one exactly at E, broadened by
+    eta = 1e-3): the FP32 inverse cannot reach the refinement threshold there,
+    so that block must be redone in FP64 and G^R on that slab must still match
+    the oracle; the other points keep the 1e-4 bound."""
+    import dataclasses
+    _say("mixed precision fallback on an ill-conditioned isolated slab")
+    base = random_tiny(32, 5, n_e=3, seed=47, up_block=8, eta=1e-3)
+    rng = np.random.default_rng(4747)
+    q, _ = np.linalg.qr(rng.normal(size=(32, 32)) + 1j * rng.normal(size=(32, 32)))
+    e0 = 0.3
+    d = rng.uniform(-1.0, 1.0, size=32)
+    d[0], d[1] = 1e5, e0
+    h_diag = base.h_diag.copy()
+    h_diag[0, 2] = (q * d) @ q.conj().T
+    h_up = base.h_up.copy()
+    h_up[1] = 0.0
+    h_up[2] = 0.0
+    wl = dataclasses.replace(base, h_diag=h_diag, h_up=h_up, energy=np.array([e0, e0 + 0.05, -0.4]))
+    s, out, n, J, (nfb, maxres) = _run(wl, "mixed", point_redo=math.inf)
+    _say(f"  fallbacks={nfb} max NS residual={maxres:.2e} status={s.status()}")
+    assert nfb >= 1 and maxres > 1e-2
+    assert s.status() in (0, 4)
+    pts = [tuple(p) for p in s.points]
+    ref, rn, rJ = _oracle_obs(wl, pts)
+    GR = out["GR"].cpu().numpy()
+    for p, r in zip(range(len(pts)), ref):
+        dr = np.diagonal(r["GR"], axis1=1, axis2=2)
+        err = np.max(np.abs(GR[p] - dr)) / np.max(np.abs(dr))
+        _say(f"  point {pts[p]} G^R err {err:.2e}")
+        assert err < TOL_MIXED
+    assert np.max(np.abs(n - rn)) / np.max(np.abs(rn)) < TOL_MIXED
+
+
+def test_mixed_ragged_alloy_samples_with_point_redo():
+    """Alloy samples of different lengths (block 400, eta = 1e-6) over the full
+    energy window.  Some points sit on resonances sharp enough that the FP32
+    recursion cannot resolve them at all (the oracle's own two FP64 evaluations
+    already drift apart by ~1e-9 there, i.e. a condition number ~1e7); their
+    block-refinement residual exposes them and the point redo solves them in
+    FP64.  Redone points must equal the FP64 path exactly (same kernels, per
+    point); every other point keeps a relative error of about its residual, so
+    the per-sample density is held to the redo bound."""
+    _say("mixed vs fp64 gpu on two ragged alloy samples, with the FP64 point redo")
+    wl = make_workload("C4", n_samples=2, n_e=64)
+    s64, o64, n64, J64, _ = _run(wl, "fp64")
+    bound = 0.03
+    s, om, n32, J32, (nfb, maxres) = _run(wl, "mixed", point_redo=bound)
+    resid = s.resid.cpu().numpy()
+    redo = np.nonzero(resid > bound)[0]
+    _say(f"  fallbacks={nfb} max block residual={maxres:.2e} points redone={s.points_redone}/{s.n_points}")
+    assert s.points_redone == len(redo) > 0
+    assert resid.max() > 1.0                        # the unresolvable points are among them
+    for k in ("GR", "GL", "bond"):
+        a, b = om[k].cpu().numpy()[redo], o64[k].cpu().numpy()[redo]
+        assert np.array_equal(a, b), k
+    for j in range(wl.n_samples):
+        a0, a1 = int(wl.slab_offset[j]), int(wl.slab_offset[j + 1])
+        err = np.max(np.abs(n32[a0:a1] - n64[a0:a1])) / np.max(np.abs(n64[a0:a1]))
+        _say(f"  sample {j} ({a1 - a0} slabs) density err {err:.2e}")
+        assert err < bound
+
+
+def test_mixed_point_redo_everywhere_is_the_fp64_path():
+    """point_redo = 0 hands every point to the FP64 context: the outputs must be
+    those of the FP64 path bit for bit (ragged samples, two batches)."""
+    _say("mixed with every point redone vs fp64")
+    wl = make_workload("C4", n_samples=3, n_slab=8, n_e=6)
+    _, o64, n64, J64, _ = _run(wl, "fp64", capacity=8)
+    s, om, n32, J32, _ = _run(wl, "mixed", capacity=8, point_redo=0.0)
+    assert s.points_redone == s.n_points
+    for k in ("GR", "GL", "GG", "bond"):
+        assert np.array_equal(om[k].cpu().numpy(), o64[k].cpu().numpy()), k
+    assert np.array_equal(n32, n64) and np.array_equal(J32, J64)
