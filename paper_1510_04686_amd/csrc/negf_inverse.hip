@@ -444,10 +444,10 @@ __global__ __launch_bounds__(256) void gj_update(UpdArgs a) {
     auto store = [&](int b) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            Es[b][0][ek + j][eo] = re[j].x;
-            Es[b][1][ek + j][eo] = re[j].y;
-            Ps[b][0][pk][poc + j] = rp[j].x;
-            Ps[b][1][pk][poc + j] = rp[j].y;
+            Es[b][0][ek + j][swz(ek + j, eo)] = re[j].x;
+            Es[b][1][ek + j][swz(ek + j, eo)] = re[j].y;
+            Ps[b][0][pk][swz(pk, poc + j)] = rp[j].x;
+            Ps[b][1][pk][swz(pk, poc + j)] = rp[j].y;
         }
     };
     // Gathered rows of the old matrix (or the transform columns inside the K range),

@@ -33,6 +33,11 @@ constexpr int BM = 64;   // tile rows = tile cols
 constexpr int BK = 16;   // K slice
 constexpr int LP = 80;   // LDS row stride (elements): rows k, k+1 of a fragment read land on disjoint banks
 
+// LDS column of element (k, c) of a staged slice: the halves of a 64-column
+// row swap on odd groups of four k, so the four k rows one store instruction
+// of the row-outer pattern touches fall on two bank halves instead of one.
+__device__ __host__ constexpr int swz(int k, int c) { return c ^ (((k >> 2) & 1) << 4); }
+
 // Loads one K slice of op(X) into registers.
 //   OUTER_K = false ("pattern X"): 64 source rows (outer index), 16 contiguous k.
 //   OUTER_K = true  ("pattern Y"): 16 source rows (k), 64 contiguous outer indices.
@@ -61,15 +66,15 @@ __device__ inline void store_slice(Acc (*S)[BK][LP], int tid, const TX (&r)[4]) 
         int o = tid >> 2, k = (tid & 3) * 4;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            S[0][k + j][o] = (Acc)r[j].x;
-            S[1][k + j][o] = CONJ ? -(Acc)r[j].y : (Acc)r[j].y;
+            S[0][k + j][swz(k + j, o)] = (Acc)r[j].x;
+            S[1][k + j][swz(k + j, o)] = CONJ ? -(Acc)r[j].y : (Acc)r[j].y;
         }
     } else {
         int k = tid >> 4, o = (tid & 15) * 4;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            S[0][k][o + j] = (Acc)r[j].x;
-            S[1][k][o + j] = CONJ ? -(Acc)r[j].y : (Acc)r[j].y;
+            S[0][k][swz(k, o + j)] = (Acc)r[j].x;
+            S[1][k][swz(k, o + j)] = CONJ ? -(Acc)r[j].y : (Acc)r[j].y;
         }
     }
 }
@@ -78,34 +83,41 @@ template <typename Acc, int MI, int NJ>
 __device__ inline void mma_slice(Acc (*As)[BK][LP], Acc (*Bs)[BK][LP], int lane, int wm, int wn,
                                  typename MF<Acc>::V (&cr)[2][2], typename MF<Acc>::V (&ci)[2][2]) {
     const int o = lane & 15;
-#pragma unroll
-    for (int kk = 0; kk < BK / 4; ++kk) {
+    // Fragments of step kk + 1 are read from LDS into the other register set
+    // while the products of step kk run.
+    Acc ar[2][MI], ai[2][MI], br[2][NJ], bi[2][NJ];
+    auto frag = [&](int kk, int set) {
         const int k = kk * 4 + (lane >> 4);
-        Acc ar[MI], ai[MI], nai[MI], br[NJ], bi[NJ];
 #pragma unroll
         for (int mi = 0; mi < MI; ++mi) {
-            ar[mi] = As[0][k][wm * 32 + mi * 16 + o];
-            ai[mi] = As[1][k][wm * 32 + mi * 16 + o];
-            nai[mi] = -ai[mi];
+            ar[set][mi] = As[0][k][swz(k, wm * 32 + mi * 16 + o)];
+            ai[set][mi] = As[1][k][swz(k, wm * 32 + mi * 16 + o)];
         }
 #pragma unroll
         for (int nj = 0; nj < NJ; ++nj) {
-            br[nj] = Bs[0][k][wn * 32 + nj * 16 + o];
-            bi[nj] = Bs[1][k][wn * 32 + nj * 16 + o];
+            br[set][nj] = Bs[0][k][swz(k, wn * 32 + nj * 16 + o)];
+            bi[set][nj] = Bs[1][k][swz(k, wn * 32 + nj * 16 + o)];
         }
+    };
+    frag(0, 0);
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk) {
+        const int c = kk & 1;
+        if (kk + 1 < BK / 4) frag(kk + 1, c ^ 1);
+        __builtin_amdgcn_sched_barrier(0);   // the reads stay ahead of this step's products
 #pragma unroll
         for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
             for (int nj = 0; nj < NJ; ++nj) {
-                cr[mi][nj] = MF<Acc>::mma(ar[mi], br[nj], cr[mi][nj]);
-                ci[mi][nj] = MF<Acc>::mma(ar[mi], bi[nj], ci[mi][nj]);
+                cr[mi][nj] = MF<Acc>::mma(ar[c][mi], br[c][nj], cr[mi][nj]);
+                ci[mi][nj] = MF<Acc>::mma(ar[c][mi], bi[c][nj], ci[mi][nj]);
             }
 #pragma unroll
         for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
             for (int nj = 0; nj < NJ; ++nj) {
-                cr[mi][nj] = MF<Acc>::mma(nai[mi], bi[nj], cr[mi][nj]);
-                ci[mi][nj] = MF<Acc>::mma(ai[mi], br[nj], ci[mi][nj]);
+                cr[mi][nj] = MF<Acc>::mma(-ai[c][mi], bi[c][nj], cr[mi][nj]);
+                ci[mi][nj] = MF<Acc>::mma(ai[c][mi], br[c][nj], ci[mi][nj]);
             }
     }
 }
