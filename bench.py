@@ -229,7 +229,13 @@ def main():
                                                          "copy-calibrated)",
                      "algorithmic_bytes_per_launch": 3 * 16 * wl.nb ** 2 * point_launches / launches if launches else None,
                      "launches": launches, "points_per_launch": point_launches / launches if launches else None,
-                     "avg_launch_ms": gemm_ms / launches if launches else None},
+                     "avg_launch_ms": gemm_ms / launches if launches else None,
+                     # achieved counts 8 b^3 real flops per complex product (the algorithmic
+                     # count); FP64 products run as three real MFMA products (3M), so the
+                     # matrix cores execute 3/4 of that
+                     "mfma_flops_per_algorithmic_flop": 0.75 if args.precision == "fp64" else 1.0,
+                     "executed_mfma_frac": ((0.75 if args.precision == "fp64" else 1.0) * achieved / peak)
+                     if achieved else None},
         "status": N.STATUS.get(st, st),
     }
     if args.workload == "C3":

@@ -5,8 +5,8 @@
 // point of a batch.  One launch covers the whole batch: a 64 x 64 output tile
 // of one point per 256-thread workgroup (4 wavefronts of 32 x 32), K staged
 // through LDS in 16-wide double-buffered slices, split real/imaginary planes.
-// A complex product is four real MFMA products (re*re - im*im, re*im + im*re)
-// on v_mfma_f64_16x16x4f64 (FP64) or v_mfma_f32_16x16x4f32 (FP32).
+// A complex product is three real MFMA products on v_mfma_f64_16x16x4f64
+// (FP64, the 3M form) or four on v_mfma_f32_16x16x4f32 (FP32).
 #include "negf_internal.hpp"
 #include "negf_mfma.hpp"
 
@@ -16,11 +16,12 @@ static_assert(BM == 64, "gemm_tiles() assumes 64-wide tiles");
 
 template <typename Acc>
 __device__ inline void mma_tile(Acc (*As)[BK][LP], Acc (*Bs)[BK][LP], int lane, int wm, int wn, int nmi, int nnj,
-                                typename MF<Acc>::V (&cr)[2][2], typename MF<Acc>::V (&ci)[2][2]) {
-    if (nmi == 2 && nnj == 2) mma_slice<Acc, 2, 2>(As, Bs, lane, wm, wn, cr, ci);
-    else if (nmi == 2 && nnj == 1) mma_slice<Acc, 2, 1>(As, Bs, lane, wm, wn, cr, ci);
-    else if (nmi == 1 && nnj == 2) mma_slice<Acc, 1, 2>(As, Bs, lane, wm, wn, cr, ci);
-    else if (nmi == 1 && nnj == 1) mma_slice<Acc, 1, 1>(As, Bs, lane, wm, wn, cr, ci);
+                                typename MF<Acc>::V (&cr)[2][2], typename MF<Acc>::V (&ci)[2][2],
+                                typename MF<Acc>::V (&cs)[2][2]) {
+    if (nmi == 2 && nnj == 2) mma_slice<Acc, 2, 2>(As, Bs, lane, wm, wn, cr, ci, cs);
+    else if (nmi == 2 && nnj == 1) mma_slice<Acc, 2, 1>(As, Bs, lane, wm, wn, cr, ci, cs);
+    else if (nmi == 1 && nnj == 2) mma_slice<Acc, 1, 2>(As, Bs, lane, wm, wn, cr, ci, cs);
+    else if (nmi == 1 && nnj == 1) mma_slice<Acc, 1, 1>(As, Bs, lane, wm, wn, cr, ci, cs);
 }
 
 template <typename TA, typename TB, typename TC, typename Acc, int OPA, int OPB, int EPI, int PF>
@@ -55,13 +56,13 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     const int nmi = rowbase >= n ? 0 : (rowbase + 16 >= n ? 1 : 2);
     const int nnj = colbase >= n ? 0 : (colbase + 16 >= n ? 1 : 2);
 
-    typename MF<Acc>::V cr[2][2], ci[2][2];
+    typename MF<Acc>::V cr[2][2], ci[2][2], cs[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) { cr[a][b][r] = 0; ci[a][b][r] = 0; }
+            for (int r = 0; r < 4; ++r) { cr[a][b][r] = 0; ci[a][b][r] = 0; cs[a][b][r] = 0; }
 
     // op(A) slice: OPA = N -> rows m, contiguous k (pattern X); C -> rows k (pattern Y)
     // op(B) slice: OPB = N -> rows k (pattern Y); C -> rows n, contiguous k (pattern X)
@@ -83,7 +84,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
                 load_slice<TA, AK>(A, n, m0, (kt + 1) * BK, tid, ra);
                 load_slice<TB, BKR>(B, n, n0, (kt + 1) * BK, tid, rb);
             }
-            mma_tile<Acc>(As[buf], Bs[buf], lane, wm, wn, nmi, nnj, cr, ci);
+            mma_tile<Acc>(As[buf], Bs[buf], lane, wm, wn, nmi, nnj, cr, ci, cs);
             if (more) {
                 store_slice<Acc, TA, AK, OPA == OP_C>(As[buf ^ 1], tid, ra);
                 store_slice<Acc, TB, BKR, OPB == OP_C>(Bs[buf ^ 1], tid, rb);
@@ -110,7 +111,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
             load_slice<TA, AK>(A, n, m0, ((KT) + 2) * BK, tid, ra[CUR]);                                  \
             load_slice<TB, BKR>(B, n, n0, ((KT) + 2) * BK, tid, rb[CUR]);                                 \
         }                                                                                                 \
-        mma_tile<Acc>(As[CUR], Bs[CUR], lane, wm, wn, nmi, nnj, cr, ci);                                  \
+        mma_tile<Acc>(As[CUR], Bs[CUR], lane, wm, wn, nmi, nnj, cr, ci, cs);                                  \
         if ((KT) + 1 < nkt) {                                                                             \
             store_slice<Acc, TA, AK, OPA == OP_C>(As[NXT], tid, ra[NXT]);                                 \
             store_slice<Acc, TB, BKR, OPB == OP_C>(Bs[NXT], tid, rb[NXT]);                                \
@@ -123,6 +124,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
         }
 #undef NEGF_GEMM_STEP
     }
+    finish_products<Acc>(cr, ci, cs);
 
     TC* __restrict__ C = (TC*)g.C + q * g.sC;
     const TC* D = (const TC*)g.D + q * g.sD;

@@ -407,13 +407,13 @@ __global__ __launch_bounds__(256) void gj_update(UpdArgs a) {
             rsr[mi][r] = (row < n) ? rs[row] : 0;
         }
 
-    typename MF<R>::V cr[2][2], ci[2][2];
+    typename MF<R>::V cr[2][2], ci[2][2], cs[2][2];
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int y = 0; y < 2; ++y)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) { cr[x][y][r] = 0; ci[x][y][r] = 0; }
+            for (int r = 0; r < 4; ++r) { cr[x][y][r] = 0; ci[x][y][r] = 0; cs[x][y][r] = 0; }
     // K slices double-buffered through LDS, the next slice's reads in flight during
     // the current slice's products.  E tile: rows m0.., k (pattern X); pivot-row
     // tile: k rows, cols n0.. (pattern Y).
@@ -450,33 +450,11 @@ __global__ __launch_bounds__(256) void gj_update(UpdArgs a) {
             Ps[b][1][pk][swz(pk, poc + j)] = rp[j].y;
         }
     };
-    // Gathered rows of the old matrix (or the transform columns inside the K range),
-    // read while the last slice's products run.
-    C xo[2][2][4];
-    auto gather = [&]() {
-#pragma unroll
-        for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-            for (int nj = 0; nj < 2; ++nj) {
-                const int col = colbase + nj * 16 + (lane & 15);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = rowbase + mi * 16 + out_row<R>(lane, r);
-                    const bool in = mi < nmi && nj < nnj && row < n && col < cend;
-                    const bool inK = col >= k0 && col < k0 + nbk;
-                    xo[mi][nj][r].x = 0; xo[mi][nj][r].y = 0;
-                    if (in) {
-                        if (inK) xo[mi][nj][r] = E[(long long)row * a.ldE + (col - k0)];
-                        else xo[mi][nj][r] = X[(long long)rsr[mi][r] * ldX + (col - xc)];
-                    }
-                }
-            }
-    };
     auto mma = [&](int b) {
-        if (nmi == 2 && nnj == 2) mma_slice<R, 2, 2>(Es[b], Ps[b], lane, wm, wn, cr, ci);
-        else if (nmi == 2 && nnj == 1) mma_slice<R, 2, 1>(Es[b], Ps[b], lane, wm, wn, cr, ci);
-        else if (nmi == 1 && nnj == 2) mma_slice<R, 1, 2>(Es[b], Ps[b], lane, wm, wn, cr, ci);
-        else if (nmi == 1 && nnj == 1) mma_slice<R, 1, 1>(Es[b], Ps[b], lane, wm, wn, cr, ci);
+        if (nmi == 2 && nnj == 2) mma_slice<R, 2, 2>(Es[b], Ps[b], lane, wm, wn, cr, ci, cs);
+        else if (nmi == 2 && nnj == 1) mma_slice<R, 2, 1>(Es[b], Ps[b], lane, wm, wn, cr, ci, cs);
+        else if (nmi == 1 && nnj == 2) mma_slice<R, 1, 2>(Es[b], Ps[b], lane, wm, wn, cr, ci, cs);
+        else if (nmi == 1 && nnj == 1) mma_slice<R, 1, 1>(Es[b], Ps[b], lane, wm, wn, cr, ci, cs);
     };
     load(0);
     store(0);
@@ -489,13 +467,30 @@ __global__ __launch_bounds__(256) void gj_update(UpdArgs a) {
         __syncthreads();
     }
     mma((nsl - 1) & 1);
-    gather();   // behind the last products, which are still in flight
+    finish_products<R>(cr, ci, cs);
 
+    // Epilogue, one 16-row block at a time: gather the old rows (or the transform
+    // columns inside the K range) and write the new tile.
     C* Y = reinterpret_cast<C*>(a.Y) + q * a.sY;
     const int* cd = a.coldst + (long long)q * n;
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi) {
         if (mi >= nmi) break;
+        C xo[2][4];
+#pragma unroll
+        for (int nj = 0; nj < 2; ++nj) {
+            const int col = colbase + nj * 16 + (lane & 15);
+            const bool inK = col >= k0 && col < k0 + nbk;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = rowbase + mi * 16 + out_row<R>(lane, r);
+                xo[nj][r].x = 0; xo[nj][r].y = 0;
+                if (nj < nnj && row < n && col < cend) {
+                    if (inK) xo[nj][r] = E[(long long)row * a.ldE + (col - k0)];
+                    else xo[nj][r] = X[(long long)rsr[mi][r] * ldX + (col - xc)];
+                }
+            }
+        }
 #pragma unroll
         for (int nj = 0; nj < 2; ++nj) {
             if (nj >= nnj) break;
@@ -506,7 +501,7 @@ __global__ __launch_bounds__(256) void gj_update(UpdArgs a) {
             for (int r = 0; r < 4; ++r) {
                 const int row = rowbase + mi * 16 + out_row<R>(lane, r);
                 if (row < n && col < cend) {
-                    C v = xo[mi][nj][r];
+                    C v = xo[nj][r];
                     if (!inK) { v.x += cr[mi][nj][r]; v.y += ci[mi][nj][r]; }
                     Y[(long long)row * a.ldY + (ocol - a.ycol0)] = v;
                 }

@@ -79,9 +79,21 @@ __device__ inline void store_slice(Acc (*S)[BK][LP], int tid, const TX (&r)[4]) 
     }
 }
 
+// FP64 complex products use three real MFMA products (the 3M form): with
+// P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi), the product is
+// (P1 - P2) + i (P3 - P1 - P2).  That is 12 MFMAs per 16x16x4 complex step
+// instead of 16; the imaginary part's rounding is bounded by the unit roundoff
+// times (|Ar| + |Ai|)(|Br| + |Bi|) instead of |Ar||Bi| + |Ai||Br|.  FP32
+// (mixed precision) keeps the four-product form and its tighter bound.
+template <typename Acc> struct ThreeM { static constexpr bool value = sizeof(Acc) == 8; };
+
+// Accumulates one staged K slice into the 2 x 2 blocks of 16 x 16 this wave
+// owns.  With the 3M form cr, ci, cs hold P1, P2, P3 until finish_products();
+// otherwise cr, ci hold the real and imaginary parts and cs is unused.
 template <typename Acc, int MI, int NJ>
 __device__ inline void mma_slice(Acc (*As)[BK][LP], Acc (*Bs)[BK][LP], int lane, int wm, int wn,
-                                 typename MF<Acc>::V (&cr)[2][2], typename MF<Acc>::V (&ci)[2][2]) {
+                                 typename MF<Acc>::V (&cr)[2][2], typename MF<Acc>::V (&ci)[2][2],
+                                 typename MF<Acc>::V (&cs)[2][2]) {
     const int o = lane & 15;
     // Fragments of step kk + 1 are read from LDS into the other register set
     // while the products of step kk run.
@@ -105,20 +117,55 @@ __device__ inline void mma_slice(Acc (*As)[BK][LP], Acc (*Bs)[BK][LP], int lane,
         const int c = kk & 1;
         if (kk + 1 < BK / 4) frag(kk + 1, c ^ 1);
         __builtin_amdgcn_sched_barrier(0);   // the reads stay ahead of this step's products
+        if constexpr (ThreeM<Acc>::value) {
+            Acc sa[MI], sb[NJ];
 #pragma unroll
-        for (int mi = 0; mi < MI; ++mi)
+            for (int mi = 0; mi < MI; ++mi) sa[mi] = ar[c][mi] + ai[c][mi];
 #pragma unroll
-            for (int nj = 0; nj < NJ; ++nj) {
-                cr[mi][nj] = MF<Acc>::mma(ar[c][mi], br[c][nj], cr[mi][nj]);
-                ci[mi][nj] = MF<Acc>::mma(ar[c][mi], bi[c][nj], ci[mi][nj]);
-            }
+            for (int nj = 0; nj < NJ; ++nj) sb[nj] = br[c][nj] + bi[c][nj];
 #pragma unroll
-        for (int mi = 0; mi < MI; ++mi)
+            for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
-            for (int nj = 0; nj < NJ; ++nj) {
-                cr[mi][nj] = MF<Acc>::mma(-ai[c][mi], bi[c][nj], cr[mi][nj]);
-                ci[mi][nj] = MF<Acc>::mma(ai[c][mi], br[c][nj], ci[mi][nj]);
-            }
+                for (int nj = 0; nj < NJ; ++nj) {
+                    cr[mi][nj] = MF<Acc>::mma(ar[c][mi], br[c][nj], cr[mi][nj]);
+                    ci[mi][nj] = MF<Acc>::mma(ai[c][mi], bi[c][nj], ci[mi][nj]);
+                    cs[mi][nj] = MF<Acc>::mma(sa[mi], sb[nj], cs[mi][nj]);
+                }
+        } else {
+#pragma unroll
+            for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+                for (int nj = 0; nj < NJ; ++nj) {
+                    cr[mi][nj] = MF<Acc>::mma(ar[c][mi], br[c][nj], cr[mi][nj]);
+                    ci[mi][nj] = MF<Acc>::mma(ar[c][mi], bi[c][nj], ci[mi][nj]);
+                }
+#pragma unroll
+            for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+                for (int nj = 0; nj < NJ; ++nj) {
+                    cr[mi][nj] = MF<Acc>::mma(-ai[c][mi], bi[c][nj], cr[mi][nj]);
+                    ci[mi][nj] = MF<Acc>::mma(ai[c][mi], br[c][nj], ci[mi][nj]);
+                }
+        }
+    }
+}
+
+// Turns the 3M partial products into real and imaginary parts (no-op for the
+// four-product form).
+template <typename Acc>
+__device__ inline void finish_products(typename MF<Acc>::V (&cr)[2][2], typename MF<Acc>::V (&ci)[2][2],
+                                       const typename MF<Acc>::V (&cs)[2][2]) {
+    if constexpr (ThreeM<Acc>::value) {
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+            for (int nj = 0; nj < 2; ++nj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const Acc p1 = cr[mi][nj][r], p2 = ci[mi][nj][r];
+                    cr[mi][nj][r] = p1 - p2;
+                    ci[mi][nj][r] = (cs[mi][nj][r] - p1) - p2;
+                }
     }
 }
 
