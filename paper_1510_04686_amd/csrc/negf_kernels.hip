@@ -366,11 +366,18 @@ hipError_t extract_launch(hipStream_t s, int dt, const ExtArgs& a) {
 //   j_i = 2 Re[ Tr(U G U^dagger g^<_i) + sum_ab (U G^<)_ab conj(L_ab) ].
 // g^<_i is anti-Hermitian, so Tr(U G U^dagger g^<) = -sum_ab (U G)_ab conj((g^< U)_ab):
 // every factor is then read row-major, in the order the threads walk b.
-// One workgroup per (point, group of atom blocks) keeps the ub rows of G and
-// G^< it needs in registers; the partials are added in a fixed order.
+// One workgroup per (point, group of atom blocks) walks the columns in chunks
+// of whole coupling blocks: the ub rows of G, G^<, L and g^<_i at a thread's
+// column are read once from HBM (those of L as they are used), the g^<_i rows of the chunk are staged in LDS
+// for the column-block product g^< U, and the diagonal block of U for the
+// row-block products sits in LDS.  The partials are added in a fixed order.
 // ---------------------------------------------------------------------------
 template <typename TI, int UB>
 __global__ __launch_bounds__(256) void bond_rows_kernel(BondArgs a) {
+    constexpr int CW = (256 / UB) * UB;   // columns per chunk, whole coupling blocks
+    __shared__ double2 gsl[UB][CW];       // g^<_i rows r0.. of the chunk
+    __shared__ double2 ub[UB][UB];        // U[r0 + i][r0 + j]
+    __shared__ double red[256];
     const int q = blockIdx.x / BOND_NWB, w = blockIdx.x - q * BOND_NWB;
     if (q >= a.np || !a.act(q)) return;
     const int n = a.n, tid = threadIdx.x;
@@ -385,32 +392,42 @@ __global__ __launch_bounds__(256) void bond_rows_kernel(BondArgs a) {
     double acc = 0.0;
     for (int A = w; A < nblk; A += BOND_NWB) {
         const int r0 = A * UB;
-        for (int b = tid; b < n; b += 256) {
-            const int bb = (b / UB) * UB;
+        if (tid < UB * UB) ub[tid / UB][tid % UB] = U[(long long)(r0 + tid / UB) * n + r0 + tid % UB];
+        for (int c0 = 0; c0 < n; c0 += CW) {
+            const int b = c0 + tid;
+            const bool on = tid < CW && b < n;
             double2 gc[UB], glc[UB], uc[UB];
+            const int bb = on ? (b / UB) * UB : 0;
 #pragma unroll
             for (int j = 0; j < UB; ++j) {
-                gc[j] = cconv<double2>(G[(long long)(r0 + j) * n + b]);
-                glc[j] = cconv<double2>(GL[(long long)(r0 + j) * n + b]);
-                uc[j] = U[(long long)(bb + j) * n + b];
-            }
-#pragma unroll
-            for (int i = 0; i < UB; ++i) {
-                const long long r = r0 + i;
-                double2 ug = make_double2(0, 0), ugl = make_double2(0, 0), gu = make_double2(0, 0);
-#pragma unroll
-                for (int j = 0; j < UB; ++j) {
-                    const double2 u = U[r * n + r0 + j];
-                    cfma(ug, u, gc[j]);
-                    cfma(ugl, u, glc[j]);
-                    cfma(gu, cconv<double2>(GS[r * n + bb + j]), uc[j]);
+                const long long o = (long long)(r0 + j) * n + b;
+                if (on) {
+                    gc[j] = cconv<double2>(G[o]);
+                    glc[j] = cconv<double2>(GL[o]);
+                    uc[j] = U[(long long)(bb + j) * n + b];
+                    gsl[j][tid] = cconv<double2>(GS[o]);
                 }
-                const double2 l = cconv<double2>(L[r * n + b]);
-                acc += (ugl.x * l.x + ugl.y * l.y) - (ug.x * gu.x + ug.y * gu.y);
             }
+            __syncthreads();
+            if (on) {
+                const int lb = bb - c0;   // the thread's column block, chunk-local
+#pragma unroll
+                for (int i = 0; i < UB; ++i) {
+                    double2 ug = make_double2(0, 0), ugl = make_double2(0, 0), gu = make_double2(0, 0);
+#pragma unroll
+                    for (int j = 0; j < UB; ++j) {
+                        const double2 u = ub[i][j];
+                        cfma(ug, u, gc[j]);
+                        cfma(ugl, u, glc[j]);
+                        cfma(gu, gsl[i][lb + j], uc[j]);
+                    }
+                    const double2 l = cconv<double2>(L[(long long)(r0 + i) * n + b]);
+                    acc += (ugl.x * l.x + ugl.y * l.y) - (ug.x * gu.x + ug.y * gu.y);
+                }
+            }
+            __syncthreads();   // gsl (and ub, at the next row block) are rewritten next
         }
     }
-    __shared__ double red[256];
     red[tid] = acc;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
