@@ -145,45 +145,61 @@ __global__ __launch_bounds__(256) void sandwich_kernel(SandArgs a) {
     }
 }
 
-// The same operation without LDS, for the common block sizes (1, 2, 4, 8, 10, 16): one thread per
-// (block row of UB rows, column c).  It forms Y = X U for its UB rows at
-// column c (UB^2 reads of X shared, through L1, by the UB threads of a column
-// block), then O = U^dagger Y in registers and writes UB coalesced outputs.
-// UB and the operand forms are compile-time, so the loops carry no guards and
-// every read of a row group can be in flight at once.
+// The same operation for the common block sizes (1, 2, 4, 8, 10, 16): one
+// workgroup per (point, block row of UB rows, chunk of whole column blocks),
+// one thread per column.  Each thread reads its UB entries of X once
+// (coalesced); for X U they go through LDS, where every thread finds the UB
+// columns of its block; U^dagger Y mixes the thread's own rows in registers
+// with the diagonal block of U from LDS.  UB and the operand forms are
+// compile-time, so the loops carry no guards.
 template <typename TX, typename TO, int UB, int OPL, int OPR>
 __global__ __launch_bounds__(256) void sandwich_cols_kernel(SandArgs a) {
+    constexpr int CW = (256 / UB) * UB;   // columns per chunk
+    __shared__ double2 xs[OPR == 1 ? UB : 1][OPR == 1 ? CW : 1];
+    __shared__ double2 ul[OPL == 2 ? UB : 1][OPL == 2 ? UB : 1];
     const int n = a.n;
-    const int nblk = n / UB;
-    const long long work = (long long)nblk * n, per = (work + 255) / 256;
-    const int q = (int)(blockIdx.x / per);
+    const int nblk = n / UB, nch = (n + CW - 1) / CW;
+    const int per = nblk * nch;
+    const int q = blockIdx.x / per;
     if (q >= a.np || !a.act(q)) return;
-    const long long idx = (blockIdx.x - (long long)q * per) * 256 + threadIdx.x;
-    if (idx >= work) return;
-    const int blk = (int)(idx / n), c = (int)(idx - (long long)blk * n);
-    const int rb = blk * UB, cb = (c / UB) * UB;
+    const int t = blockIdx.x - q * per;
+    const int blk = t / nch, c0 = (t - blk * nch) * CW;
+    const int tid = threadIdx.x;
+    const int c = c0 + tid;
+    const bool on = tid < CW && c < n;
+    const int rb = blk * UB, cb = on ? (c / UB) * UB : 0;
     const int4 d = a.ps.desc[a.ps.p0 + q];
     const int ik = d.y, ie = d.z, ns = d.w;
     const long long sfirst = a.ps.slab_off[d.x];
     double2 y[UB];
 #pragma unroll
     for (int i = 0; i < UB; ++i) y[i] = make_double2(0, 0);
-    if (a.X) {
+    if (a.X) {   // uniform over the workgroup
         const TX* X = reinterpret_cast<const TX*>(a.X) + q * a.sX;
         const double2* U = a.hup + ik * a.hup_k + (sfirst + a.uslab) * (long long)n * n;
-        if constexpr (OPR == 1) {
-            double2 uc[UB];   // U[cb + j][c]
-#pragma unroll
-            for (int j = 0; j < UB; ++j) uc[j] = U[(long long)(cb + j) * n + c];
+        if constexpr (OPL == 2) {
+            if (tid < UB * UB) ul[tid / UB][tid % UB] = U[(long long)(rb + tid / UB) * n + rb + tid % UB];
+        }
+        if (on) {
 #pragma unroll
             for (int i = 0; i < UB; ++i) {
-                const TX* xr = X + (long long)(rb + i) * n + cb;
-#pragma unroll
-                for (int j = 0; j < UB; ++j) cfma(y[i], cconv<double2>(xr[j]), uc[j]);
+                const double2 x = cconv<double2>(X[(long long)(rb + i) * n + c]);
+                if constexpr (OPR == 1) xs[i][tid] = x;
+                else y[i] = x;
             }
-        } else {
+        }
+        if constexpr (OPR == 1 || OPL == 2) __syncthreads();
+        if constexpr (OPR == 1) {
+            if (on) {
+                double2 uc[UB];   // U[cb + j][c]
 #pragma unroll
-            for (int i = 0; i < UB; ++i) y[i] = cconv<double2>(X[(long long)(rb + i) * n + c]);
+                for (int j = 0; j < UB; ++j) uc[j] = U[(long long)(cb + j) * n + c];
+                const int lb = cb - c0;
+#pragma unroll
+                for (int i = 0; i < UB; ++i)
+#pragma unroll
+                    for (int j = 0; j < UB; ++j) cfma(y[i], xs[i][lb + j], uc[j]);
+            }
         }
         if constexpr (OPL == 2) {
             double2 z[UB];
@@ -191,12 +207,13 @@ __global__ __launch_bounds__(256) void sandwich_cols_kernel(SandArgs a) {
             for (int i = 0; i < UB; ++i) {
                 z[i] = make_double2(0, 0);
 #pragma unroll
-                for (int k = 0; k < UB; ++k) cfma(z[i], cconj(U[(long long)(rb + k) * n + rb + i]), y[k]);
+                for (int k = 0; k < UB; ++k) cfma(z[i], cconj(ul[k][i]), y[k]);
             }
 #pragma unroll
             for (int i = 0; i < UB; ++i) y[i] = z[i];
         }
     }
+    if (!on) return;
     TO* O = reinterpret_cast<TO*>(a.O) + q * a.sO;
     const long long gslab = sfirst + a.slab;
     const double E = a.energy ? a.energy[ie] : 0.0;
@@ -237,8 +254,9 @@ static bool sandwich_cols_ops(hipStream_t s, const SandArgs& a, dim3 grid) {
 
 template <typename TX, typename TO>
 static bool sandwich_cols_launch(hipStream_t s, const SandArgs& a) {
-    const long long work = (long long)(a.n / a.ub) * a.n;
-    dim3 grid((unsigned)((long long)a.np * ((work + 255) / 256)));
+    const int cw = (256 / a.ub) * a.ub;
+    const long long per = (long long)(a.n / a.ub) * ((a.n + cw - 1) / cw);
+    dim3 grid((unsigned)((long long)a.np * per));
     switch (a.ub) {
         case 1: return sandwich_cols_ops<TX, TO, 1>(s, a, grid);
         case 2: return sandwich_cols_ops<TX, TO, 2>(s, a, grid);
