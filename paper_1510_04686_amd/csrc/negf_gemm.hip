@@ -15,13 +15,13 @@ namespace negf {
 static_assert(BM == 64, "gemm_tiles() assumes 64-wide tiles");
 
 template <typename Acc>
-__device__ inline void mma_tile(Acc (*As)[BK][LP], Acc (*Bs)[BK][LP], int lane, int wm, int wn, int nmi, int nnj,
+__device__ inline void mma_tile(Acc (*As)[BK][LP], Acc (*Bs)[BK][LP], int lane, int am0, int bn0, int nmi, int nnj,
                                 typename MF<Acc>::V (&cr)[2][2], typename MF<Acc>::V (&ci)[2][2],
                                 typename MF<Acc>::V (&cs)[2][2]) {
-    if (nmi == 2 && nnj == 2) mma_slice<Acc, 2, 2>(As, Bs, lane, wm, wn, cr, ci, cs);
-    else if (nmi == 2 && nnj == 1) mma_slice<Acc, 2, 1>(As, Bs, lane, wm, wn, cr, ci, cs);
-    else if (nmi == 1 && nnj == 2) mma_slice<Acc, 1, 2>(As, Bs, lane, wm, wn, cr, ci, cs);
-    else if (nmi == 1 && nnj == 1) mma_slice<Acc, 1, 1>(As, Bs, lane, wm, wn, cr, ci, cs);
+    if (nmi == 2 && nnj == 2) mma_slice<Acc, 2, 2>(As, Bs, lane, am0, bn0, cr, ci, cs);
+    else if (nmi == 2 && nnj == 1) mma_slice<Acc, 2, 1>(As, Bs, lane, am0, bn0, cr, ci, cs);
+    else if (nmi == 1 && nnj == 2) mma_slice<Acc, 1, 2>(As, Bs, lane, am0, bn0, cr, ci, cs);
+    else if (nmi == 1 && nnj == 1) mma_slice<Acc, 1, 1>(As, Bs, lane, am0, bn0, cr, ci, cs);
 }
 
 template <typename TA, typename TB, typename TC, typename Acc, int OPA, int OPB, int EPI, int PF>
@@ -51,10 +51,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     const TA* __restrict__ A = (const TA*)g.A + q * g.sA;
     const TB* __restrict__ B = (const TB*)g.B + q * g.sB;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
-    const int rowbase = m0 + wm * 32, colbase = n0 + wn * 32;
-    const int nmi = rowbase >= n ? 0 : (rowbase + 16 >= n ? 1 : 2);
-    const int nnj = colbase >= n ? 0 : (colbase + 16 >= n ? 1 : 2);
+    const WaveTile wt = wave_tile(wave, n - m0, n - n0);
+    const int am0 = wt.am0, bn0 = wt.bn0, nmi = wt.nmi, nnj = wt.nnj;
+    const int rowbase = m0 + am0, colbase = n0 + bn0;
 
     typename MF<Acc>::V cr[2][2], ci[2][2], cs[2][2];
 #pragma unroll
@@ -84,7 +83,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
                 load_slice<TA, AK>(A, n, m0, (kt + 1) * BK, tid, ra);
                 load_slice<TB, BKR>(B, n, n0, (kt + 1) * BK, tid, rb);
             }
-            mma_tile<Acc>(As[buf], Bs[buf], lane, wm, wn, nmi, nnj, cr, ci, cs);
+            mma_tile<Acc>(As[buf], Bs[buf], lane, am0, bn0, nmi, nnj, cr, ci, cs);
             if (more) {
                 store_slice<Acc, TA, AK, OPA == OP_C>(As[buf ^ 1], tid, ra);
                 store_slice<Acc, TB, BKR, OPB == OP_C>(Bs[buf ^ 1], tid, rb);
@@ -111,7 +110,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
             load_slice<TA, AK>(A, n, m0, ((KT) + 2) * BK, tid, ra[CUR]);                                  \
             load_slice<TB, BKR>(B, n, n0, ((KT) + 2) * BK, tid, rb[CUR]);                                 \
         }                                                                                                 \
-        mma_tile<Acc>(As[CUR], Bs[CUR], lane, wm, wn, nmi, nnj, cr, ci, cs);                                  \
+        mma_tile<Acc>(As[CUR], Bs[CUR], lane, am0, bn0, nmi, nnj, cr, ci, cs);                                  \
         if ((KT) + 1 < nkt) {                                                                             \
             store_slice<Acc, TA, AK, OPA == OP_C>(As[NXT], tid, ra[NXT]);                                 \
             store_slice<Acc, TB, BKR, OPB == OP_C>(Bs[NXT], tid, rb[NXT]);                                \

@@ -383,10 +383,9 @@ __global__ __launch_bounds__(256) void gj_update(UpdArgs a) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int k0 = a.k0, nbk = a.nbk;
     const int nsl = (nbk + BK - 1) / BK;
-    const int wm = wave >> 1, wn = wave & 1;
-    const int rowbase = m0 + wm * 32, colbase = n0 + wn * 32;
-    const int nmi = rowbase >= n ? 0 : (rowbase + 16 >= n ? 1 : 2);
-    const int nnj = colbase >= cend ? 0 : (colbase + 16 >= cend ? 1 : 2);
+    const WaveTile wt = wave_tile(wave, n - m0, cend - n0);
+    const int am0 = wt.am0, bn0 = wt.bn0, nmi = wt.nmi, nnj = wt.nnj;
+    const int rowbase = m0 + am0, colbase = n0 + bn0;
     const C* X = reinterpret_cast<const C*>(a.X) + q * a.sX;
     const C* E = reinterpret_cast<const C*>(a.E) + (long long)q * n * a.ldE;
     const C* Pr = a.Prow ? reinterpret_cast<const C*>(a.Prow) + (long long)q * NBMAX * a.ldP : nullptr;
@@ -451,10 +450,10 @@ __global__ __launch_bounds__(256) void gj_update(UpdArgs a) {
         }
     };
     auto mma = [&](int b) {
-        if (nmi == 2 && nnj == 2) mma_slice<R, 2, 2>(Es[b], Ps[b], lane, wm, wn, cr, ci, cs);
-        else if (nmi == 2 && nnj == 1) mma_slice<R, 2, 1>(Es[b], Ps[b], lane, wm, wn, cr, ci, cs);
-        else if (nmi == 1 && nnj == 2) mma_slice<R, 1, 2>(Es[b], Ps[b], lane, wm, wn, cr, ci, cs);
-        else if (nmi == 1 && nnj == 1) mma_slice<R, 1, 1>(Es[b], Ps[b], lane, wm, wn, cr, ci, cs);
+        if (nmi == 2 && nnj == 2) mma_slice<R, 2, 2>(Es[b], Ps[b], lane, am0, bn0, cr, ci, cs);
+        else if (nmi == 2 && nnj == 1) mma_slice<R, 2, 1>(Es[b], Ps[b], lane, am0, bn0, cr, ci, cs);
+        else if (nmi == 1 && nnj == 2) mma_slice<R, 1, 2>(Es[b], Ps[b], lane, am0, bn0, cr, ci, cs);
+        else if (nmi == 1 && nnj == 1) mma_slice<R, 1, 1>(Es[b], Ps[b], lane, am0, bn0, cr, ci, cs);
     };
     load(0);
     store(0);

@@ -87,11 +87,32 @@ __device__ inline void store_slice(Acc (*S)[BK][LP], int tid, const TX (&r)[4]) 
 // (mixed precision) keeps the four-product form and its tighter bound.
 template <typename Acc> struct ThreeM { static constexpr bool value = sizeof(Acc) == 8; };
 
-// Accumulates one staged K slice into the 2 x 2 blocks of 16 x 16 this wave
-// owns.  With the 3M form cr, ci, cs hold P1, P2, P3 until finish_products();
+// The part of a 64 x 64 output tile a wave computes: tile-local origin
+// (am0, bn0) and its count of 16-row and 16-column blocks inside the valid
+// vr x vc corner of the tile.  Normally a 32 x 32 quarter; in a tile with at
+// most 16 valid rows (or columns), such as the last tile row at b = 400, the
+// four waves take one 16-wide block each along the other direction instead,
+// so none of them idles while the workgroup holds its slot.
+struct WaveTile { int am0, bn0, nmi, nnj; };
+__device__ inline WaveTile wave_tile(int wave, int vr, int vc) {
+    WaveTile w;
+    if (vr <= 16 && vc > 16) {
+        w.am0 = 0; w.bn0 = 16 * wave; w.nmi = 1; w.nnj = w.bn0 < vc ? 1 : 0;
+    } else if (vc <= 16 && vr > 16) {
+        w.am0 = 16 * wave; w.bn0 = 0; w.nmi = w.am0 < vr ? 1 : 0; w.nnj = 1;
+    } else {
+        w.am0 = (wave >> 1) * 32; w.bn0 = (wave & 1) * 32;
+        w.nmi = w.am0 >= vr ? 0 : (w.am0 + 16 >= vr ? 1 : 2);
+        w.nnj = w.bn0 >= vc ? 0 : (w.bn0 + 16 >= vc ? 1 : 2);
+    }
+    return w;
+}
+
+// Accumulates one staged K slice into the (up to) 2 x 2 blocks of 16 x 16 at
+// tile-local (am0, bn0) that this wave owns.  With the 3M form cr, ci, cs hold P1, P2, P3 until finish_products();
 // otherwise cr, ci hold the real and imaginary parts and cs is unused.
 template <typename Acc, int MI, int NJ>
-__device__ inline void mma_slice(Acc (*As)[BK][LP], Acc (*Bs)[BK][LP], int lane, int wm, int wn,
+__device__ inline void mma_slice(Acc (*As)[BK][LP], Acc (*Bs)[BK][LP], int lane, int am0, int bn0,
                                  typename MF<Acc>::V (&cr)[2][2], typename MF<Acc>::V (&ci)[2][2],
                                  typename MF<Acc>::V (&cs)[2][2]) {
     const int o = lane & 15;
@@ -102,13 +123,13 @@ __device__ inline void mma_slice(Acc (*As)[BK][LP], Acc (*Bs)[BK][LP], int lane,
         const int k = kk * 4 + (lane >> 4);
 #pragma unroll
         for (int mi = 0; mi < MI; ++mi) {
-            ar[set][mi] = As[0][k][swz(k, wm * 32 + mi * 16 + o)];
-            ai[set][mi] = As[1][k][swz(k, wm * 32 + mi * 16 + o)];
+            ar[set][mi] = As[0][k][swz(k, am0 + mi * 16 + o)];
+            ai[set][mi] = As[1][k][swz(k, am0 + mi * 16 + o)];
         }
 #pragma unroll
         for (int nj = 0; nj < NJ; ++nj) {
-            br[set][nj] = Bs[0][k][swz(k, wn * 32 + nj * 16 + o)];
-            bi[set][nj] = Bs[1][k][swz(k, wn * 32 + nj * 16 + o)];
+            br[set][nj] = Bs[0][k][swz(k, bn0 + nj * 16 + o)];
+            bi[set][nj] = Bs[1][k][swz(k, bn0 + nj * 16 + o)];
         }
     };
     frag(0, 0);
