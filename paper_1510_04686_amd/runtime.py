@@ -28,7 +28,7 @@ def _dev(a, dtype, device):
 class RGFSolver:
     """Batched RGF over every (sample, k, E) point of a workload on one GPU."""
 
-    def __init__(self, wl, precision="fp64", capacity=None, device="cuda", mem_fraction=0.6, adjoint_segment=0,
+    def __init__(self, wl, precision="fp64", capacity=None, device="cuda", mem_fraction=0.75, adjoint_segment=0,
                  tune=None, lanes=1, point_redo=0.03):
         """tune: None keeps the library's default kernel shapes; "auto" measures
         them on this context once (negf_autotune) and caches the choice per
@@ -74,7 +74,8 @@ class RGFSolver:
             per_point = 2 * self.n_slab_max * nb * nb * ce + 24 * nb * nb * 16 + (64 + 2 * 256 + 64) * nb * 16
             free, _ = torch.cuda.mem_get_info(self.device)
             lanes = max(1, int(lanes))
-            capacity = int(max(1, min(-(-self.n_points // lanes), 256 // lanes,
+            # up to 512 points per batch: two inverse panels per CU hide each other's latency
+            capacity = int(max(1, min(-(-self.n_points // lanes), 512 // lanes,
                                       (free * mem_fraction) // (per_point * lanes))))
         self.capacity = int(capacity)
         self.lanes = max(1, int(lanes))
