@@ -297,7 +297,10 @@ int negf_gemm_timing(negf_ctx* ctx, void* stream, long long* launches, double* m
 /*
  * Kernel shape choices of a context (the batching form picks tile shapes by
  * measurement, not by a fixed table).
- *   gemm_prefetch  K slices of the batched GEMM in flight: 1 or 2 (default 2)
+ *   gemm_prefetch  K slices of the batched GEMM in flight: 1 or 2 (default 2);
+ *                  3 = two, with persistent workgroups that carry the K pipeline
+ *                  from one output tile to the next (FP64 products of blocks
+ *                  wider than 16; the form 2 kernel otherwise)
  *   inv_outer      outer panel width of the two-level block inverse: 0 (one
  *                  level) or a multiple of 32 in [64, 256] (default 128)
  * negf_autotune times every candidate on the context's own workspace (block nb,

@@ -1058,7 +1058,7 @@ int negf_get_tuning(const negf_ctx* c, negf_tuning* out) {
 
 int negf_set_tuning(negf_ctx* c, const negf_tuning* t) {
     if (!c || !t) return NEGF_EINVAL;
-    if (t->gemm_prefetch != 1 && t->gemm_prefetch != 2) return NEGF_EINVAL;
+    if (t->gemm_prefetch < 1 || t->gemm_prefetch > 3) return NEGF_EINVAL;
     if (t->inv_outer != 0 && (t->inv_outer < 64 || t->inv_outer > INV_WMAX || t->inv_outer % 32 != 0)) return NEGF_EINVAL;
     c->tune = *t;
     return NEGF_OK;
@@ -1095,7 +1095,7 @@ int negf_autotune(negf_ctx* c, void* stream, int reps, negf_tuning* out) {
     // batched GEMM: K slices in flight
     if ((err = fill(c->tmp[0], 0.0)) == hipSuccess) err = fill(c->tmp[1], 0.0);
     float best_ms = 0.0f;
-    for (int pf = 1; pf <= 2 && err == hipSuccess; ++pf) {
+    for (int pf = 1; pf <= 3 && err == hipSuccess; ++pf) {
         GemmArgs G = gargs(n, np, all);
         G.A = c->tmp[0]; G.sA = nn; G.B = c->tmp[1]; G.sB = nn; G.C = c->tmp[2]; G.sC = nn; G.pf = pf;
         const GemmTypes ty{dt, dt, dt, dt};

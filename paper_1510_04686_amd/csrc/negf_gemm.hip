@@ -7,6 +7,8 @@
 // through LDS in 16-wide double-buffered slices, split real/imaginary planes.
 // A complex product is three real MFMA products on v_mfma_f64_16x16x4f64
 // (FP64, the 3M form) or four on v_mfma_f32_16x16x4f32 (FP32).
+#include <algorithm>
+
 #include "negf_internal.hpp"
 #include "negf_mfma.hpp"
 
@@ -24,6 +26,80 @@ __device__ inline void mma_tile(Acc (*As)[BK][LP], Acc (*Bs)[BK][LP], int lane, 
     else if (nmi == 1 && nnj == 1) mma_slice<Acc, 1, 1>(As, Bs, lane, am0, bn0, cr, ci, cs);
 }
 
+// Output tile t of one point: row-major over all tiles, or over the lower
+// triangle (tj <= ti) for the anti-Hermitian epilogues.
+template <bool AH>
+__device__ inline void tile_of(int t, int tiles, int& ti, int& tj) {
+    if (AH) {
+        ti = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+        while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+        while (ti * (ti + 1) / 2 > t) --ti;
+        tj = t - ti * (ti + 1) / 2;
+    } else {
+        ti = t / tiles;
+        tj = t - ti * tiles;
+    }
+}
+
+// Writes this wave's part of the finished tile (m0, n0) of point q.  LEAN
+// keeps the scheduler from interleaving the four 16 x 16 blocks (fewer live
+// registers, for the persistent kernel, where the epilogue sits inside a loop).
+template <typename TC, typename Acc, int EPI, bool LEAN = false>
+__device__ inline void gemm_epilogue(const GemmArgs& g, int q, int m0, int n0, const WaveTile& wt, int lane,
+                                     const typename MF<Acc>::V (&cr)[2][2], const typename MF<Acc>::V (&ci)[2][2]) {
+    constexpr bool AH = (EPI == EPI_STORE_AH || EPI == EPI_ADD_TTD_AH);
+    const int n = g.n;
+    const int rowbase = m0 + wt.am0, colbase = n0 + wt.bn0;
+    TC* __restrict__ C = (TC*)g.C + q * g.sC;
+    const TC* D = (const TC*)g.D + q * g.sD;
+    const TC* T = (const TC*)g.T + q * g.sT;
+    TC* C2 = (TC*)g.C2 + q * g.sC2;
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi) {
+        if (mi >= wt.nmi) break;
+#pragma unroll
+        for (int nj = 0; nj < 2; ++nj) {
+            if (nj >= wt.nnj) break;
+            const int col = colbase + nj * 16 + (lane & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = rowbase + mi * 16 + out_row<Acc>(lane, r);
+                if (row < n && col < n && !(AH && m0 == n0 && row < col)) {
+                    const long long idx = (long long)row * n + col;
+                    double vr = (double)cr[mi][nj][r], vi = (double)ci[mi][nj][r];
+                    TC out;
+                    if (EPI == EPI_STORE_AH) {
+                        out.x = (row == col) ? 0.0 : vr; out.y = vi; C[idx] = out;
+                    } else if (EPI == EPI_STORE) {
+                        out.x = vr; out.y = vi; C[idx] = out;
+                    } else if (EPI == EPI_ADD || EPI == EPI_SUB) {
+                        TC d = D[idx];
+                        double s = (EPI == EPI_ADD) ? 1.0 : -1.0;
+                        out.x = (double)d.x + s * vr; out.y = (double)d.y + s * vi; C[idx] = out;
+                    } else if (EPI == EPI_ADD_TTD || EPI == EPI_ADD_TTD_AH) {
+                        TC d = D[idx], t1 = T[idx], t2 = T[(long long)col * n + row];
+                        out.x = (double)d.x + vr + (double)t1.x - (double)t2.x;
+                        out.y = (double)d.y + vi + (double)t1.y + (double)t2.y;
+                        if (EPI == EPI_ADD_TTD_AH && row == col) out.x = 0.0;
+                        C[idx] = out;
+                    } else if (EPI == EPI_DUAL) {
+                        TC c1 = C[idx], c2 = C2[idx];
+                        out.x = (double)c1.x + vr; out.y = (double)c1.y + vi; C[idx] = out;
+                        out.x = (double)c2.x + vr; out.y = (double)c2.y + vi; C2[idx] = out;
+                    } else if (EPI == EPI_IMINUS) {
+                        out.x = (row == col ? 1.0 : 0.0) - vr; out.y = -vi; C[idx] = out;
+                    }
+                    if (AH && row != col) {
+                        TC m; m.x = -out.x; m.y = out.y;
+                        C[(long long)col * n + row] = m;
+                    }
+                }
+            }
+            if constexpr (LEAN) __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
 template <typename TA, typename TB, typename TC, typename Acc, int OPA, int OPB, int EPI, int PF>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     __shared__ Acc As[2][2][BK][LP];
@@ -37,23 +113,13 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     if (q >= g.np || !g.act(q)) return;
     const int t = lid - q * tpp;
     int ti, tj;
-    if (AH) {
-        // t -> (ti, tj), tj <= ti, row-major over the lower triangle of tiles
-        ti = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
-        while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
-        while (ti * (ti + 1) / 2 > t) --ti;
-        tj = t - ti * (ti + 1) / 2;
-    } else {
-        ti = t / tiles;
-        tj = t - ti * tiles;
-    }
+    tile_of<AH>(t, tiles, ti, tj);
     const int m0 = ti * BM, n0 = tj * BM;
     const TA* __restrict__ A = (const TA*)g.A + q * g.sA;
     const TB* __restrict__ B = (const TB*)g.B + q * g.sB;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const WaveTile wt = wave_tile(wave, n - m0, n - n0);
     const int am0 = wt.am0, bn0 = wt.bn0, nmi = wt.nmi, nnj = wt.nnj;
-    const int rowbase = m0 + am0, colbase = n0 + bn0;
 
     typename MF<Acc>::V cr[2][2], ci[2][2], cs[2][2];
 #pragma unroll
@@ -124,62 +190,157 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
 #undef NEGF_GEMM_STEP
     }
     finish_products<Acc>(cr, ci, cs);
+    gemm_epilogue<TC, Acc, EPI>(g, q, m0, n0, wt, lane, cr, ci);
+}
 
-    TC* __restrict__ C = (TC*)g.C + q * g.sC;
-    const TC* D = (const TC*)g.D + q * g.sD;
-    const TC* T = (const TC*)g.T + q * g.sT;
-    TC* C2 = (TC*)g.C2 + q * g.sC2;
-#pragma unroll
-    for (int mi = 0; mi < 2; ++mi) {
-        if (mi >= nmi) break;
-#pragma unroll
-        for (int nj = 0; nj < 2; ++nj) {
-            if (nj >= nnj) break;
-            const int col = colbase + nj * 16 + (lane & 15);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = rowbase + mi * 16 + out_row<Acc>(lane, r);
-                if (row < n && col < n && !(AH && m0 == n0 && row < col)) {
-                    const long long idx = (long long)row * n + col;
-                    double vr = (double)cr[mi][nj][r], vi = (double)ci[mi][nj][r];
-                    TC out;
-                    if (EPI == EPI_STORE_AH) {
-                        out.x = (row == col) ? 0.0 : vr; out.y = vi; C[idx] = out;
-                    } else if (EPI == EPI_STORE) {
-                        out.x = vr; out.y = vi; C[idx] = out;
-                    } else if (EPI == EPI_ADD || EPI == EPI_SUB) {
-                        TC d = D[idx];
-                        double s = (EPI == EPI_ADD) ? 1.0 : -1.0;
-                        out.x = (double)d.x + s * vr; out.y = (double)d.y + s * vi; C[idx] = out;
-                    } else if (EPI == EPI_ADD_TTD || EPI == EPI_ADD_TTD_AH) {
-                        TC d = D[idx], t1 = T[idx], t2 = T[(long long)col * n + row];
-                        out.x = (double)d.x + vr + (double)t1.x - (double)t2.x;
-                        out.y = (double)d.y + vi + (double)t1.y + (double)t2.y;
-                        if (EPI == EPI_ADD_TTD_AH && row == col) out.x = 0.0;
-                        C[idx] = out;
-                    } else if (EPI == EPI_DUAL) {
-                        TC c1 = C[idx], c2 = C2[idx];
-                        out.x = (double)c1.x + vr; out.y = (double)c1.y + vi; C[idx] = out;
-                        out.x = (double)c2.x + vr; out.y = (double)c2.y + vi; C2[idx] = out;
-                    } else if (EPI == EPI_IMINUS) {
-                        out.x = (row == col ? 1.0 : 0.0) - vr; out.y = -vi; C[idx] = out;
-                    }
-                    if (AH && row != col) {
-                        TC m; m.x = -out.x; m.y = out.y;
-                        C[(long long)col * n + row] = m;
-                    }
-                }
-            }
-        }
+// Persistent form of the two-slices-in-flight kernel: each workgroup walks the
+// tiles lid, lid + G, ... (G = workgroups in the grid, sized to the resident
+// slots) and keeps the K pipeline running across tile boundaries: the next
+// tile's first slice is read during the current tile's last two products and
+// staged in LDS with its last one; its second slice is read right after the
+// epilogue (so no prefetch registers are live across it) and lands during the
+// next tile's first products; a tile's epilogue stores overlap those products.
+// Requires n > BK (at least two K slices per tile).
+template <typename TA, typename TB, typename TC, typename Acc, int OPA, int OPB, int EPI>
+__global__ __launch_bounds__(256, 2) void gemm_persist_kernel(GemmArgs g) {
+    __shared__ Acc As[2][2][BK][LP];
+    __shared__ Acc Bs[2][2][BK][LP];
+    constexpr bool AH = (EPI == EPI_STORE_AH || EPI == EPI_ADD_TTD_AH);
+    constexpr bool AK = (OPA == OP_C);
+    constexpr bool BKR = (OPB == OP_N);
+    const int n = g.n;
+    const int tiles = (n + BM - 1) / BM;
+    const int tpp = AH ? tiles * (tiles + 1) / 2 : tiles * tiles;
+    const long long total = (long long)g.np * tpp;
+    const int G = gridDim.x;
+    const int nkt = (n + BK - 1) / BK;
+    int tid = threadIdx.x;   // per tile an opaque copy (see the tile loop)
+    // next tile of an active point at or after lt in this workgroup's sequence
+    auto advance = [&](long long lt) {
+        while (lt < total && !g.act((int)(lt / tpp))) lt += G;
+        return lt;
+    };
+    long long lc = advance(xcd_remap(blockIdx.x, G));
+    if (lc >= total) return;
+    long long ln = advance(lc + G);
+    int cq, cm0, cn0, nq = 0, nm0 = 0, nn0 = 0;
+    {
+        int ti, tj;
+        cq = (int)(lc / tpp);
+        tile_of<AH>((int)(lc - (long long)cq * tpp), tiles, ti, tj);
+        cm0 = ti * BM; cn0 = tj * BM;
     }
+    auto set_next = [&]() {
+        if (ln < total) {
+            int ti, tj;
+            nq = (int)(ln / tpp);
+            tile_of<AH>((int)(ln - (long long)nq * tpp), tiles, ti, tj);
+            nm0 = ti * BM; nn0 = tj * BM;
+        }
+    };
+    set_next();
+    auto ldA = [&](int q, int m0, int kt, TA (&r)[4]) {
+        load_slice<TA, AK>((const TA*)g.A + q * g.sA, n, m0, kt * BK, tid, r);
+    };
+    auto ldB = [&](int q, int n0, int kt, TB (&r)[4]) {
+        load_slice<TB, BKR>((const TB*)g.B + q * g.sB, n, n0, kt * BK, tid, r);
+    };
+    TA ra[2][4];
+    TB rb[2][4];
+    ldA(cq, cm0, 0, ra[0]); ldB(cq, cn0, 0, rb[0]);
+    ldA(cq, cm0, 1, ra[1]); ldB(cq, cn0, 1, rb[1]);
+    store_slice<Acc, TA, AK, OPA == OP_C>(As[0], tid, ra[0]);
+    store_slice<Acc, TB, BKR, OPB == OP_C>(Bs[0], tid, rb[0]);
+    __syncthreads();
+
+    typename MF<Acc>::V cr[2][2], ci[2][2], cs[2][2];
+    int lb = 0;   // LDS buffer holding the slice about to be multiplied
+    // One step: RC receives the slice two ahead, RN holds the next slice, which
+    // is staged into the other LDS buffer while buffer lb is multiplied.  Within
+    // a tile the register sets alternate with kt; the LDS buffers alternate with
+    // every slice of the workgroup's sequence.
+#define NEGF_PERSIST_STEP(KT, RC, RN, MI, NJ)                                                             \
+    {                                                                                                     \
+        const int k2 = (KT) + 2;                                                                          \
+        if (k2 < nkt) {                                                                                   \
+            ldA(cq, cm0, k2, ra[RC]); ldB(cq, cn0, k2, rb[RC]);                                           \
+        } else if (k2 == nkt && ln < total) {                                                             \
+            ldA(nq, nm0, 0, ra[RC]); ldB(nq, nn0, 0, rb[RC]);                                             \
+        }                                                                                                 \
+        if constexpr (MI > 0 && NJ > 0)                                                                   \
+            mma_slice<Acc, (MI > 0 ? MI : 1), (NJ > 0 ? NJ : 1)>(As[lb], Bs[lb], lane, wt.am0, wt.bn0,     \
+                                                                 cr, ci, cs);                             \
+        if ((KT) + 1 < nkt || ln < total) {                                                               \
+            store_slice<Acc, TA, AK, OPA == OP_C>(As[lb ^ 1], tid, ra[RN]);                               \
+            store_slice<Acc, TB, BKR, OPB == OP_C>(Bs[lb ^ 1], tid, rb[RN]);                              \
+        }                                                                                                 \
+        __syncthreads();                                                                                  \
+        lb ^= 1;                                                                                          \
+    }
+    // the K loop of one tile for a wave owning MI x NJ blocks (0: loads and barriers only)
+#define NEGF_PERSIST_TILE(MI, NJ)                                                                         \
+    for (int kt = 0; kt < nkt; kt += 2) {                                                                 \
+        NEGF_PERSIST_STEP(kt, 0, 1, MI, NJ)                                                               \
+        if (kt + 1 < nkt) NEGF_PERSIST_STEP(kt + 1, 1, 0, MI, NJ)                                         \
+    }
+    for (;;) {
+        // LDS buffer lb holds slice 0 of the current tile, registers 1 its slice 1.
+        // The thread id is passed through an empty asm once per tile, so the
+        // per-thread address offsets derived from it are recomputed here instead
+        // of being hoisted out of the tile loop and kept alive across the epilogue.
+        asm volatile("" : "+v"(tid));
+        const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) { cr[a][b][r] = 0; ci[a][b][r] = 0; cs[a][b][r] = 0; }
+        const WaveTile wt = wave_tile(wave, n - cm0, n - cn0);
+        if (wt.nmi == 2 && wt.nnj == 2) NEGF_PERSIST_TILE(2, 2)
+        else if (wt.nmi == 2 && wt.nnj == 1) NEGF_PERSIST_TILE(2, 1)
+        else if (wt.nmi == 1 && wt.nnj == 2) NEGF_PERSIST_TILE(1, 2)
+        else if (wt.nmi == 1 && wt.nnj == 1) NEGF_PERSIST_TILE(1, 1)
+        else NEGF_PERSIST_TILE(0, 0)
+        finish_products<Acc>(cr, ci, cs);
+        gemm_epilogue<TC, Acc, EPI, true>(g, cq, cm0, cn0, wt, lane, cr, ci);
+        if (ln >= total) return;
+        cq = nq; cm0 = nm0; cn0 = nn0;
+        // the new tile's second slice: both register sets are free here
+        ldA(cq, cm0, 1, ra[1]); ldB(cq, cn0, 1, rb[1]);
+        ln = advance(ln + G);
+        set_next();
+    }
+#undef NEGF_PERSIST_TILE
+#undef NEGF_PERSIST_STEP
+}
+
+// Resident workgroup slots of the current device for the persistent kernel:
+// two 80 KB-LDS workgroups per compute unit.
+static int persist_slots() {
+    static int slots[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    if (slots[dev] == 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return 0;
+        slots[dev] = 2 * cus;
+    }
+    return slots[dev];
 }
 
 template <typename TA, typename TB, typename TC, typename Acc, int OPA, int OPB>
 static hipError_t launch_epi(hipStream_t s, int epi, const GemmArgs& g, dim3 grid) {
+    // pf 3: the persistent two-slice kernel (FP64 products, at least two K slices)
+    const int slots = (g.pf == 3 && sizeof(Acc) == 8 && g.n > BK) ? persist_slots() : 0;
+    const bool persist = slots > 0;
+    dim3 pgrid(persist ? (unsigned)std::min<long long>((long long)grid.x, slots) : 1u);
     switch (epi) {
 #define NEGF_EPI(E)                                                                                       \
     case E:                                                                                               \
-        if (g.pf != 1)                                                                                    \
+        if (persist)                                                                                      \
+            hipLaunchKernelGGL((gemm_persist_kernel<TA, TB, TC, Acc, OPA, OPB, E>), pgrid, dim3(256), 0, s, g); \
+        else if (g.pf != 1)                                                                               \
             hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, Acc, OPA, OPB, E, 2>), grid, dim3(256), 0, s, g); \
         else                                                                                              \
             hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, Acc, OPA, OPB, E, 1>), grid, dim3(256), 0, s, g); \

@@ -36,7 +36,7 @@ struct GemmArgs {
     int n;
     int np;
     Active act;
-    int pf;              // K slices in flight: 1 or 2 (0: 2)
+    int pf;              // K slices in flight: 1 or 2 (0: 2); 3: two, persistent workgroups
 };
 
 struct GemmTypes {

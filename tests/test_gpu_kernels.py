@@ -120,7 +120,7 @@ def test_tuning_validation_and_roundtrip(ctx):
     from paper_1510_04686_amd import negf
     _say("tuning set/get")
     old = negf.negf_get_tuning(ctx)
-    for bad in ((0, 128), (3, 128), (2, 32), (2, 100), (2, 288)):
+    for bad in ((0, 128), (4, 128), (2, 32), (2, 100), (2, 288)):
         with pytest.raises(negf.NegfError):
             negf.negf_set_tuning(ctx, *bad)
     negf.negf_set_tuning(ctx, 1, 64)
@@ -152,8 +152,8 @@ def test_zinv_every_outer_width(ctx, W):
         assert err < 1e-14 * np.linalg.cond(A[b]) * n + 1e-13, (b, err)
 
 
-@pytest.mark.parametrize("pf", [1, 2])
-@pytest.mark.parametrize("n", [17, 100, 400])
+@pytest.mark.parametrize("pf", [1, 2, 3])
+@pytest.mark.parametrize("n", [16, 17, 100, 400])
 def test_zgemm_prefetch_depths_agree(ctx, pf, n):
     from paper_1510_04686_amd import negf
     _say(f"zgemm prefetch {pf} n={n}")
@@ -178,3 +178,31 @@ def test_autotune_returns_a_valid_choice():
     assert t["gemm_prefetch"] in (1, 2)
     assert t["inv_outer"] == 0 or (64 <= t["inv_outer"] < 200 and t["inv_outer"] % 32 == 0)
     assert negf.negf_get_tuning(c) == t
+
+
+@pytest.mark.parametrize("n,batch", [(65, 300), (100, 160), (400, 12)])
+def test_zgemm_persistent_walks_many_tiles(n, batch):
+    """The persistent form (prefetch 3) with far more output tiles than
+    resident workgroups, so each workgroup carries its K pipeline across
+    several tiles (edge tiles included at n = 65): every operand form must
+    equal the per-tile kernel bit for bit, and NumPy on sampled entries."""
+    from paper_1510_04686_amd import negf
+    _say(f"persistent zgemm n={n} batch={batch}")
+    c = negf.negf_create(nb=n, n_slab_max=1, capacity=batch)
+    rng = np.random.default_rng(7000 + n)
+    A = torch.from_numpy(_rand(rng, (batch, n, n))).cuda()
+    B = torch.from_numpy(_rand(rng, (batch, n, n))).cuda()
+    for opa, opb in [(0, 0), (0, 1), (1, 0)]:
+        out = {}
+        for pf in (2, 3):
+            negf.negf_set_tuning(c, pf, negf.negf_get_tuning(c)["inv_outer"])
+            C = torch.zeros_like(A)
+            negf.negf_zgemm_batched(c, A, B, C, opa, opb)
+            torch.cuda.synchronize()
+            out[pf] = C.cpu().numpy()
+        assert np.array_equal(out[2], out[3]), (opa, opb)
+        idx = rng.choice(batch, size=3, replace=False)
+        a, b = A.cpu().numpy()[idx], B.cpu().numpy()[idx]
+        ref = _op(a, opa) @ _op(b, opb)
+        assert np.max(np.abs(out[3][idx] - ref)) / np.max(np.abs(ref)) < 1e-13 * np.sqrt(n)
+    del c

@@ -302,3 +302,21 @@ def test_two_lanes_match_one_lane(graph):
         a, b = o1[k].cpu().numpy(), o2[k].cpu().numpy()
         assert np.array_equal(a, b), (k, np.max(np.abs(a - b)))
     assert h1 == h2
+
+
+@pytest.mark.parametrize("capacity", [64, 200])
+def test_persistent_gemm_gives_the_same_solve(capacity):
+    """The whole RGF path (ragged samples, several batches, anti-Hermitian and
+    adding epilogues) with the persistent GEMM equals the per-tile GEMM bit for
+    bit; block 80 gives four tiles per point, 800 tiles per full batch."""
+    _say(f"persistent GEMM in the full solve, capacity={capacity}")
+    wl = make_workload("C4", n_slab=8, n_e=40, n_z=2, n_y=4, n_samples=5)
+    outs = []
+    for pf in (2, 3):
+        s = _solver(wl, capacity=capacity, tune={"gemm_prefetch": pf, "inv_outer": 64})
+        o = s.solve(want_T=True)
+        torch.cuda.synchronize()
+        assert s.status() == 0
+        outs.append({k: v.cpu().numpy() for k, v in o.items()})
+    for k in outs[0]:
+        assert np.array_equal(outs[0][k], outs[1][k]), k
