@@ -33,28 +33,57 @@ constexpr int BM = 64;   // tile rows = tile cols
 constexpr int BK = 16;   // K slice
 constexpr int LP = 80;   // LDS row stride (elements): rows k, k+1 of a fragment read land on disjoint banks
 
-// LDS column of element (k, c) of a staged slice: the halves of a 64-column
-// row swap on odd groups of four k, so the four k rows one store instruction
-// of the row-outer pattern touches fall on two bank halves instead of one.
-__device__ __host__ constexpr int swz(int k, int c) { return c ^ (((k >> 2) & 1) << 4); }
+// LDS column of element (k, c) of a staged slice: each group of four k rows
+// XORs the column by a different multiple of 4, so the four k rows one store
+// instruction of the row-outer pattern touches start 8 dwords apart and fill
+// all 32 LDS banks, while every fragment read (one k group) stays a plain
+// permutation of 16-column blocks.
+__device__ __host__ constexpr int swz(int k, int c) { return c ^ (((k >> 2) & 3) << 2); }
+
+// Element j (0..3) of a thread's share of one K slice, as (k row, outer index)
+// within the slice.
+//   KROWS = false ("pattern X"): 64 outer rows, 16 contiguous k: 4 consecutive k.
+//   KROWS = true  ("pattern Y"): 16 k rows, 64 contiguous outer indices: two
+//   column pairs 2l, 2l + 1 and 32 + 2l, 33 + 2l (l = tid mod 16), so that eight
+//   lanes' 16-byte LDS stores cover 32 consecutive dwords.
+template <bool KROWS>
+__device__ inline void slice_slot(int tid, int j, int& k, int& o) {
+    if (!KROWS) { o = tid >> 2; k = (tid & 3) * 4 + j; }
+    else { k = tid >> 4; o = 2 * (tid & 15) + (j & 1) + ((j >> 1) << 5); }
+}
 
 // Loads one K slice of op(X) into registers.
-//   OUTER_K = false ("pattern X"): 64 source rows (outer index), 16 contiguous k.
-//   OUTER_K = true  ("pattern Y"): 16 source rows (k), 64 contiguous outer indices.
 template <typename TX, bool KROWS>
 __device__ inline void load_slice(const TX* __restrict__ X, int n, int o0, int k0, int tid, TX (&r)[4]) {
-    int row, col;
-    if (!KROWS) { row = o0 + (tid >> 2); col = k0 + (tid & 3) * 4; }
-    else        { row = k0 + (tid >> 4); col = o0 + (tid & 15) * 4; }
-    const TX* p = X + (long long)row * n + col;
-    if (row < n && col + 3 < n) {
+    if (!KROWS) {
+        const int row = o0 + (tid >> 2), col = k0 + (tid & 3) * 4;
+        const TX* p = X + (long long)row * n + col;
+        if (row < n && col + 3 < n) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) r[j] = p[j];
+            for (int j = 0; j < 4; ++j) r[j] = p[j];
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (row < n && col + j < n) r[j] = p[j];
+                else { r[j].x = 0; r[j].y = 0; }
+            }
+        }
     } else {
+        const int row = k0 + (tid >> 4), col = o0 + 2 * (tid & 15);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            if (row < n && col + j < n) r[j] = p[j];
-            else { r[j].x = 0; r[j].y = 0; }
+        for (int h = 0; h < 2; ++h) {
+            const int c = col + 32 * h;
+            const TX* p = X + (long long)row * n + c;
+            if (row < n && c + 1 < n) {
+                r[2 * h] = p[0];
+                r[2 * h + 1] = p[1];
+            } else {
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    if (row < n && c + j < n) r[2 * h + j] = p[j];
+                    else { r[2 * h + j].x = 0; r[2 * h + j].y = 0; }
+                }
+            }
         }
     }
 }
@@ -62,29 +91,15 @@ __device__ inline void load_slice(const TX* __restrict__ X, int n, int o0, int k
 // Writes the register slice into LDS planes S[re/im][k][outer] (conjugated if CONJ).
 template <typename Acc, typename TX, bool KROWS, bool CONJ>
 __device__ inline void store_slice(Acc (*S)[BK][LP], int tid, const TX (&r)[4]) {
-    if (!KROWS) {
-        int o = tid >> 2, k = (tid & 3) * 4;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            S[0][k + j][swz(k + j, o)] = (Acc)r[j].x;
-            S[1][k + j][swz(k + j, o)] = CONJ ? -(Acc)r[j].y : (Acc)r[j].y;
-        }
-    } else {
-        int k = tid >> 4, o = (tid & 15) * 4;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            S[0][k][swz(k, o + j)] = (Acc)r[j].x;
-            S[1][k][swz(k, o + j)] = CONJ ? -(Acc)r[j].y : (Acc)r[j].y;
-        }
+    for (int j = 0; j < 4; ++j) {
+        int k, o;
+        slice_slot<KROWS>(tid, j, k, o);
+        S[0][k][swz(k, o)] = (Acc)r[j].x;
+        S[1][k][swz(k, o)] = CONJ ? -(Acc)r[j].y : (Acc)r[j].y;
     }
 }
 
-// FP64 complex products use three real MFMA products (the 3M form): with
-// P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi), the product is
-// (P1 - P2) + i (P3 - P1 - P2).  That is 12 MFMAs per 16x16x4 complex step
-// instead of 16; the imaginary part's rounding is bounded by the unit roundoff
-// times (|Ar| + |Ai|)(|Br| + |Bi|) instead of |Ar||Bi| + |Ai||Br|.  FP32
-// (mixed precision) keeps the four-product form and its tighter bound.
 template <typename Acc> struct ThreeM { static constexpr bool value = sizeof(Acc) == 8; };
 
 // The part of a 64 x 64 output tile a wave computes: tile-local origin
