@@ -394,7 +394,7 @@ __global__ __launch_bounds__(256) void gj_update(UpdArgs a) {
     // Row sources read ahead: the pivot row this thread loads in the next K slice (when
     // gathered from X) and the tile rows it gathers at the end, so no global read of
     // the matrix waits on an index read.
-    const int pk = tid >> 4, poc = 2 * (tid & 15);   // pivot-row columns poc, poc + 1, poc + 32, poc + 33
+    const int pk = tid >> 4, poc = tid & 15;   // pivot-row columns poc + 16 j
     auto row_of = [&](int s) { const int kk = s * BK + pk; return (!Pr && kk < nbk) ? rs[k0 + kk] : 0; };
     int src_next = row_of(0);   // pivot-row source of the slice loaded next (read one slice ahead)
     int rsr[2][4];
@@ -435,7 +435,7 @@ __global__ __launch_bounds__(256) void gj_update(UpdArgs a) {
         if (kk < nbk) prow = Pr ? Pr + (long long)kk * a.ldP - a.pc0 : X + (long long)src * ldX - xc;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int col = n0 + poc + (j & 1) + ((j >> 1) << 5);
+            const int col = n0 + poc + 16 * j;
             rp[j].x = 0; rp[j].y = 0;
             if (prow && col < cend) rp[j] = prow[col];
         }
@@ -443,7 +443,7 @@ __global__ __launch_bounds__(256) void gj_update(UpdArgs a) {
     auto store = [&](int b) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int pc = poc + (j & 1) + ((j >> 1) << 5);
+            const int pc = poc + 16 * j;
             Es[b][0][ek + j][swz(ek + j, eo)] = re[j].x;
             Es[b][1][ek + j][swz(ek + j, eo)] = re[j].y;
             Ps[b][0][pk][swz(pk, pc)] = rp[j].x;

@@ -43,13 +43,13 @@ __device__ __host__ constexpr int swz(int k, int c) { return c ^ (((k >> 2) & 3)
 // Element j (0..3) of a thread's share of one K slice, as (k row, outer index)
 // within the slice.
 //   KROWS = false ("pattern X"): 64 outer rows, 16 contiguous k: 4 consecutive k.
-//   KROWS = true  ("pattern Y"): 16 k rows, 64 contiguous outer indices: two
-//   column pairs 2l, 2l + 1 and 32 + 2l, 33 + 2l (l = tid mod 16), so that eight
-//   lanes' 16-byte LDS stores cover 32 consecutive dwords.
+//   KROWS = true  ("pattern Y"): 16 k rows, 64 contiguous outer indices:
+//   columns l, l + 16, l + 32, l + 48 (l = tid mod 16), so that the 16 lanes of
+//   a k row store 16 consecutive values (all 32 banks) per instruction.
 template <bool KROWS>
 __device__ inline void slice_slot(int tid, int j, int& k, int& o) {
     if (!KROWS) { o = tid >> 2; k = (tid & 3) * 4 + j; }
-    else { k = tid >> 4; o = 2 * (tid & 15) + (j & 1) + ((j >> 1) << 5); }
+    else { k = tid >> 4; o = (tid & 15) + 16 * j; }
 }
 
 // Loads one K slice of op(X) into registers.
@@ -69,21 +69,12 @@ __device__ inline void load_slice(const TX* __restrict__ X, int n, int o0, int k
             }
         }
     } else {
-        const int row = k0 + (tid >> 4), col = o0 + 2 * (tid & 15);
+        const int row = k0 + (tid >> 4), col = o0 + (tid & 15);
+        const TX* p = X + (long long)row * n + col;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int c = col + 32 * h;
-            const TX* p = X + (long long)row * n + c;
-            if (row < n && c + 1 < n) {
-                r[2 * h] = p[0];
-                r[2 * h + 1] = p[1];
-            } else {
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    if (row < n && c + j < n) r[2 * h + j] = p[j];
-                    else { r[2 * h + j].x = 0; r[2 * h + j].y = 0; }
-                }
-            }
+        for (int j = 0; j < 4; ++j) {
+            if (row < n && col + 16 * j < n) r[j] = p[16 * j];
+            else { r[j].x = 0; r[j].y = 0; }
         }
     }
 }
