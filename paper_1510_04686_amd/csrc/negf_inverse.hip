@@ -456,18 +456,23 @@ __global__ __launch_bounds__(256) void gj_update(UpdArgs a) {
         else if (nmi == 1 && nnj == 2) mma_slice<R, 1, 2>(Es[b], Ps[b], lane, am0, bn0, cr, ci, cs);
         else if (nmi == 1 && nnj == 1) mma_slice<R, 1, 1>(Es[b], Ps[b], lane, am0, bn0, cr, ci, cs);
     };
-    load(0);
-    store(0);
-    __syncthreads();
-    for (int s = 0; s + 1 < nsl; ++s) {
-        const int b = s & 1;
-        load(s + 1);
-        mma(b);
-        store(b ^ 1);
+    // A tile whose columns all lie inside the panel's K range only copies the
+    // transform columns: its products would be discarded (uniform per workgroup).
+    const bool copy_only = n0 >= k0 && min(n0 + BM, cend) <= k0 + nbk;
+    if (!copy_only) {
+        load(0);
+        store(0);
         __syncthreads();
+        for (int s = 0; s + 1 < nsl; ++s) {
+            const int b = s & 1;
+            load(s + 1);
+            mma(b);
+            store(b ^ 1);
+            __syncthreads();
+        }
+        mma((nsl - 1) & 1);
+        finish_products<R>(cr, ci, cs);
     }
-    mma((nsl - 1) & 1);
-    finish_products<R>(cr, ci, cs);
 
     // Epilogue, one 16-row block at a time: gather the old rows (or the transform
     // columns inside the K range) and write the new tile.
