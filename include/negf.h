@@ -303,6 +303,13 @@ int negf_gemm_timing(negf_ctx* ctx, void* stream, long long* launches, double* m
  *                  wider than 16; the form 2 kernel otherwise)
  *   inv_outer      outer panel width of the two-level block inverse: 0 (one
  *                  level) or a multiple of 32 in [64, 256] (default 128)
+ *   inv_mid        mid block width of a three-level inverse: 0 (two levels,
+ *                  default) or a multiple of 32 in [32, 256]; used when narrower
+ *                  than inv_outer and the inner panels hold one row per thread
+ *                  (b <= 512 in FP64): inside an outer panel the inner panels
+ *                  then update only their mid block, which passes its
+ *                  composite transform to the rest of the outer panel in one
+ *                  rank-inv_mid product
  * negf_autotune times every candidate on the context's own workspace (block nb,
  * batch = capacity, the context's precision) with synthetic well-conditioned
  * blocks, `reps` launches each, applies the fastest and returns it.  It
@@ -313,6 +320,7 @@ int negf_gemm_timing(negf_ctx* ctx, void* stream, long long* launches, double* m
 typedef struct {
     int gemm_prefetch;
     int inv_outer;
+    int inv_mid;
 } negf_tuning;
 int negf_get_tuning(const negf_ctx* ctx, negf_tuning* out);
 int negf_set_tuning(negf_ctx* ctx, const negf_tuning* tuning);

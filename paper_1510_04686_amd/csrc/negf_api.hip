@@ -41,6 +41,7 @@ struct negf_ctx {
     void* invN0 = nullptr;        // narrow outer-panel copies of the two-level inverse
     void* invN1 = nullptr;
     int* invComp = nullptr;
+    int* invComp2 = nullptr;      // mid-block composite row sources of the three-level inverse
     int* rowsrc = nullptr;
     int* piv = nullptr;
     int* coldst = nullptr;
@@ -84,7 +85,7 @@ struct negf_ctx {
     double* trans_d = nullptr;
 
     // tuning choices (negf_set_tuning / negf_autotune)
-    negf_tuning tune{2, 128};
+    negf_tuning tune{2, 128, 0};
 
     // forward state
     bool fwd_done = false;
@@ -223,7 +224,8 @@ SandArgs sand_base(const negf_ctx* c, int p0, const Active& act, int np) {
 
 InvWork invwork(negf_ctx* c, void* partner) {
     return InvWork{partner, c->invE, c->invP, c->rowsrc, c->piv, c->coldst, c->status,
-                   c->invN0, c->invN1, c->invComp, c->invN0 ? c->tune.inv_outer : 0};
+                   c->invN0, c->invN1, c->invComp, c->invN0 ? c->tune.inv_outer : 0,
+                   c->invComp2, c->invN0 ? c->tune.inv_mid : 0};
 }
 
 // Synthetic well-conditioned blocks for timing: entries in [-1, 1) from an
@@ -336,7 +338,8 @@ int negf_create(const negf_config* cfg, negf_ctx** out) {
          dev_alloc(c, &c->invP, cap * c->nb * NBMAX_INV * sizeof(double2), c->allocs) &&
          (c->nb <= 64 || (dev_alloc(c, &c->invN0, cap * c->nb * INV_WMAX * sizeof(double2), c->allocs) &&
                           dev_alloc(c, &c->invN1, cap * c->nb * INV_WMAX * sizeof(double2), c->allocs) &&
-                          dev_alloc(c, &c->invComp, cap * c->nb * sizeof(int), c->allocs))) &&
+                          dev_alloc(c, &c->invComp, cap * c->nb * sizeof(int), c->allocs) &&
+                          dev_alloc(c, &c->invComp2, cap * c->nb * sizeof(int), c->allocs))) &&
          dev_alloc(c, &c->rowsrc, cap * c->nb * sizeof(int), c->allocs) &&
          dev_alloc(c, &c->piv, cap * c->nb * sizeof(int), c->allocs) &&
          dev_alloc(c, &c->coldst, cap * c->nb * sizeof(int), c->allocs) &&
@@ -1060,6 +1063,7 @@ int negf_set_tuning(negf_ctx* c, const negf_tuning* t) {
     if (!c || !t) return NEGF_EINVAL;
     if (t->gemm_prefetch < 1 || t->gemm_prefetch > 3) return NEGF_EINVAL;
     if (t->inv_outer != 0 && (t->inv_outer < 64 || t->inv_outer > INV_WMAX || t->inv_outer % 32 != 0)) return NEGF_EINVAL;
+    if (t->inv_mid != 0 && (t->inv_mid < 32 || t->inv_mid > INV_WMAX || t->inv_mid % 32 != 0)) return NEGF_EINVAL;
     c->tune = *t;
     return NEGF_OK;
 }
@@ -1106,15 +1110,18 @@ int negf_autotune(negf_ctx* c, void* stream, int reps, negf_tuning* out) {
         if (err == hipSuccess) err = elapsed(&ms);
         if (err == hipSuccess && (pf == 1 || ms < best_ms)) { best_ms = ms; best.gemm_prefetch = pf; }
     }
-    // block inverse: outer panel width (0: one level)
-    const int cands[] = {0, 64, 96, 128, 160, 192, 256};
+    // block inverse: outer panel width (0: one level) and mid block width (0: two levels)
+    const int cands[][2] = {{0, 0}, {64, 0}, {96, 0}, {128, 0}, {160, 0}, {192, 0}, {256, 0},
+                            {128, 64}, {192, 64}, {256, 64}, {256, 128}};
     best_ms = 0.0f;
     bool first = true;
-    for (int W : cands) {
+    for (const auto& cw : cands) {
+        const int W = cw[0], Wm = cw[1];
         if (err != hipSuccess) break;
         if (W != 0 && (!c->invN0 || W >= n)) continue;
         InvWork w = invwork(c, c->tmp[5]);
         w.W = W;
+        w.Wm = Wm;
         float ms = 0.0f;
         for (int r = 0; r <= reps && err == hipSuccess; ++r) {   // r == 0 warms up
             err = fill(c->tmp[3], (double)n);
@@ -1124,7 +1131,9 @@ int negf_autotune(negf_ctx* c, void* stream, int reps, negf_tuning* out) {
             if (err == hipSuccess) err = elapsed(&one);
             if (r > 0) ms += one;
         }
-        if (err == hipSuccess && (first || ms < best_ms)) { best_ms = ms; best.inv_outer = W; first = false; }
+        if (err == hipSuccess && (first || ms < best_ms)) {
+            best_ms = ms; best.inv_outer = W; best.inv_mid = Wm; first = false;
+        }
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);

@@ -66,6 +66,8 @@ struct InvWork {
     void* N0; void* N1;  // narrow ping-pong copies of an outer panel, [np][n][INV_WMAX] each (NULL: one level)
     int* comp;           // [np][n] composite row source of an outer panel
     int W;               // outer panel width (a multiple of 32, <= INV_WMAX), 0: one level
+    int* comp2;          // [np][n] composite row source of a mid block, or NULL
+    int Wm;              // mid block width (three levels; a multiple of 32 below W), 0: two levels
 };
 // dst = src^-1 for every active point (Gauss-Jordan, partial pivoting).  src
 // is destroyed.  dt = DT_C128 or DT_C64 (matrix and arithmetic type).

@@ -45,6 +45,8 @@ struct PanelArgs {
     int* coldst;                   // [np][n]
     int* comp;                     // [np][n] composite row source over an outer panel, or NULL
     int comp_first;                // first inner step of the outer panel
+    int* comp2;                    // [np][n] composite row source over a mid block, or NULL
+    int comp2_first;               // first inner step of the mid block
     int n, k0, nbk, np, last;
     Active act;
     int* status;
@@ -226,19 +228,23 @@ __global__ __launch_bounds__(NT) void gj_panel(PanelArgs a) {
     if (tid < nbk) pg[k0 + tid] = sh_piv[tid];
     if (tid == 0 && sh_bad) raise_status(a.status, sh_bad);
     if (a.comp) {
-        // composite row source of the outer panel: comp'[p] = comp[rsrc[p]]
+        // composite row sources of the outer panel (and of the mid block):
+        // comp'[p] = comp[rsrc[p]], starting from rsrc at the first inner step
         int* cm = a.comp + (long long)q * n;
-        int nv[RPT];
+        int* cm2 = a.comp2 ? a.comp2 + (long long)q * n : nullptr;
+        int nv[RPT], nv2[RPT];
 #pragma unroll
         for (int t = 0; t < RPT; ++t) {
             const int r = tid + NT * t;
             nv[t] = (r < n) ? (a.comp_first ? rsrc[r] : cm[rsrc[r]]) : 0;
+            nv2[t] = (r < n && cm2) ? (a.comp2_first ? rsrc[r] : cm2[rsrc[r]]) : 0;
         }
         __syncthreads();
 #pragma unroll
         for (int t = 0; t < RPT; ++t) {
             const int r = tid + NT * t;
             if (r < n) cm[r] = nv[t];
+            if (r < n && cm2) cm2[r] = nv2[t];
         }
     }
 
@@ -583,7 +589,7 @@ static hipError_t inverse_typed(hipStream_t s, void* src, long long s_src, void*
         for (int k0 = 0; k0 < n; k0 += ps.nb) {
             const int nbk = (n - k0 < ps.nb) ? (n - k0) : ps.nb;
             const int last = (k0 + nbk == n);
-            PanelArgs pa{cur, s_cur, n, 0, w.E, w.Prow, 0, n, w.rowsrc, w.piv, w.coldst, nullptr, 0,
+            PanelArgs pa{cur, s_cur, n, 0, w.E, w.Prow, 0, n, w.rowsrc, w.piv, w.coldst, nullptr, 0, nullptr, 0,
                          n, k0, nbk, np, last, act, w.status, nullptr, 0, 0, 0, 0, 0};
             launch_panel<R>(s, ps, np, lds, pa, false);
             hipError_t e = hipGetLastError();
@@ -597,6 +603,10 @@ static hipError_t inverse_typed(hipStream_t s, void* src, long long s_src, void*
         }
         return hipSuccess;
     }
+    // three levels: mid blocks of Wm columns inside an outer panel (fused inner panels
+    // with one row per thread only); the last mid block of each outer panel is fused
+    // over the whole outer panel, the others get a rank-Wm update of the outer panel
+    const bool three = w.Wm > 0 && w.Wm % 32 == 0 && w.comp2 && ps.rpt == 1 && ps.nb == 32;
     int Wk = w.W;
     for (int K0 = 0; K0 < n; K0 += Wk) {
         // a remainder narrower than half an outer panel joins the current one (one
@@ -616,26 +626,50 @@ static hipError_t inverse_typed(hipStream_t s, void* src, long long s_src, void*
         bool in_narrow = false;
         void* nbuf[2] = {w.N0, w.N1};
         int nb_i = 0;
-        for (int k0 = K0; k0 < K0 + W; k0 += ps.nb) {
-            const int nbk = (K0 + W - k0 < ps.nb) ? (K0 + W - k0) : ps.nb;
-            const int last = (k0 + nbk == n);
-            const bool fuse = ps.rpt == 1 && nbk == ps.nb;
-            void* ydst = fuse && in_narrow ? const_cast<void*>(ncur) : nbuf[nb_i];
-            PanelArgs pa{ncur, s_ncur, ld_ncur, xc_ncur, w.E, w.Prow, K0, W, w.rowsrc, w.piv, w.coldst,
-                         w.comp, k0 == K0, n, k0, nbk, np, last, act, w.status,
-                         ydst, sN, W, K0, K0, W};
-            launch_panel<R>(s, ps, np, lds, pa, fuse);
-            hipError_t e = hipGetLastError();
-            if (e != hipSuccess) return e;
-            if (!fuse) {
-                UpdArgs ua{ncur, s_ncur, ld_ncur, xc_ncur, ydst, sN, W, K0, K0, W,
-                           w.E, NBMAX, w.Prow, W, K0, w.rowsrc, w.coldst, n, k0, nbk, np, 0, act};
-                e = launch_update<R>(s, ua);
+        const int Wm = (three && w.Wm < W) ? w.Wm : W;
+        for (int M0 = K0; M0 < K0 + W; M0 += Wm) {
+            const bool last_mid = M0 + Wm >= K0 + W;
+            const int Wmid = last_mid ? K0 + W - M0 : Wm;
+            // the values the mid update transforms: the outer panel before this mid block
+            const void* mold = ncur;
+            const long long s_mold = s_ncur;
+            const int ld_mold = ld_ncur, xc_mold = xc_ncur;
+            // fused range of the inner panels: this mid block, or the whole outer panel
+            const int uc0 = last_mid ? K0 : M0, unc = last_mid ? W : Wmid;
+            for (int k0 = M0; k0 < M0 + Wmid; k0 += ps.nb) {
+                const int nbk = (M0 + Wmid - k0 < ps.nb) ? (M0 + Wmid - k0) : ps.nb;
+                const int last = (k0 + nbk == n);
+                const bool fuse = ps.rpt == 1 && nbk == ps.nb;
+                void* ydst = fuse && in_narrow ? const_cast<void*>(ncur) : nbuf[nb_i];
+                PanelArgs pa{ncur, s_ncur, ld_ncur, xc_ncur, w.E, w.Prow, K0, W, w.rowsrc, w.piv, w.coldst,
+                             w.comp, k0 == K0, last_mid ? nullptr : w.comp2, k0 == M0, n, k0, nbk, np, last, act,
+                             w.status, ydst, sN, W, K0, uc0, unc};
+                launch_panel<R>(s, ps, np, lds, pa, fuse);
+                hipError_t e = hipGetLastError();
                 if (e != hipSuccess) return e;
+                if (!fuse) {
+                    UpdArgs ua{ncur, s_ncur, ld_ncur, xc_ncur, ydst, sN, W, K0, K0, W,
+                               w.E, NBMAX, w.Prow, W, K0, w.rowsrc, w.coldst, n, k0, nbk, np, 0, act};
+                    e = launch_update<R>(s, ua);
+                    if (e != hipSuccess) return e;
+                }
+                if (ydst == nbuf[nb_i]) nb_i ^= 1;
+                ncur = ydst; s_ncur = sN; ld_ncur = W; xc_ncur = K0;
+                in_narrow = true;
             }
-            if (ydst == nbuf[nb_i]) nb_i ^= 1;
-            ncur = ydst; s_ncur = sN; ld_ncur = W; xc_ncur = K0;
-            in_narrow = true;
+            if (!last_mid) {
+                // mid update: the mid block's composite transform on the rest of the outer
+                // panel, from its values before the block; the block's own columns are
+                // copied from the transform columns.  Out of place into the other buffer.
+                const void* Emid = static_cast<const char*>(ncur) + (size_t)(M0 - K0) * sizeof(cplx<R>);
+                void* ynext = nbuf[nb_i];
+                UpdArgs ua{mold, s_mold, ld_mold, xc_mold, ynext, sN, W, K0, K0, W,
+                           Emid, W, nullptr, 0, 0, w.comp2, w.coldst, n, M0, Wmid, np, 0, act};
+                hipError_t e = launch_update<R>(s, ua);
+                if (e != hipSuccess) return e;
+                nb_i ^= 1;
+                ncur = ynext; s_ncur = sN; ld_ncur = W; xc_ncur = K0;
+            }
         }
         // outer update: every column from the matrix before the outer panel, the panel's
         // columns from the narrow copy; the composite row map gathers rows and pivot rows

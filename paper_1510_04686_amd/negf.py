@@ -39,7 +39,7 @@ class negf_config(ctypes.Structure):
 
 
 class negf_tuning(ctypes.Structure):
-    _fields_ = [("gemm_prefetch", c_int), ("inv_outer", c_int)]
+    _fields_ = [("gemm_prefetch", c_int), ("inv_outer", c_int), ("inv_mid", c_int)]
 
 
 class negf_system(ctypes.Structure):
@@ -311,11 +311,11 @@ def negf_gemm_timing(ctx, stream=None):
 def negf_get_tuning(ctx):
     t = negf_tuning()
     _check("negf_get_tuning", lib().negf_get_tuning(ctx.handle, ctypes.byref(t)))
-    return {"gemm_prefetch": int(t.gemm_prefetch), "inv_outer": int(t.inv_outer)}
+    return {"gemm_prefetch": int(t.gemm_prefetch), "inv_outer": int(t.inv_outer), "inv_mid": int(t.inv_mid)}
 
 
-def negf_set_tuning(ctx, gemm_prefetch, inv_outer):
-    t = negf_tuning(int(gemm_prefetch), int(inv_outer))
+def negf_set_tuning(ctx, gemm_prefetch, inv_outer, inv_mid=0):
+    t = negf_tuning(int(gemm_prefetch), int(inv_outer), int(inv_mid))
     _check("negf_set_tuning", lib().negf_set_tuning(ctx.handle, ctypes.byref(t)))
 
 
@@ -324,5 +324,5 @@ def negf_autotune(ctx, reps=3, stream=None):
     fastest and returns it as a dict."""
     t = negf_tuning()
     _check("negf_autotune", lib().negf_autotune(ctx.handle, _stream(stream), int(reps), ctypes.byref(t)))
-    return {"gemm_prefetch": int(t.gemm_prefetch), "inv_outer": int(t.inv_outer)}
+    return {"gemm_prefetch": int(t.gemm_prefetch), "inv_outer": int(t.inv_outer), "inv_mid": int(t.inv_mid)}
 

@@ -86,7 +86,7 @@ class RGFSolver:
         self.streams = [torch.cuda.Stream(self.device) for _ in range(self.lanes)] if self.lanes > 1 else None
         self.tuning = self._tune(tune, precision)
         for c in self.ctxs[1:]:
-            N.negf_set_tuning(c, self.tuning["gemm_prefetch"], self.tuning["inv_outer"])
+            N.negf_set_tuning(c, self.tuning["gemm_prefetch"], self.tuning["inv_outer"], self.tuning["inv_mid"])
         self._last_fwd = None
         self.eta_fill = 0
         mixed = self.prec == N.NEGF_MIXED
@@ -102,13 +102,14 @@ class RGFSolver:
         if tune is None:
             return N.negf_get_tuning(self.ctx)
         if isinstance(tune, dict):
-            N.negf_set_tuning(self.ctx, tune["gemm_prefetch"], tune["inv_outer"])
+            N.negf_set_tuning(self.ctx, tune["gemm_prefetch"], tune["inv_outer"], tune.get("inv_mid", 0))
             return N.negf_get_tuning(self.ctx)
         if tune != "auto":
             raise ValueError(f"tune must be None, 'auto' or a dict, not {tune!r}")
         path = os.environ.get("NEGF_TUNING_CACHE",
                               os.path.join(os.path.expanduser("~"), ".cache", "paper_1510_04686_amd", "tuning.json"))
-        key = f"{torch.cuda.get_device_name(self.device)}|nb={self.wl.nb}|cap={self.capacity}|{precision}"
+        # the key names the candidate set too, so choices made among fewer shapes are redone
+        key = f"{torch.cuda.get_device_name(self.device)}|nb={self.wl.nb}|cap={self.capacity}|{precision}|shapes=3"
         cache = {}
         try:
             with open(path) as fh:
@@ -117,7 +118,7 @@ class RGFSolver:
             cache = {}
         if key in cache:
             t = cache[key]
-            N.negf_set_tuning(self.ctx, t["gemm_prefetch"], t["inv_outer"])
+            N.negf_set_tuning(self.ctx, t["gemm_prefetch"], t["inv_outer"], t.get("inv_mid", 0))
             return N.negf_get_tuning(self.ctx)
         t = N.negf_autotune(self.ctx, reps=3)
         cache[key] = t

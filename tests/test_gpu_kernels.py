@@ -120,32 +120,38 @@ def test_tuning_validation_and_roundtrip(ctx):
     from paper_1510_04686_amd import negf
     _say("tuning set/get")
     old = negf.negf_get_tuning(ctx)
-    for bad in ((0, 128), (4, 128), (2, 32), (2, 100), (2, 288)):
+    for bad in ((0, 128), (4, 128), (2, 32), (2, 100), (2, 288), (2, 128, 16), (2, 128, 48), (2, 128, 288)):
         with pytest.raises(negf.NegfError):
             negf.negf_set_tuning(ctx, *bad)
     negf.negf_set_tuning(ctx, 1, 64)
-    assert negf.negf_get_tuning(ctx) == {"gemm_prefetch": 1, "inv_outer": 64}
-    negf.negf_set_tuning(ctx, old["gemm_prefetch"], old["inv_outer"])
+    assert negf.negf_get_tuning(ctx) == {"gemm_prefetch": 1, "inv_outer": 64, "inv_mid": 0}
+    negf.negf_set_tuning(ctx, 3, 192, 64)
+    assert negf.negf_get_tuning(ctx) == {"gemm_prefetch": 3, "inv_outer": 192, "inv_mid": 64}
+    negf.negf_set_tuning(ctx, old["gemm_prefetch"], old["inv_outer"], old["inv_mid"])
 
 
-@pytest.mark.parametrize("W", [0, 64, 96, 192, 256])
-def test_zinv_every_outer_width(ctx, W):
-    """Each outer panel width (and the one-level scheme) gives the same inverse."""
+@pytest.mark.parametrize("W,Wm,n", [(0, 0, 400), (64, 0, 400), (96, 0, 400), (192, 0, 400), (256, 0, 400),
+                                    (128, 64, 400), (192, 64, 400), (256, 64, 400), (256, 128, 400),
+                                    (96, 32, 400), (128, 64, 416), (128, 64, 300), (192, 64, 130)])
+def test_zinv_every_outer_width(ctx, W, Wm, n):
+    """Each outer panel width, with and without mid blocks (three levels), and
+    the one-level scheme give the same inverse; 416 and 300 merge a remainder
+    into the last outer panel (300: its last mid block ends in a 12-column
+    panel that is not fused)."""
     from paper_1510_04686_amd import negf
-    _say(f"zinv outer width {W}")
+    _say(f"zinv outer width {W}, mid {Wm}, n={n}")
     old = negf.negf_get_tuning(ctx)
-    rng = np.random.default_rng(3000 + W)
-    n = 400
+    rng = np.random.default_rng(3000 + W + 7 * Wm + n)
     A = _rand(rng, (3, n, n))
     A[1][np.diag_indices(n)] = 0
     ref = np.linalg.inv(A)
     try:
-        negf.negf_set_tuning(ctx, old["gemm_prefetch"], W)
+        negf.negf_set_tuning(ctx, old["gemm_prefetch"], W, Wm)
         dX = torch.zeros((3, n, n), dtype=torch.complex128, device="cuda")
         negf.negf_zinv_batched(ctx, torch.from_numpy(A.copy()).cuda(), dX)
         assert negf.negf_sync_status(ctx) == 0
     finally:
-        negf.negf_set_tuning(ctx, old["gemm_prefetch"], old["inv_outer"])
+        negf.negf_set_tuning(ctx, old["gemm_prefetch"], old["inv_outer"], old["inv_mid"])
     X = dX.cpu().numpy()
     for b in range(3):
         err = np.max(np.abs(X[b] - ref[b])) / np.max(np.abs(ref[b]))
@@ -165,7 +171,7 @@ def test_zgemm_prefetch_depths_agree(ctx, pf, n):
         negf.negf_set_tuning(ctx, pf, old["inv_outer"])
         negf.negf_zgemm_batched(ctx, torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), dC, 0, 1)
     finally:
-        negf.negf_set_tuning(ctx, old["gemm_prefetch"], old["inv_outer"])
+        negf.negf_set_tuning(ctx, old["gemm_prefetch"], old["inv_outer"], old["inv_mid"])
     ref = A @ B.conj().transpose(0, 2, 1)
     assert np.max(np.abs(dC.cpu().numpy() - ref)) / np.max(np.abs(ref)) < 1e-13 * np.sqrt(n)
 
@@ -175,8 +181,9 @@ def test_autotune_returns_a_valid_choice():
     _say("autotune")
     c = negf.negf_create(nb=200, n_slab_max=1, capacity=4)
     t = negf.negf_autotune(c, reps=1)
-    assert t["gemm_prefetch"] in (1, 2)
+    assert t["gemm_prefetch"] in (1, 2, 3)
     assert t["inv_outer"] == 0 or (64 <= t["inv_outer"] < 200 and t["inv_outer"] % 32 == 0)
+    assert t["inv_mid"] in (0, 64, 128)
     assert negf.negf_get_tuning(c) == t
 
 

@@ -320,3 +320,19 @@ def test_persistent_gemm_gives_the_same_solve(capacity):
         outs.append({k: v.cpu().numpy() for k, v in o.items()})
     for k in outs[0]:
         assert np.array_equal(outs[0][k], outs[1][k]), k
+
+
+def test_three_level_inverse_in_the_full_solve():
+    """Block 400 with the three-level inverse (outer 192, mid 64) against the
+    oracle, every point."""
+    _say("rgf block 400 with the three-level inverse")
+    wl = make_workload("C2", n_slab=5, n_e=3, n_k=2)
+    s = _solver(wl, tune={"gemm_prefetch": 2, "inv_outer": 192, "inv_mid": 64})
+    assert s.tuning["inv_mid"] == 64
+    out = s.solve(want_T=True)
+    torch.cuda.synchronize()
+    assert s.status() == 0
+    pts = [tuple(p) for p in s.points]
+    ref, tols = _ref_and_tol(wl, pts, transmission=True)
+    for p, r in enumerate(ref):
+        _check_point(out, p, r, wl.total_slabs, T=True, tol=tols[p])
