@@ -99,6 +99,29 @@ def test_zinv_fp32(ctx, n):
         assert err < 1e-6 * cond * np.sqrt(n), (b, err, cond)
 
 
+@pytest.mark.parametrize("W,Wm,n", [(128, 0, 300), (128, 64, 300), (192, 64, 400), (96, 32, 130)])
+def test_zinv_fp32_outer_and_mid_widths(ctx, W, Wm, n):
+    """FP32 (the mixed-precision path) through the two- and three-level schemes."""
+    from paper_1510_04686_amd import negf
+    _say(f"zinv fp32 outer {W} mid {Wm} n={n}")
+    old = negf.negf_get_tuning(ctx)
+    rng = np.random.default_rng(2500 + n + W + Wm)
+    A = _rand(rng, (2, n, n), np.complex64) + 4 * np.eye(n, dtype=np.complex64)
+    ref = np.linalg.inv(A.astype(np.complex128))
+    try:
+        negf.negf_set_tuning(ctx, old["gemm_prefetch"], W, Wm)
+        dX = torch.zeros((2, n, n), dtype=torch.complex64, device="cuda")
+        negf.negf_zinv_batched(ctx, torch.from_numpy(A.copy()).cuda(), dX)
+        assert negf.negf_sync_status(ctx) == 0
+    finally:
+        negf.negf_set_tuning(ctx, old["gemm_prefetch"], old["inv_outer"], old["inv_mid"])
+    X = dX.cpu().numpy()
+    for b in range(2):
+        cond = np.linalg.cond(A[b])
+        err = np.max(np.abs(X[b] - ref[b])) / np.max(np.abs(ref[b]))
+        assert err < 1e-6 * cond * np.sqrt(n), (b, err, cond)
+
+
 def test_zinv_flags_singular_block(ctx):
     from paper_1510_04686_amd import negf
     _say("zinv singular")
