@@ -121,8 +121,8 @@ def main():
                     help="first run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the (E,k) points of a step "
-              "shard over GPUs by energy blocks, which this build does not launch.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the multi-GPU form, which would "
+              "shard the (E,k) points of a step over GPUs by energy blocks, is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

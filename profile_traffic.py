@@ -1,18 +1,19 @@
 """HBM traffic of the batched GEMM from two rocprofv3 counter runs.
 
-Reads the FETCH_SIZE and WRITE_SIZE databases that these commands write (one
-counter per run, each run also copies a known 256 MiB buffer first so the
-counters can be calibrated; both use the library's default kernel shapes so
-the two runs dispatch the same kernels):
+Reads the FETCH_SIZE and WRITE_SIZE databases that these commands write into
+an output directory OUT (one counter per run, each run also copies a known
+256 MiB buffer first so the counters can be calibrated; both use the library's
+default kernel shapes so the two runs dispatch the same kernels):
 
-    rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_FETCH_SIZE -o run -- \
-        python3 bench.py --n-e 16 --no-cpu-baseline --tune default --copy-calibration 256 > gpurun_out/pmc_FETCH_SIZE.log
-    rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_WRITE_SIZE -o run -- \
-        python3 bench.py --n-e 16 --no-cpu-baseline --tune default --copy-calibration 256 > gpurun_out/pmc_WRITE_SIZE.log
+    rocprofv3 --pmc FETCH_SIZE -d OUT/pmc_FETCH_SIZE -o run -- \
+        python3 bench.py --n-e 16 --no-cpu-baseline --tune default --copy-calibration 256 > OUT/pmc_FETCH_SIZE.log
+    rocprofv3 --pmc WRITE_SIZE -d OUT/pmc_WRITE_SIZE -o run -- \
+        python3 bench.py --n-e 16 --no-cpu-baseline --tune default --copy-calibration 256 > OUT/pmc_WRITE_SIZE.log
 
 and writes profiles/gemm_traffic_C2.json (read by bench.py for the roofline's
 `traffic`, valid while the GEMM sources keep the recorded SHA-1) and a short
-text summary.  Usage: python profile_traffic.py [gpurun_out]
+text summary that records the commands with OUT as given.
+Usage: python profile_traffic.py OUT
 """
 import collections
 import hashlib
@@ -47,6 +48,7 @@ def sources_sha1():
 
 
 def main(base):
+    out_dir = os.path.basename(os.path.normpath(base))
     fetch, write = _rows(base, "FETCH_SIZE"), _rows(base, "WRITE_SIZE")
     assert [r[1] for r in fetch] == [r[1] for r in write], "the two runs dispatched different kernels"
     copy_f = [v for _, k, g, v in fetch if "copyBuffer" in k and g == 131072][0] * 1024
@@ -75,10 +77,9 @@ def main(base):
         "algorithmic_bytes_per_point_launch": 3 * 16 * b * b,
         "calibration": {"copy_bytes": COPY_BYTES, "FETCH_SIZE_factor": ff, "WRITE_SIZE_factor": fw},
         "commands": [
-            "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_FETCH_SIZE -o run -- python3 bench.py --n-e 16 "
-            "--no-cpu-baseline --tune default --copy-calibration 256",
-            "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_WRITE_SIZE -o run -- python3 bench.py --n-e 16 "
-            "--no-cpu-baseline --tune default --copy-calibration 256",
+            f"rocprofv3 --pmc {c} -d {out_dir}/pmc_{c} -o run -- python3 bench.py --n-e 16 "
+            "--no-cpu-baseline --tune default --copy-calibration 256"
+            for c in ("FETCH_SIZE", "WRITE_SIZE")
         ],
     }
     with open(os.path.join(ROOT, "profiles", "gemm_traffic_C2.json"), "w") as fh:
@@ -97,7 +98,7 @@ def main(base):
         "Commands (one counter per run, each with one plain 256 MiB device copy first for calibration):",
         "",
         *["    " + c for c in out["commands"]],
-        "    python profile_traffic.py gpurun_out",
+        f"    python profile_traffic.py {out_dir}",
         "",
         f"Calibration (the 256 MiB copy): FETCH_SIZE factor {ff:.2f}, WRITE_SIZE factor {fw:.2f}.",
         "",
@@ -119,4 +120,6 @@ def main(base):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1] if len(sys.argv) > 1 else os.path.join(ROOT, "gpurun_out"))
+    if len(sys.argv) != 2:
+        sys.exit("usage: python profile_traffic.py OUT  (the directory the two rocprofv3 runs wrote into)")
+    main(sys.argv[1])

@@ -68,7 +68,7 @@ def test_block400_70_slabs_bench_configuration():
         assert _rel(GG[p], d(r["GG"])) < tol
         # the trace sums b * m products of size |H_{i,i+1}| |G^<|: its rounding scales with
         # |G^<| even where the current itself is exponentially small (E far above mu), so
-        # it is judged on this point's G^< and on the device's current scale
+        # it is compared on the scale of this point's G^< and of the device's current
         ref_scale = max(np.max(np.abs(r["bond"])), 1e-3 * np.max(np.abs(d(r["GL"]))), 1e-6 * jscale)
         assert np.max(np.abs(bond[p, :N - 1] - r["bond"])) < tol * 10 * ref_scale
         assert abs(T[p] - r["T"]) < tol * max(1.0, abs(r["T"]))
@@ -85,8 +85,8 @@ def test_block1200_200_slabs_adjoint_against_gpu_differences():
     w = rng.normal(size=n0.shape)
     g = s.density_vjp(torch.from_numpy(w)).cpu().numpy()
     assert np.all(np.isfinite(g))
-    # directional derivative along a change of 8 seeded atoms by +-h (the survey's per-atom
-    # difference step; a dense random direction would make the step itself large)
+    # directional derivative along a change of 8 seeded atoms by +-h (a per-atom difference
+    # step; a dense random direction would make the step itself large)
     delta = np.zeros(n0.shape)
     flat = rng.choice(delta.size, size=8, replace=False)
     delta.flat[flat] = rng.choice([-1.0, 1.0], size=8)
