@@ -5,8 +5,8 @@
 // point of a batch.  One launch covers the whole batch: a 64 x 64 output tile
 // of one point per 256-thread workgroup (4 wavefronts of 32 x 32), K staged
 // through LDS in 16-wide double-buffered slices, split real/imaginary planes.
-// A complex product is three real MFMA products on v_mfma_f64_16x16x4f64
-// (FP64, the 3M form) or four on v_mfma_f32_16x16x4f32 (FP32).
+// A complex product is three real MFMA products (the 3M form) on
+// v_mfma_f64_16x16x4f64 (FP64) or v_mfma_f32_16x16x4f32 (FP32).
 #include <algorithm>
 
 #include "negf_internal.hpp"

@@ -91,7 +91,11 @@ __device__ inline void store_slice(Acc (*S)[BK][LP], int tid, const TX (&r)[4]) 
     }
 }
 
-template <typename Acc> struct ThreeM { static constexpr bool value = sizeof(Acc) == 8; };
+// Complex products use three real MFMA products (the 3M form): with
+// P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi), the product is
+// (P1 - P2) + i (P3 - P1 - P2), 12 MFMAs per complex 16x16x4 step instead of
+// 16.  The imaginary part's rounding is bounded by the unit roundoff times
+// (|Ar| + |Ai|)(|Br| + |Bi|) instead of |Ar||Bi| + |Ai||Br|.
 
 // The part of a 64 x 64 output tile a wave computes: tile-local origin
 // (am0, bn0) and its count of 16-row and 16-column blocks inside the valid
@@ -115,8 +119,8 @@ __device__ inline WaveTile wave_tile(int wave, int vr, int vc) {
 }
 
 // Accumulates one staged K slice into the (up to) 2 x 2 blocks of 16 x 16 at
-// tile-local (am0, bn0) that this wave owns.  With the 3M form cr, ci, cs hold P1, P2, P3 until finish_products();
-// otherwise cr, ci hold the real and imaginary parts and cs is unused.
+// tile-local (am0, bn0) that this wave owns; cr, ci, cs accumulate P1, P2, P3
+// of the 3M form until finish_products().
 template <typename Acc, int MI, int NJ>
 __device__ inline void mma_slice(Acc (*As)[BK][LP], Acc (*Bs)[BK][LP], int lane, int am0, int bn0,
                                  typename MF<Acc>::V (&cr)[2][2], typename MF<Acc>::V (&ci)[2][2],
@@ -144,56 +148,36 @@ __device__ inline void mma_slice(Acc (*As)[BK][LP], Acc (*Bs)[BK][LP], int lane,
         const int c = kk & 1;
         if (kk + 1 < BK / 4) frag(kk + 1, c ^ 1);
         __builtin_amdgcn_sched_barrier(0);   // the reads stay ahead of this step's products
-        if constexpr (ThreeM<Acc>::value) {
-            Acc sa[MI], sb[NJ];
+        Acc sa[MI], sb[NJ];
 #pragma unroll
-            for (int mi = 0; mi < MI; ++mi) sa[mi] = ar[c][mi] + ai[c][mi];
+        for (int mi = 0; mi < MI; ++mi) sa[mi] = ar[c][mi] + ai[c][mi];
 #pragma unroll
-            for (int nj = 0; nj < NJ; ++nj) sb[nj] = br[c][nj] + bi[c][nj];
+        for (int nj = 0; nj < NJ; ++nj) sb[nj] = br[c][nj] + bi[c][nj];
 #pragma unroll
-            for (int mi = 0; mi < MI; ++mi)
+        for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
-                for (int nj = 0; nj < NJ; ++nj) {
-                    cr[mi][nj] = MF<Acc>::mma(ar[c][mi], br[c][nj], cr[mi][nj]);
-                    ci[mi][nj] = MF<Acc>::mma(ai[c][mi], bi[c][nj], ci[mi][nj]);
-                    cs[mi][nj] = MF<Acc>::mma(sa[mi], sb[nj], cs[mi][nj]);
-                }
-        } else {
-#pragma unroll
-            for (int mi = 0; mi < MI; ++mi)
-#pragma unroll
-                for (int nj = 0; nj < NJ; ++nj) {
-                    cr[mi][nj] = MF<Acc>::mma(ar[c][mi], br[c][nj], cr[mi][nj]);
-                    ci[mi][nj] = MF<Acc>::mma(ar[c][mi], bi[c][nj], ci[mi][nj]);
-                }
-#pragma unroll
-            for (int mi = 0; mi < MI; ++mi)
-#pragma unroll
-                for (int nj = 0; nj < NJ; ++nj) {
-                    cr[mi][nj] = MF<Acc>::mma(-ai[c][mi], bi[c][nj], cr[mi][nj]);
-                    ci[mi][nj] = MF<Acc>::mma(ai[c][mi], br[c][nj], ci[mi][nj]);
-                }
-        }
+            for (int nj = 0; nj < NJ; ++nj) {
+                cr[mi][nj] = MF<Acc>::mma(ar[c][mi], br[c][nj], cr[mi][nj]);
+                ci[mi][nj] = MF<Acc>::mma(ai[c][mi], bi[c][nj], ci[mi][nj]);
+                cs[mi][nj] = MF<Acc>::mma(sa[mi], sb[nj], cs[mi][nj]);
+            }
     }
 }
 
-// Turns the 3M partial products into real and imaginary parts (no-op for the
-// four-product form).
+// Turns the partial products P1, P2, P3 into real and imaginary parts.
 template <typename Acc>
 __device__ inline void finish_products(typename MF<Acc>::V (&cr)[2][2], typename MF<Acc>::V (&ci)[2][2],
                                        const typename MF<Acc>::V (&cs)[2][2]) {
-    if constexpr (ThreeM<Acc>::value) {
 #pragma unroll
-        for (int mi = 0; mi < 2; ++mi)
+    for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-            for (int nj = 0; nj < 2; ++nj)
+        for (int nj = 0; nj < 2; ++nj)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const Acc p1 = cr[mi][nj][r], p2 = ci[mi][nj][r];
-                    cr[mi][nj][r] = p1 - p2;
-                    ci[mi][nj][r] = (cs[mi][nj][r] - p1) - p2;
-                }
-    }
+            for (int r = 0; r < 4; ++r) {
+                const Acc p1 = cr[mi][nj][r], p2 = ci[mi][nj][r];
+                cr[mi][nj][r] = p1 - p2;
+                ci[mi][nj][r] = (cs[mi][nj][r] - p1) - p2;
+            }
 }
 
 }  // namespace negf
