@@ -41,10 +41,8 @@ __device__ inline void tile_of(int t, int tiles, int& ti, int& tj) {
     }
 }
 
-// Writes this wave's part of the finished tile (m0, n0) of point q.  LEAN
-// keeps the scheduler from interleaving the four 16 x 16 blocks (fewer live
-// registers, for the persistent kernel, where the epilogue sits inside a loop).
-template <typename TC, typename Acc, int EPI, bool LEAN = false>
+// Writes this wave's part of the finished tile (m0, n0) of point q.
+template <typename TC, typename Acc, int EPI>
 __device__ inline void gemm_epilogue(const GemmArgs& g, int q, int m0, int n0, const WaveTile& wt, int lane,
                                      const typename MF<Acc>::V (&cr)[2][2], const typename MF<Acc>::V (&ci)[2][2]) {
     constexpr bool AH = (EPI == EPI_STORE_AH || EPI == EPI_ADD_TTD_AH);
@@ -95,7 +93,6 @@ __device__ inline void gemm_epilogue(const GemmArgs& g, int q, int m0, int n0, c
                     }
                 }
             }
-            if constexpr (LEAN) __builtin_amdgcn_sched_barrier(0);
         }
     }
 }
@@ -303,7 +300,7 @@ __global__ __launch_bounds__(256, 2) void gemm_persist_kernel(GemmArgs g) {
         else if (wt.nmi == 1 && wt.nnj == 1) NEGF_PERSIST_TILE(1, 1)
         else NEGF_PERSIST_TILE(0, 0)
         finish_products<Acc>(cr, ci, cs);
-        gemm_epilogue<TC, Acc, EPI, true>(g, cq, cm0, cn0, wt, lane, cr, ci);
+        gemm_epilogue<TC, Acc, EPI>(g, cq, cm0, cn0, wt, lane, cr, ci);
         if (ln >= total) return;
         cq = nq; cm0 = nm0; cn0 = nn0;
         // the new tile's second slice: both register sets are free here
