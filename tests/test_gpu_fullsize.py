@@ -1,5 +1,5 @@
 """GPU at the full block and device sizes of the headline workloads, in the
-launch configuration the benchmark times (256-point batches, measured kernel
+launch configuration the benchmark times (512-point batches, measured kernel
 shapes): sampled points against the oracle one by one, and properties that
 hold at any size (current conservation with the eta sink, positivity of the
 spectral function and of the occupation, G^> = G^< + G^R - G^A) on every
@@ -29,9 +29,9 @@ def _rel(a, b):
 
 def test_block400_70_slabs_bench_configuration():
     from paper_1510_04686_amd.runtime import RGFSolver
-    _say("C2 geometry (block 400, 70 slabs, 8 k) x 64 E in 256-point batches")
+    _say("C2 geometry (block 400, 70 slabs, 8 k) x 64 E in one 512-point batch, as the bench runs it")
     wl = make_workload("C2", n_e=64)
-    s = RGFSolver(wl, capacity=256, tune="auto")
+    s = RGFSolver(wl, capacity=512, tune="auto")
     out = s.solve(want_T=True)
     torch.cuda.synchronize()
     assert s.status() == 0 and s.lead_status == 0 and s.lead_dual == 1
@@ -104,3 +104,96 @@ def test_block1200_200_slabs_adjoint_against_gpu_differences():
     ad = float(np.sum(g * delta))
     _say(f"  adjoint {ad:.9e}  differences {fd:.9e}")
     assert abs(fd - ad) < 1e-6 * max(abs(ad), np.max(np.abs(g)))
+
+
+def _properties(wl, out, counts, pts):
+    """Checks that hold at any size on every point: spectral function and
+    occupation non-negative, G^> = G^< + G^R - G^A, and the eta sink balance of
+    the bond currents j_{i-1} - j_i = 2 eta Tr(-i G^<_ii) on interior slabs
+    (ballistic solves only)."""
+    GR, GL, GG = (out[k].cpu().numpy() for k in ("GR", "GL", "GG"))
+    bond = out["bond"].cpu().numpy()
+    assert np.all(np.isfinite(GR)) and np.all(np.isfinite(GL)) and np.all(np.isfinite(bond))
+    scale_g = np.max(np.abs(GR))
+    assert np.min(-GR.imag) > -1e-10 * scale_g
+    assert np.min(GL.imag) > -1e-10 * np.max(np.abs(GL))
+    assert np.max(np.abs(GG - (GL + GR - GR.conj()))) < 1e-12 * scale_g
+    jscale = max(np.max(np.abs(bond)), 1e-300)
+    for p in range(len(pts)):
+        N = int(counts[pts[p][0]])
+        sink = 2 * wl.eta * GL[p, :N].imag.sum(axis=1)
+        lhs = bond[p, :N - 2] - bond[p, 1:N - 1]
+        # the trace sums b * m products of size up to |G^R| |G^<| (large at an alloy's
+        # resonances, far above the net current), so its rounding has that floor
+        floor = 1e-14 * wl.nb * np.max(np.abs(GR[p, :N])) * np.max(np.abs(GL[p, :N]))
+        assert np.max(np.abs(lhs - sink[1:N - 1])) < 1e-8 * jscale + floor, p
+
+
+def test_block240_120_slabs_scba_graph_configuration():
+    """C3 geometry (block 240, 120 slabs) on the 5 meV grid: the ballistic pass
+    against the oracle at sampled points and the properties on every point,
+    then two SCBA iterations in the captured graph (as the bench runs them)
+    equal to the same iterations run eagerly, with causal scattering
+    self-energies (Im Sigma^R <= 0, Im Sigma^< >= 0)."""
+    from paper_1510_04686_amd.runtime import RGFSolver
+    _say("C3 geometry (block 240, 120 slabs) x 2 k x 48 E: ballistic vs oracle, SCBA graph vs eager")
+    wl = make_workload("C3", n_e=48, n_k=2)
+    s = RGFSolver(wl, tune="auto")
+    out = s.solve()
+    torch.cuda.synchronize()
+    assert s.status() == 0
+    counts = np.diff(wl.slab_offset)
+    _properties(wl, out, counts, s.points)
+    rng = np.random.default_rng(240)
+    pts = [tuple(int(x) for x in s.points[p]) for p in rng.choice(s.n_points, size=2, replace=False)]
+    ref = O.solve_points(wl, pts)
+    alt = O.solve_points(wl, pts, variant="alt")
+    d = lambda x: np.diagonal(x, axis1=1, axis2=2)
+    for pt, r, a in zip(pts, ref, alt):
+        p = s.index[pt]
+        tol = max(1e-10, 100 * max(_rel(a[k], r[k]) for k in ("GR", "GL")))
+        _say(f"  point {list(pt)} tol {tol:.1e}")
+        assert _rel(out["GR"][p].cpu().numpy(), d(r["GR"])) < tol
+        assert _rel(out["GL"][p].cpu().numpy(), d(r["GL"])) < tol
+    del out
+    res = {}
+    for graph in (True, False):
+        o, hist = s.scba(n_iter=2, graph=graph)
+        torch.cuda.synchronize()
+        assert s.status() == 0
+        res[graph] = ({k: o[k].cpu().numpy() for k in ("GR", "GL", "bond")}, hist,
+                      s.scat_R.cpu().numpy(), s.scat_L.cpu().numpy())
+    for k in ("GR", "GL", "bond"):
+        assert np.array_equal(res[True][0][k], res[False][0][k]), k
+    assert res[True][1] == res[False][1]
+    sigR, sigL = res[True][2], res[True][3]
+    assert np.max(sigR.imag) <= 1e-14 * np.max(np.abs(sigR))
+    assert np.min(sigL.imag) >= -1e-14 * np.max(np.abs(sigL))
+
+
+def test_block400_ragged_alloy_samples_fp64():
+    """C4 geometry in FP64: three alloy samples of 50-90 slabs (block 400) in one
+    ragged 512-point batch configuration: sampled points against the oracle and
+    the properties on every point."""
+    from paper_1510_04686_amd.runtime import RGFSolver
+    _say("C4 geometry (block 400, ragged 50-90 slabs) x 3 samples x 32 E in FP64")
+    wl = make_workload("C4", n_samples=3, n_e=32)
+    counts = np.diff(wl.slab_offset)
+    assert len(set(counts.tolist())) > 1
+    s = RGFSolver(wl, tune="auto")
+    out = s.solve()
+    torch.cuda.synchronize()
+    assert s.status() == 0
+    _properties(wl, out, counts, s.points)
+    rng = np.random.default_rng(400)
+    pts = [tuple(int(x) for x in s.points[p]) for p in rng.choice(s.n_points, size=2, replace=False)]
+    ref = O.solve_points(wl, pts)
+    alt = O.solve_points(wl, pts, variant="alt")
+    d = lambda x: np.diagonal(x, axis1=1, axis2=2)
+    for pt, r, a in zip(pts, ref, alt):
+        p = s.index[pt]
+        N = int(counts[pt[0]])
+        tol = max(1e-10, 100 * max(_rel(a[k], r[k]) for k in ("GR", "GL")))
+        _say(f"  point {list(pt)} ({N} slabs) tol {tol:.1e}")
+        assert _rel(out["GR"][p, :N].cpu().numpy(), d(r["GR"])) < tol
+        assert _rel(out["GL"][p, :N].cpu().numpy(), d(r["GL"])) < tol
