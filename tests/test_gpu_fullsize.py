@@ -22,6 +22,19 @@ def _say(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+@pytest.fixture(autouse=True)
+def _release_cached_memory():
+    """These workloads take most of the device memory (the block-400 batch of 512
+    points alone holds ~200 GiB of recursion stores): hand back what earlier
+    tests left in torch's caching allocator first."""
+    import gc
+    gc.collect()
+    torch.cuda.empty_cache()
+    yield
+    gc.collect()
+    torch.cuda.empty_cache()
+
+
 def _rel(a, b):
     a, b = np.asarray(a), np.asarray(b)
     return float(np.max(np.abs(a - b)) / max(float(np.max(np.abs(b))), 1e-300))
