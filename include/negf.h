@@ -288,9 +288,12 @@ int negf_mixed_point_residuals(negf_ctx* ctx, void* stream, int n, double* out);
 
 /* Kernel timing of the dominant kernel family (the batched complex GEMM):
  * enable = 1 records a HIP event pair around every GEMM launch on the launch
- * stream; negf_gemm_timing returns the launch count, summed kernel milliseconds
- * and summed algorithmic flops (8 n^3 per point per launch) since enabling.
- * Synchronises `stream`. */
+ * stream, 2 only around launches whose products run on FP64 matrix cores, 3
+ * only around those on FP32 matrix cores (the block algebra of a mixed
+ * context, whose lead decimation and residual products stay FP64); 0 stops.
+ * negf_gemm_timing returns the launch count, summed kernel milliseconds and
+ * summed algorithmic flops (8 n^3 per point per launch) since enabling.
+ * Synchronises `stream`.  Errors: NEGF_EINVAL (NULL, enable outside 0..3). */
 int negf_gemm_timing_enable(negf_ctx* ctx, int enable);
 int negf_gemm_timing(negf_ctx* ctx, void* stream, long long* launches, double* ms, double* flops);
 

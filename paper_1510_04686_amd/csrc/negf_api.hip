@@ -93,6 +93,7 @@ struct negf_ctx {
 
     // timing of the GEMM family
     bool timing = false;
+    int timing_acc = -1;          // accumulation type to time (DT_C128 / DT_C64), -1 = every launch
     std::vector<TimedLaunch> pending;
     std::vector<hipEvent_t> ev_free;
     long long t_launches = 0;
@@ -153,7 +154,7 @@ hipError_t run_gemm(negf_ctx* c, hipStream_t s, GemmTypes ty, int opa, int opb, 
     if (g.np <= 0 || active <= 0) return hipSuccess;
     GemmArgs gt = g;
     gt.pf = c->tune.gemm_prefetch;
-    if (!c->timing) return gemm_launch(s, ty, opa, opb, epi, gt);
+    if (!c->timing || (c->timing_acc >= 0 && ty.acc != c->timing_acc)) return gemm_launch(s, ty, opa, opb, epi, gt);
     if ((int)c->pending.size() >= EV_POOL) {
         hipError_t e = drain_timing(c);
         if (e != hipSuccess) return e;
@@ -1047,8 +1048,9 @@ int negf_set_mixed_threshold(negf_ctx* c, double thr) {
 }
 
 int negf_gemm_timing_enable(negf_ctx* c, int enable) {
-    if (!c) return NEGF_EINVAL;
+    if (!c || enable < 0 || enable > 3) return NEGF_EINVAL;
     c->timing = enable != 0;
+    c->timing_acc = enable == 2 ? DT_C128 : (enable == 3 ? DT_C64 : -1);
     if (c->timing) { c->t_launches = 0; c->t_ms = 0; c->t_flops = 0; }
     return NEGF_OK;
 }

@@ -295,8 +295,12 @@ def negf_mixed_point_residuals(ctx, out, n=None, stream=None):
            lib().negf_mixed_point_residuals(ctx.handle, _stream(stream), n, _ptr(out, torch.float64, "out")))
 
 
+GEMM_TIMING = {False: 0, True: 1, "all": 1, "fp64": 2, "fp32": 3}
+
+
 def negf_gemm_timing_enable(ctx, enable=True):
-    _check("negf_gemm_timing_enable", lib().negf_gemm_timing_enable(ctx.handle, int(bool(enable))))
+    """enable: False/True, or "all", "fp64", "fp32" (only launches on matrix cores of that precision)."""
+    _check("negf_gemm_timing_enable", lib().negf_gemm_timing_enable(ctx.handle, GEMM_TIMING[enable]))
 
 
 def negf_gemm_timing(ctx, stream=None):

@@ -236,3 +236,25 @@ def test_zgemm_persistent_walks_many_tiles(n, batch):
         ref = _op(a, opa) @ _op(b, opb)
         assert np.max(np.abs(out[3][idx] - ref)) / np.max(np.abs(ref)) < 1e-13 * np.sqrt(n)
     del c
+
+
+def test_gemm_timing_filters_by_matrix_core_precision(ctx):
+    """Timing mode "fp64" records only FP64 products and "fp32" only FP32 ones,
+    each with the algorithmic 8 n^3 flops per point; mode 1 records both."""
+    from paper_1510_04686_amd import negf
+    _say("gemm timing filter")
+    n, batch = 100, 3
+    rng = np.random.default_rng(11)
+    A64 = torch.from_numpy(_rand(rng, (batch, n, n))).cuda()
+    A32 = A64.to(torch.complex64)
+    C64, C32 = torch.empty_like(A64), torch.empty_like(A32)
+    for mode, want in (("fp64", (1, 0)), ("fp32", (0, 1)), ("all", (1, 1))):
+        negf.negf_gemm_timing_enable(ctx, mode)
+        negf.negf_zgemm_batched(ctx, A64, A64, C64, 0, 0)
+        negf.negf_zgemm_batched(ctx, A32, A32, C32, 0, 0)
+        launches, ms, flops = negf.negf_gemm_timing(ctx)
+        assert launches == sum(want), (mode, launches)
+        assert flops == pytest.approx(8.0 * n ** 3 * batch * sum(want)), mode
+        assert ms > 0
+    negf.negf_gemm_timing_enable(ctx, False)
+    assert negf.lib().negf_gemm_timing_enable(ctx.handle, 4) == -1   # NEGF_EINVAL
