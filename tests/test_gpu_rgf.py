@@ -336,3 +336,40 @@ def test_three_level_inverse_in_the_full_solve():
     ref, tols = _ref_and_tol(wl, pts, transmission=True)
     for p, r in enumerate(ref):
         _check_point(out, p, r, wl.total_slabs, T=True, tol=tols[p])
+
+
+def test_abi_rejects_empty_and_out_of_range_point_ranges():
+    """Empty point sets, ranges past the bound points or the capacity, and calls
+    out of order are refused on the host before anything is launched; the
+    context then still solves correctly."""
+    from paper_1510_04686_amd import negf as N
+    _say("ABI: empty / out-of-range point ranges, call order")
+    wl = random_tiny(4, 3, n_e=3, seed=11, eta=1e-3)
+    s = _solver(wl, capacity=2)
+    s.lead_selfenergies()
+    c = s.ctx
+    with pytest.raises(N.NegfError) as e:
+        N.negf_rgf_forward(c, 0, 0, s.sigma_L, s.sigma_R)
+    assert e.value.code == -1                       # NEGF_EINVAL: empty range
+    with pytest.raises(N.NegfError) as e:
+        N.negf_rgf_forward(c, s.n_points - 1, 2, s.sigma_L, s.sigma_R)
+    assert e.value.code == -1                       # past the bound points
+    with pytest.raises(N.NegfError) as e:
+        N.negf_rgf_forward(c, 0, 3, s.sigma_L, s.sigma_R)
+    assert e.value.code == -2                       # NEGF_ESHAPE: above the capacity
+    GR = torch.zeros((2, s.slab_stride, wl.nb), dtype=torch.complex128, device="cuda")
+    N.negf_rgf_forward(c, 0, 2, s.sigma_L, s.sigma_R)
+    with pytest.raises(N.NegfError) as e:
+        N.negf_rgf_backward(c, 1, 2, GR=GR, slab_stride=s.slab_stride)
+    assert e.value.code == -5                       # NEGF_ESTATE: not the forward's range
+    with pytest.raises(N.NegfError) as e:
+        N.negf_bind(c, wl.nb, wl.slab_offset, wl.n_k, wl.n_e, s.h_diag, s.h_up, 0, wl.up_block, s.v, s.energy,
+                    wl.eta, wl.mu_L, wl.mu_R, wl.kT, 0, np.zeros((0, 3), dtype=np.int32))
+    assert e.value.code == -1                       # no points to bind
+    s._bind()                                       # restore the solver's binding
+    out = s.solve()
+    torch.cuda.synchronize()
+    assert s.status() == 0
+    ref, tols = _ref_and_tol(wl, [tuple(p) for p in s.points])
+    for p, r in enumerate(ref):
+        _check_point(out, p, r, 3, tol=tols[p])
