@@ -411,6 +411,14 @@ __global__ __launch_bounds__(256) void gj_update(UpdArgs a) {
             const int row = rowbase + mi * 16 + out_row<R>(lane, r);
             rsr[mi][r] = (row < n) ? rs[row] : 0;
         }
+    // output columns (the final column permutation on the last update), read
+    // here so that the epilogue's stores do not wait for them
+    int ocols[2];
+#pragma unroll
+    for (int nj = 0; nj < 2; ++nj) {
+        const int col = colbase + nj * 16 + (lane & 15);
+        ocols[nj] = (a.last && col < cend) ? a.coldst[(long long)q * n + col] : col;
+    }
 
     typename MF<R>::V cr[2][2], ci[2][2], cs[2][2];
 #pragma unroll
@@ -424,16 +432,13 @@ __global__ __launch_bounds__(256) void gj_update(UpdArgs a) {
     // tile: k rows, cols n0.. (pattern Y).
     const int eo = tid >> 2, ek = (tid & 3) * 4, erow = m0 + eo;
     C re[4], rp[4];
+    // The E reads use indices clamped into the block and are masked (and the
+    // -delta applied) only when stored to LDS, after the slice's products: a
+    // select on a loaded value would make each read wait before the next.
+    const long long erow_off = (long long)min(erow, n - 1) * a.ldE;
     auto load = [&](int s) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int kk = s * BK + ek + j;
-            re[j].x = 0; re[j].y = 0;
-            if (erow < n && kk < nbk) {
-                re[j] = E[(long long)erow * a.ldE + kk];
-                if (erow == k0 + kk) re[j].x -= (R)1;
-            }
-        }
+        for (int j = 0; j < 4; ++j) re[j] = E[erow_off + min(s * BK + ek + j, nbk - 1)];
         const int kk = s * BK + pk;
         const C* prow = nullptr;
         const int src = src_next;
@@ -446,12 +451,15 @@ __global__ __launch_bounds__(256) void gj_update(UpdArgs a) {
             if (prow && col < cend) rp[j] = prow[col];
         }
     };
-    auto store = [&](int b) {
+    auto store = [&](int b, int s) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int pc = poc + 16 * j;
-            Es[b][0][ek + j][swz(ek + j, eo)] = re[j].x;
-            Es[b][1][ek + j][swz(ek + j, eo)] = re[j].y;
+            const int kk = s * BK + ek + j;
+            const bool ok = erow < n && kk < nbk;
+            const R ex = ok ? re[j].x - (erow == k0 + kk ? (R)1 : (R)0) : (R)0;
+            Es[b][0][ek + j][swz(ek + j, eo)] = ex;
+            Es[b][1][ek + j][swz(ek + j, eo)] = ok ? re[j].y : (R)0;
             Ps[b][0][pk][swz(pk, pc)] = rp[j].x;
             Ps[b][1][pk][swz(pk, pc)] = rp[j].y;
         }
@@ -467,13 +475,13 @@ __global__ __launch_bounds__(256) void gj_update(UpdArgs a) {
     const bool copy_only = n0 >= k0 && min(n0 + BM, cend) <= k0 + nbk;
     if (!copy_only) {
         load(0);
-        store(0);
+        store(0, 0);
         __syncthreads();
         for (int s = 0; s + 1 < nsl; ++s) {
             const int b = s & 1;
             load(s + 1);
             mma(b);
-            store(b ^ 1);
+            store(b ^ 1, s + 1);
             __syncthreads();
         }
         mma((nsl - 1) & 1);
@@ -481,9 +489,10 @@ __global__ __launch_bounds__(256) void gj_update(UpdArgs a) {
     }
 
     // Epilogue, one 16-row block at a time: gather the old rows (or the transform
-    // columns inside the K range) and write the new tile.
+    // columns inside the K range) and write the new tile.  The gather selects
+    // addresses, not loaded values (a lane outside the tile reads element 0 and
+    // discards it), so the reads of a block are in flight together.
     C* Y = reinterpret_cast<C*>(a.Y) + q * a.sY;
-    const int* cd = a.coldst + (long long)q * n;
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi) {
         if (mi >= nmi) break;
@@ -495,11 +504,10 @@ __global__ __launch_bounds__(256) void gj_update(UpdArgs a) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = rowbase + mi * 16 + out_row<R>(lane, r);
-                xo[nj][r].x = 0; xo[nj][r].y = 0;
-                if (nj < nnj && row < n && col < cend) {
-                    if (inK) xo[nj][r] = E[(long long)row * a.ldE + (col - k0)];
-                    else xo[nj][r] = X[(long long)rsr[mi][r] * ldX + (col - xc)];
-                }
+                const bool v = nj < nnj && row < n && col < cend;
+                const C* src = !v ? X : (inK ? E + ((long long)row * a.ldE + (col - k0))
+                                             : X + ((long long)rsr[mi][r] * ldX + (col - xc)));
+                xo[nj][r] = *src;
             }
         }
 #pragma unroll
@@ -507,7 +515,7 @@ __global__ __launch_bounds__(256) void gj_update(UpdArgs a) {
             if (nj >= nnj) break;
             const int col = colbase + nj * 16 + (lane & 15);
             const bool inK = col >= k0 && col < k0 + nbk;
-            const int ocol = (a.last && col < cend) ? cd[col] : col;
+            const int ocol = ocols[nj];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = rowbase + mi * 16 + out_row<R>(lane, r);

@@ -21,12 +21,13 @@ __device__ inline double fermi_d(double E, double mu, double kT) {
 //                           - f_L (Sigma_L - Sigma_L^dagger)(i=0) - f_R (Sigma_R - Sigma_R^dagger)(i=N-1)
 // ---------------------------------------------------------------------------
 // Adds the mode's base term to element (gr, gc) of the assembled block.
+// With `hpre`, element (gr, gc) of H_ii has already been read into *hpre.
 __device__ inline void sandwich_base(const SandArgs& a, double2& z, int gr, int gc, int ik, int ie, int ns,
-                                     long long gslab, double E) {
+                                     long long gslab, double E, const double2* hpre = nullptr) {
     const int n = a.n;
     if (a.mode == 1) {
         const double2* H = a.hdiag + ik * a.hdiag_k + gslab * (long long)n * n;
-        double2 h = H[(long long)gr * n + gc];
+        double2 h = hpre ? *hpre : H[(long long)gr * n + gc];
         z.x -= h.x; z.y -= h.y;
         if (gr == gc) {
             z.x += E; z.y += a.eta;
@@ -217,11 +218,21 @@ __global__ __launch_bounds__(256) void sandwich_cols_kernel(SandArgs a) {
     TO* O = reinterpret_cast<TO*>(a.O) + q * a.sO;
     const long long gslab = sfirst + a.slab;
     const double E = a.energy ? a.energy[ie] : 0.0;
+    // the assembly's H_ii entries of all UB rows are read at once (the stores
+    // of the row loop would otherwise keep each read behind the previous row);
+    // the assembly is the U^dagger X U form, the only one whose registers it costs
+    constexpr bool PRE = (OPL == 2 && OPR == 1);
+    double2 hv[PRE ? UB : 1];
+    if (PRE && a.mode == 1) {
+        const double2* H = a.hdiag + ik * a.hdiag_k + gslab * (long long)n * n;
+#pragma unroll
+        for (int i = 0; i < UB; ++i) hv[i] = H[(long long)(rb + i) * n + c];
+    }
 #pragma unroll
     for (int i = 0; i < UB; ++i) {
         double2 z = y[i];
         z.x *= a.sign; z.y *= a.sign;
-        sandwich_base(a, z, rb + i, c, ik, ie, ns, gslab, E);
+        sandwich_base(a, z, rb + i, c, ik, ie, ns, gslab, E, (PRE && a.mode == 1) ? &hv[PRE ? i : 0] : nullptr);
         O[(long long)(rb + i) * n + c] = cconv<TO>(z);
     }
 }
