@@ -427,14 +427,24 @@ __global__ __launch_bounds__(256) void bond_rows_kernel(BondArgs a) {
             const bool on = tid < CW && b < n;
             double2 gc[UB], glc[UB], uc[UB];
             const int bb = on ? (b / UB) * UB : 0;
+            if (on) {
+                // the g^< rows first, all in flight at once, then their LDS
+                // stores; then the G, G^< and U rows, all in flight at once
+                // (two memory round trips instead of one per row, in the same
+                // registers)
+                {
+                    double2 gs[UB];
 #pragma unroll
-            for (int j = 0; j < UB; ++j) {
-                const long long o = (long long)(r0 + j) * n + b;
-                if (on) {
+                    for (int j = 0; j < UB; ++j) gs[j] = cconv<double2>(GS[(long long)(r0 + j) * n + b]);
+#pragma unroll
+                    for (int j = 0; j < UB; ++j) gsl[j][tid] = gs[j];
+                }
+#pragma unroll
+                for (int j = 0; j < UB; ++j) {
+                    const long long o = (long long)(r0 + j) * n + b;
                     gc[j] = cconv<double2>(G[o]);
                     glc[j] = cconv<double2>(GL[o]);
                     uc[j] = U[(long long)(bb + j) * n + b];
-                    gsl[j][tid] = cconv<double2>(GS[o]);
                 }
             }
             __syncthreads();
