@@ -153,9 +153,13 @@ __global__ __launch_bounds__(256) void sandwich_kernel(SandArgs a) {
 // columns of its block; U^dagger Y mixes the thread's own rows in registers
 // with the diagonal block of U from LDS.  UB and the operand forms are
 // compile-time, so the loops carry no guards.
+// Threads per workgroup of the column-chunk form: 128 keeps the X U chunk in
+// LDS at about 20 KB, so twice as many workgroups (and their reads) fit on a CU.
+constexpr int SAND_NT = 128;
+
 template <typename TX, typename TO, int UB, int OPL, int OPR>
-__global__ __launch_bounds__(256) void sandwich_cols_kernel(SandArgs a) {
-    constexpr int CW = (256 / UB) * UB;   // columns per chunk
+__global__ __launch_bounds__(SAND_NT) void sandwich_cols_kernel(SandArgs a) {
+    constexpr int CW = (SAND_NT / UB) * UB;   // columns per chunk
     __shared__ double2 xs[OPR == 1 ? UB : 1][OPR == 1 ? CW : 1];
     __shared__ double2 ul[OPL == 2 ? UB : 1][OPL == 2 ? UB : 1];
     const int n = a.n;
@@ -179,7 +183,7 @@ __global__ __launch_bounds__(256) void sandwich_cols_kernel(SandArgs a) {
         const TX* X = reinterpret_cast<const TX*>(a.X) + q * a.sX;
         const double2* U = a.hup + ik * a.hup_k + (sfirst + a.uslab) * (long long)n * n;
         if constexpr (OPL == 2) {
-            if (tid < UB * UB) ul[tid / UB][tid % UB] = U[(long long)(rb + tid / UB) * n + rb + tid % UB];
+            for (int e = tid; e < UB * UB; e += SAND_NT) ul[e / UB][e % UB] = U[(long long)(rb + e / UB) * n + rb + e % UB];
         }
         if (on) {
 #pragma unroll
@@ -255,17 +259,17 @@ hipError_t sandwich_init() {
 
 template <typename TX, typename TO, int UB>
 static bool sandwich_cols_ops(hipStream_t s, const SandArgs& a, dim3 grid) {
-    if (a.opL == 0 && a.opR == 1) hipLaunchKernelGGL((sandwich_cols_kernel<TX, TO, UB, 0, 1>), grid, dim3(256), 0, s, a);
-    else if (a.opL == 2 && a.opR == 0) hipLaunchKernelGGL((sandwich_cols_kernel<TX, TO, UB, 2, 0>), grid, dim3(256), 0, s, a);
-    else if (a.opL == 2 && a.opR == 1) hipLaunchKernelGGL((sandwich_cols_kernel<TX, TO, UB, 2, 1>), grid, dim3(256), 0, s, a);
-    else if (a.opL == 0 && a.opR == 0) hipLaunchKernelGGL((sandwich_cols_kernel<TX, TO, UB, 0, 0>), grid, dim3(256), 0, s, a);
+    if (a.opL == 0 && a.opR == 1) hipLaunchKernelGGL((sandwich_cols_kernel<TX, TO, UB, 0, 1>), grid, dim3(SAND_NT), 0, s, a);
+    else if (a.opL == 2 && a.opR == 0) hipLaunchKernelGGL((sandwich_cols_kernel<TX, TO, UB, 2, 0>), grid, dim3(SAND_NT), 0, s, a);
+    else if (a.opL == 2 && a.opR == 1) hipLaunchKernelGGL((sandwich_cols_kernel<TX, TO, UB, 2, 1>), grid, dim3(SAND_NT), 0, s, a);
+    else if (a.opL == 0 && a.opR == 0) hipLaunchKernelGGL((sandwich_cols_kernel<TX, TO, UB, 0, 0>), grid, dim3(SAND_NT), 0, s, a);
     else return false;
     return true;
 }
 
 template <typename TX, typename TO>
 static bool sandwich_cols_launch(hipStream_t s, const SandArgs& a) {
-    const int cw = (256 / a.ub) * a.ub;
+    const int cw = (SAND_NT / a.ub) * a.ub;
     const long long per = (long long)(a.n / a.ub) * ((a.n + cw - 1) / cw);
     dim3 grid((unsigned)((long long)a.np * per));
     switch (a.ub) {
