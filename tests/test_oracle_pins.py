@@ -377,3 +377,126 @@ def test_sancho_rubio_alternate_association_closed_form(E):
     assert conv
     ref = _chain_sigma(z - eps, t)
     assert abs(sig[0, 0] - ref) < 1e-10 * max(1, abs(ref))
+
+
+# --------------------------------------------------------------------------
+# Lead-coupling orientation with non-symmetric couplings (Eq. 3, Sigma_lead)
+# --------------------------------------------------------------------------
+
+def _bands(h00, h01, n_kx=8001):
+    """Bulk bands E_n(kx) of an ordered lead, H(kx) = h00 + h01 e^{ikx} + h01^dagger e^{-ikx},
+    on a closed kx grid over one period, each row sorted."""
+    ks = np.linspace(0.0, 2 * np.pi, n_kx)
+    return np.array([np.linalg.eigvalsh(h00 + h01 * np.exp(1j * k) + h01.conj().T * np.exp(-1j * k)) for k in ks])
+
+
+def _open_channels(bands, E):
+    """Number of right-moving Bloch states at E: upward crossings of E by the
+    bands over one period (brute force on the kx grid)."""
+    d = bands - E
+    return int(np.sum((d[:-1] < 0) & (d[1:] >= 0)))
+
+
+def _band_edges(bands):
+    """Every extremum of every band (where the channel count changes)."""
+    out = []
+    for n in range(bands.shape[1]):
+        b = bands[:, n]
+        turn = np.where(np.diff(np.sign(np.diff(b))) != 0)[0] + 1
+        out.extend(list(b[turn]) + [b.min(), b.max()])
+    return np.array(out)
+
+
+@pytest.mark.parametrize("ik", [0, 1])
+def test_ordered_cross_section_integer_transmission_nonsymmetric_couplings(ik):
+    """An ordered pure-Si cross-section (the device continues its leads) is a
+    perfect conductor: T(E) equals the number of open bulk channels, counted
+    here by brute force from the bulk bands.  The atom couplings are not
+    symmetric (h01 != h01^T) and h00 is complex at k != 0, so this pins the
+    orientation of Sigma = tau g_s tau^dagger, which lead layer h01 points to,
+    and the left lead's h01 direction: a transposed or swapped coupling gives
+    non-integer T (checked below by planting that mistake)."""
+    from synth.workloads import cross_section_workload
+    wl = cross_section_workload("ordered", 2, 1, [3], 4, np.zeros(1), 1510046862, ge_fraction=0.0, eta=1e-9)
+    assert np.abs(wl.lead_h01_R - wl.lead_h01_R.T).max() > 0.1   # genuinely non-symmetric
+    h00 = wl.lead_h00[ik]
+    bands = _bands(h00, wl.lead_h01_R)
+    edges = _band_edges(bands)
+    grid = np.arange(-2.0, 2.0, 0.01)
+    pick = [E for E in grid if _open_channels(bands, E) >= 1 and np.min(np.abs(edges - E)) >= 0.03]
+    assert len(pick) >= 2
+    pick = pick[:: max(1, len(pick) // 6)]
+    hd, hu, _ = wl.sample_blocks(0, ik)
+    swapped_misses = 0
+    for E in pick:
+        z = E + 1j * wl.eta
+        sL, _, cL = O.lead_selfenergy(h00, wl.lead_h01_L, wl.lead_tau_L, z)
+        sR, _, cR = O.lead_selfenergy(h00, wl.lead_h01_R, wl.lead_tau_R, z)
+        assert cL and cR
+        r = O.rgf(hd, hu, E, wl.eta, sL, sR, 1.0, 0.0, transmission=True)
+        n_open = _open_channels(bands, E)
+        assert abs(r["T"] - n_open) < 1e-5, (E, r["T"], n_open)
+        # planted mistake: tau^dagger g_s tau instead of tau g_s tau^dagger
+        gL, _, _ = O.sancho_rubio(h00, wl.lead_h01_L, z)
+        gR, _, _ = O.sancho_rubio(h00, wl.lead_h01_R, z)
+        tL, tR = wl.lead_tau_L, wl.lead_tau_R
+        w = O.rgf(hd, hu, E, wl.eta, tL.conj().T @ gL @ tL, tR.conj().T @ gR @ tR, 1.0, 0.0, transmission=True)
+        swapped_misses += abs(w["T"] - n_open) > 1e-2
+    assert swapped_misses >= 1
+
+
+# --------------------------------------------------------------------------
+# SCBA closed forms (Eqs. 4 and 6): the Hermitian part of Sigma^R (full complex G^R)
+# --------------------------------------------------------------------------
+
+def _single_level(eps, energy, eta, D=0.0, M=0.0, shift=0, n0=0.0, mu=-50.0):
+    """One orbital, one slab, leads decoupled (tau = 0): only the device eta
+    and the scattering self-energies broaden the level.  mu far below the level
+    leaves it empty (G^< = 0)."""
+    from synth.workloads import Workload
+    c = lambda x: np.array([[x]], dtype=np.complex128)
+    n_e = len(energy)
+    return Workload(name="level", seed=0, nb=1, orbs_per_atom=1, slab_offset=np.array([0, 1]),
+                    kpts=np.zeros(1), w_k=np.ones(1), energy=np.asarray(energy, dtype=np.float64),
+                    w_e=np.full(n_e, 0.01), h_diag=c(eps)[None, None], h_up=np.zeros((1, 1, 1), np.complex128),
+                    up_block=1, lead_h00=c(0.0)[None], lead_h01_L=c(1.0), lead_tau_L=c(0.0), lead_h01_R=c(1.0),
+                    lead_tau_R=c(0.0), lead_block=1, v_onsite=None, species=None, eta=eta, mu_L=mu, mu_R=mu,
+                    D_ac=D, M_op=M, shift=shift, n_bose=n0)
+
+
+def test_scba_acoustic_single_level_closed_form():
+    """Sigma^R = D G^R on one level: the SCBA fixed point solves D G^2 - (z - eps) G + 1 = 0,
+    G = (z - eps - sqrt((z - eps)^2 - 4 D)) / 2D on the branch with Im G < 0
+    (a semicircle broadened by eta).  Pins reading Q8 (the full complex G^R,
+    not i Im G^R): both the real and the imaginary part of G are compared."""
+    E = np.linspace(-1.0, 1.0, 41)
+    D, eps, eta = 0.04, 0.1, 0.05
+    r = O.scba(_single_level(eps, E, eta, D=D), 400, tol=1e-15)
+    assert r["hist"][-1] < 1e-14
+    G = r["GRd"][0, :, 0, 0]
+    z = E + 1j * eta - eps
+    sq = np.sqrt(z * z - 4 * D)
+    roots = np.stack([(z - sq) / (2 * D), (z + sq) / (2 * D)])
+    assert np.all((roots.imag < 0).sum(axis=0) == 1)      # exactly one retarded root
+    Gc = np.where(roots[0].imag < 0, roots[0], roots[1])
+    assert np.max(np.abs(G.real - Gc.real)) < 1e-12 * np.max(np.abs(Gc))
+    assert np.max(np.abs(G.imag - Gc.imag)) < 1e-12 * np.max(np.abs(Gc))
+    assert np.max(np.abs(Gc.real)) > 0.5 * np.max(np.abs(Gc))   # the real part matters
+
+
+def test_scba_optical_empty_level_continued_fraction():
+    """Optical phonons on an empty level (G^< = 0) with n0 = 0: Eq. (6) leaves
+    Sigma^R(E) = M G^R(E - hw), so the SCBA fixed point is the continued
+    fraction G(E_j) = 1 / (z_j - eps - M G(E_{j-s})) built up from the bottom
+    of the grid, with G(E_j) = 1 / (z_j - eps) for j < s (the off-grid group
+    dropped, reading Q6).  Pins the direction of the emission shift and the
+    (1 + n0) weight in Sigma^R, and the full complex G^R."""
+    E = np.linspace(-1.0, 1.0, 41)
+    eps, eta, M, s = 0.1, 0.05, 0.02, 3
+    r = O.scba(_single_level(eps, E, eta, M=M, shift=s), 60, tol=1e-15)
+    assert np.max(np.abs(r["GLd"])) == 0.0
+    G = r["GRd"][0, :, 0, 0]
+    Gc = np.zeros(len(E), dtype=np.complex128)
+    for j in range(len(E)):
+        Gc[j] = 1.0 / (E[j] + 1j * eta - eps - (M * Gc[j - s] if j >= s else 0.0))
+    assert np.max(np.abs(G - Gc)) < 1e-13 * np.max(np.abs(Gc))
