@@ -1,17 +1,21 @@
 """Benchmark of the batched RGF hot path on one MI355X.
 
-One step = the whole path over the workload with inputs resident in HBM:
-lead self-energies (Sancho-Rubio, FP64) for every (k, E), forward + backward
-RGF sweeps for every (sample, k, E) point in batches, and the density /
-current reductions.  Prints ONE JSON line.
+Prints ONE JSON line.
 
     python bench.py [--steps K] [--warmup W] [--workload C2] [--precision fp64|mixed]
 
 Workloads (default C2, the block-400 headline):
-  C2/C1/C4  one step as above
-  C3        one step = leads + the SCBA loop (iteration replayed from a HIP graph)
-  C5        one step = leads + forward density; the adjoint dn/dV (VJP) is timed
-            after the steps and reported as a cost ratio
+  C2  one step = one batch of bound points (512 points: the 512 energies of one
+      k-point): that batch's lead self-energies (Sancho-Rubio, FP64), its
+      forward + backward RGF sweeps, and the density / current reductions over
+      the point set.  Steps cycle through the 8 batches (k-points) of the
+      4096-point workload, so 8 steps make one full pass.
+  C1  one step = the whole 256-point workload (one batch)
+  C4  one step = leads + every batch of the alloy ensemble + reductions
+  C3  one step = leads + the SCBA loop (iteration replayed from a HIP graph)
+  C5  one step = leads + forward density; the adjoint dn/dV (VJP) is timed
+      after the steps and reported as a cost ratio
+Inputs are resident in HBM before the timed region starts.
 """
 from __future__ import annotations
 
@@ -36,26 +40,6 @@ WORKLOAD_DESC = {
 }
 
 
-def model_flops(wl, iters_L, iters_R, n_solves=1, shared=False):
-    """Algorithmic flops of one step.  U = 8 b^3 (one complex b x b x b product
-    or one complex inverse).  RGF for G^R + G^<: 7 U per slab per point (forward:
-    inverse, g X, then (g X) g^dagger of which only the anti-Hermitian half is
-    formed; backward: P = L G, G = g + P R, T = P Q, W = L G^<, and the
-    anti-Hermitian half of W L^dagger).
-    Sancho-Rubio: 7 U per decimation step per lead (1 inverse + 6 products)
-    plus 3 U per lead for the final surface inverse and tau g tau^dagger; with
-    the shared decimation (h01_L = h01_R^dagger) one run of max(iters) steps
-    serves both leads."""
-    import numpy as np
-    b = wl.nb
-    U = 8.0 * b ** 3
-    counts = np.diff(wl.slab_offset)
-    rgf = 7.0 * U * float(np.sum(counts)) * wl.n_k * wl.n_e * n_solves
-    steps = float(np.sum(np.maximum(iters_L, iters_R))) if shared else float(np.sum(iters_L)) + float(np.sum(iters_R))
-    lead = U * (7.0 * steps + 3.0 * 2 * wl.n_k * wl.n_e)
-    return rgf, lead
-
-
 GEMM_SOURCES = ["negf_gemm.hip", "negf_mfma.hpp", "negf_common.hpp", "negf_internal.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_traffic_C2.json")
 
@@ -78,8 +62,10 @@ def gemm_traffic_per_point_launch(precision):
     return float(t["hbm_bytes_per_point_launch"])
 
 
-def cpu_baseline(wl, n_points, seed=0):
-    """Time the oracle (as it stands) on a bounded sample of the same workload."""
+def cpu_baseline(wl, max_points=16, budget_s=15.0, seed=0):
+    """Time the oracle (as it stands) on a bounded sample of the same workload:
+    random points, each with its own lead decimations, until `budget_s` of host
+    time or `max_points` points (at least two)."""
     import numpy as np
     import oracle as O
     try:
@@ -89,13 +75,18 @@ def cpu_baseline(wl, n_points, seed=0):
         threads = 1
     rng = np.random.default_rng(seed)
     pts = wl.points()
-    sel = pts[rng.choice(len(pts), size=min(n_points, len(pts)), replace=False)]
+    sel = pts[rng.choice(len(pts), size=min(max_points, len(pts)), replace=False)]
     t0 = time.perf_counter()
-    O.solve_points(wl, [tuple(p) for p in sel])
+    done = 0
+    for p in sel:
+        O.solve_points(wl, [tuple(p)])
+        done += 1
+        if done >= 2 and time.perf_counter() - t0 >= budget_s:
+            break
     dt = time.perf_counter() - t0
-    return {"value": len(sel) / dt, "unit": "(E,k) points/s", "cores": threads, "kind": "oracle",
-            "sample": f"{len(sel)} random (sample,k,E) points of the same workload, leads included, "
-                      f"{dt:.1f} s on the host"}
+    return {"value": done / dt, "unit": "(E,k) points/s", "cores": threads, "kind": "oracle",
+            "sample": f"{done} random (sample,k,E) points of the same workload, each with its own two lead "
+                      f"decimations, {dt:.1f} s on the host"}
 
 
 def main():
@@ -116,7 +107,7 @@ def main():
                     help="batches in flight at once, each on its own context and stream")
     ap.add_argument("--tune", default="auto", choices=["auto", "default"],
                     help="kernel shapes: measured on this GPU before timing (auto) or the library defaults")
-    ap.add_argument("--cpu-points", type=int, default=4)
+    ap.add_argument("--cpu-points", type=int, default=16, help="oracle points at most (about 15 s of host time)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -155,19 +146,31 @@ def main():
           f"{sum(N.negf_workspace_bytes(c) for c in solver.ctxs) / 2**30:.1f} GiB", file=sys.stderr, flush=True)
     n_iter = (args.scba_iters or wl.n_scba) if args.workload == "C3" else 1
     out = solver.alloc_outputs(want=("GR", "GL", "GG", "bond"))
+    batches = solver.batches()
+    # C2: one step is one batch (the 512 energies of one k-point); the others run
+    # the whole workload per step
+    per_batch = args.workload == "C2" and args.precision == "fp64" and args.lanes == 1
+    lead_steps = []        # (ik, e0, e1) lead ranges computed in each timed step
 
-    def step():
+    def step(j):
+        if per_batch:
+            p0, np_ = batches[j % len(batches)]
+            ranges = solver.lead_selfenergies_for(p0, np_)
+            solver.run_batch(out, p0, np_)
+            n, J, jE = solver.observables(out["GL"], out["bond"])
+            return n, J, jE, np_, ranges
         solver.lead_selfenergies()
+        ranges = [(ik, 0, wl.n_e) for ik in range(wl.n_k)]
         if args.workload == "C3":
             o, hist = solver.scba(n_iter=n_iter, graph=True)
-            return solver.observables(o["GL"], o["bond"])
+            return (*solver.observables(o["GL"], o["bond"]), solver.n_points, ranges)
         if args.workload == "C5":
-            return solver.density(), None, None
+            return solver.density(), None, None, solver.n_points, ranges
         solver.run_batches(out)
-        return solver.observables(out["GL"], out["bond"])
+        return (*solver.observables(out["GL"], out["bond"]), solver.n_points, ranges)
 
     for w in range(args.warmup):
-        step()
+        step(w)
         torch.cuda.synchronize()
         print(f"[bench] warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
 
@@ -178,13 +181,21 @@ def main():
     for c in solver.ctxs:
         N.negf_gemm_timing_enable(c, ("fp64" if args.precision == "fp64" else "fp32") if timed_gemm else False)
     torch.cuda.synchronize()
+    points = 0
+    rgf_f = lead_f = 0.0
+    lead_iters = []
+    counts = np.diff(wl.slab_offset)
+    U = 8.0 * wl.nb ** 3
     t0 = time.perf_counter()
     for k in range(args.steps):
-        n, J, jE = step()
+        n, J, jE, npts, ranges = step(args.warmup + k)
         torch.cuda.synchronize()
+        points += npts
+        lead_steps.append(ranges)
         print(f"[bench] step {k + 1}/{args.steps} done at {time.perf_counter() - t0:.1f} s", file=sys.stderr,
               flush=True)
     dt = time.perf_counter() - t0
+    points *= n_iter
     launches, gemm_ms, gemm_flops = 0, 0.0, 0.0
     for c in solver.ctxs:
         l_, m_, f_ = N.negf_gemm_timing(c)
@@ -193,8 +204,22 @@ def main():
     st = solver.status()
     iters_L = solver.iters_L.cpu().numpy()
     iters_R = solver.iters_R.cpu().numpy()
-    rgf_f, lead_f = model_flops(wl, iters_L, iters_R, n_solves=n_iter, shared=bool(solver.lead_dual))
-    points = solver.n_points * n_iter * args.steps
+    # model flops of the timed steps (U = 8 b^3): 7 U per slab per point solved,
+    # and per lead point 7 U per decimation step (max of the two leads with the
+    # shared decimation) plus 3 U per lead for the surface inverse and tau g tau^dagger
+    for k, ranges in enumerate(lead_steps):
+        if per_batch:
+            p0, np_ = batches[(args.warmup + k) % len(batches)]
+            slabs = float(np.sum(counts[solver.points[p0:p0 + np_, 0]]))
+        else:
+            slabs = float(np.sum(counts)) * wl.n_k * wl.n_e
+        rgf_f += 7.0 * U * slabs * n_iter
+        for ik, e0, e1 in ranges:
+            iL, iR = iters_L[ik, e0:e1], iters_R[ik, e0:e1]
+            steps_ = float(np.sum(np.maximum(iL, iR))) if solver.lead_dual else float(np.sum(iL) + np.sum(iR))
+            lead_f += U * (7.0 * steps_ + 3.0 * 2 * (e1 - e0))
+            lead_iters.append((iL + iR) / 2.0)
+    lead_iters = np.concatenate(lead_iters) if lead_iters else np.zeros(1)
     dtype = "f64" if args.precision == "fp64" else "f32+f64"
     peak = PEAK["f64"] if args.precision == "fp64" else PEAK["f32"]
     achieved = gemm_flops / (gemm_ms * 1e-3) if gemm_ms > 0 else None
@@ -216,13 +241,17 @@ def main():
         "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOAD_DESC[args.workload]}",
-                   "points_per_step": solver.n_points, "block": wl.nb, "slabs": int(wl.total_slabs),
+                   "points_per_step": points // max(args.steps * n_iter, 1),
+                   "step": ("one batch of bound points (one k-point's 512 energies): its leads, forward + "
+                            "backward sweeps, and the reductions over the point set; steps cycle over the "
+                            f"{len(batches)} batches" if per_batch else "the whole workload"),
+                   "points_per_pass": solver.n_points, "block": wl.nb, "slabs": int(wl.total_slabs),
                    "samples": wl.n_samples, "n_e": wl.n_e, "n_k": wl.n_k,
                    "batch_capacity": solver.capacity, "lanes": solver.lanes, "precision": args.precision,
                    "parallelism": "single GPU, batched (sample,k,E) points"},
-        "model_tflops": (rgf_f + lead_f) * args.steps / dt / 1e12,
-        "model_flops_per_step": {"rgf": rgf_f, "leads": lead_f},
-        "lead_iterations_mean": float((iters_L.mean() + iters_R.mean()) / 2),
+        "model_tflops": (rgf_f + lead_f) / dt / 1e12,
+        "model_flops_per_step": {"rgf": rgf_f / args.steps, "leads": lead_f / args.steps},
+        "lead_iterations_mean": float(np.mean(lead_iters)),
         "lead_shared_decimation": bool(solver.lead_dual),
         "kernel_shapes": solver.tuning,
         "roofline": {"bound": "mfma", "kernel": "batched complex GEMM (negf::gemm_kernel)" +
@@ -286,6 +315,7 @@ def main():
                                                      "reference": ref_note}
     if not args.no_cpu_baseline and args.cpu_points > 0:
         res["cpu_baseline"] = cpu_baseline(wl, args.cpu_points)
+        res["gpu_over_cpu"] = res["value"] / res["cpu_baseline"]["value"]
     print(json.dumps(res), flush=True)
 
 

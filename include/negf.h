@@ -75,6 +75,11 @@ typedef struct {
 int negf_create(const negf_config* cfg, negf_ctx** out);
 void negf_destroy(negf_ctx* ctx);
 
+/* SHA-1 of the library's sources (HIP files, headers and this header) it was
+ * built from, as a NUL-terminated hex string owned by the library.  A binding
+ * compares it with the sources at hand and refuses a stale build. */
+const char* negf_build_id(void);
+
 /* Bytes of device workspace the context holds. */
 long long negf_workspace_bytes(const negf_ctx* ctx);
 

@@ -6,6 +6,7 @@ from __future__ import annotations
 
 import concurrent.futures as cf
 import glob
+import hashlib
 import os
 import subprocess
 import sys
@@ -28,9 +29,23 @@ FLAGS = [
 ]
 
 
-def _compile(src: str) -> str:
+def sources_sha1() -> str:
+    """SHA-1 over every HIP source and header of the library and the public
+    header: the build id compiled into the library (negf_build_id), which the
+    binding compares before it uses a built library."""
+    files = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.hpp")) +
+                   [os.path.join(INCLUDE, "negf.h")])
+    h = hashlib.sha1()
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _compile(src: str, build_id: str) -> str:
     obj = os.path.join(BUILD_DIR, os.path.basename(src).replace(".hip", ".o"))
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *FLAGS, f'-DNEGF_BUILD_ID="{build_id}"', "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr[-4000:]}")
@@ -44,8 +59,9 @@ def build(verbose: bool = True) -> str:
     if not sources:
         raise RuntimeError("no HIP sources found")
     jobs = min(len(sources), int(os.environ.get("MAX_JOBS", "8")))
+    build_id = sources_sha1()
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, sources))
+        objs = list(ex.map(lambda src: _compile(src, build_id), sources))
     tmp = LIB_PATH + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)

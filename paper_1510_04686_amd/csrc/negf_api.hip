@@ -381,6 +381,11 @@ int negf_create(const negf_config* cfg, negf_ctx** out) {
 
 void negf_destroy(negf_ctx* c) { delete c; }
 
+#ifndef NEGF_BUILD_ID
+#error "NEGF_BUILD_ID (the SHA-1 of the sources) must be defined by the build"
+#endif
+const char* negf_build_id(void) { return NEGF_BUILD_ID; }
+
 long long negf_workspace_bytes(const negf_ctx* c) { return c ? c->ws_bytes : 0; }
 
 int negf_sync_status(negf_ctx* c, void* stream) {

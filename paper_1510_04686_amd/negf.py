@@ -14,7 +14,7 @@ from ctypes import POINTER, c_double, c_int, c_longlong, c_void_p
 
 import torch
 
-from .build import LIB_PATH
+from .build import LIB_PATH, sources_sha1
 
 _lib = None
 
@@ -58,6 +58,7 @@ EXPORTS = [
     "negf_bind", "negf_lead_selfenergy", "negf_lead_selfenergy_pair", "negf_rgf_forward", "negf_rgf_backward",
     "negf_scba_selfenergy", "negf_observables", "negf_rgf_adjoint", "negf_zgemm_batched", "negf_zinv_batched", "negf_mixed_stats",
     "negf_set_mixed_threshold", "negf_mixed_point_residuals", "negf_gemm_timing_enable", "negf_gemm_timing", "negf_get_tuning", "negf_set_tuning", "negf_autotune",
+    "negf_build_id",
 ]
 
 
@@ -69,6 +70,12 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"HIP library not built: {LIB_PATH} missing (run paper_1510_04686_amd.build)")
     L = ctypes.CDLL(LIB_PATH)
+    L.negf_build_id.restype = ctypes.c_char_p
+    L.negf_build_id.argtypes = []
+    built, now = L.negf_build_id().decode(), sources_sha1()
+    if built != now:
+        raise RuntimeError(f"HIP library {LIB_PATH} is stale: built from sources {built[:12]}, the sources are now "
+                           f"{now[:12]} (run paper_1510_04686_amd.build)")
     vp, i, d, ll = c_void_p, c_int, c_double, c_longlong
     sig = {
         "negf_create": (i, [POINTER(negf_config), POINTER(vp)]),

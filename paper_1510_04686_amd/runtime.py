@@ -145,13 +145,49 @@ class RGFSolver:
         self._bind()
 
     # ------------------------------------------------------------------ leads
-    def lead_selfenergies(self, tol=1e-14, max_iter=100, shared_decimation=True):
+    def _alloc_lead_tables(self):
         wl = self.wl
         shape = (wl.n_k, wl.n_e, wl.nb, wl.nb)
-        self.sigma_L = torch.empty(shape, dtype=torch.complex128, device=self.device)
-        self.sigma_R = torch.empty(shape, dtype=torch.complex128, device=self.device)
-        self.iters_L = torch.empty((wl.n_k, wl.n_e), dtype=torch.int32, device=self.device)
-        self.iters_R = torch.empty((wl.n_k, wl.n_e), dtype=torch.int32, device=self.device)
+        if self.sigma_L is None:
+            self.sigma_L = torch.zeros(shape, dtype=torch.complex128, device=self.device)
+            self.sigma_R = torch.zeros(shape, dtype=torch.complex128, device=self.device)
+            self.iters_L = torch.zeros((wl.n_k, wl.n_e), dtype=torch.int32, device=self.device)
+            self.iters_R = torch.zeros((wl.n_k, wl.n_e), dtype=torch.int32, device=self.device)
+
+    def lead_ranges(self, p0, np_):
+        """(ik, e0, e1) energy ranges of the lead self-energies that bound points
+        [p0, p0 + np_) read: one range per k-point, spanning the batch's energies
+        of that k."""
+        sel = self.points[p0:p0 + np_]
+        out = []
+        for ik in np.unique(sel[:, 1]):
+            es = sel[sel[:, 1] == ik, 2]
+            out.append((int(ik), int(es.min()), int(es.max()) + 1))
+        return out
+
+    def lead_selfenergies_for(self, p0, np_, tol=1e-14, max_iter=100):
+        """Lead self-energies of only the (k, E) points that the batch [p0, p0 + np_)
+        reads, written into their slots of the full tables (one shared
+        decimation call per k-point of the batch).  Returns the (ik, e0, e1)
+        ranges computed."""
+        self._alloc_lead_tables()
+        ranges = self.lead_ranges(p0, np_)
+        status, dual = 0, 1
+        for ik, e0, e1 in ranges:
+            k = slice(ik, ik + 1)
+            st, du = N.negf_lead_selfenergy_pair(
+                self.ctx, self.lead_h00[k], self.lead_h01_L[k], self.lead_tau_L[k], self.lead_h01_R[k],
+                self.lead_tau_R[k], self.energy[e0:e1], self.wl.eta, tol, max_iter,
+                self.sigma_L[ik, e0:e1], self.sigma_R[ik, e0:e1], self.iters_L[ik, e0:e1],
+                self.iters_R[ik, e0:e1])
+            status, dual = max(status, st), min(dual, du)
+        self.lead_status, self.lead_dual = status, dual
+        return ranges
+
+    def lead_selfenergies(self, tol=1e-14, max_iter=100, shared_decimation=True):
+        self.sigma_L = None
+        self._alloc_lead_tables()
+        wl = self.wl
         if shared_decimation:
             self.lead_status, self.lead_dual = N.negf_lead_selfenergy_pair(
                 self.ctx, self.lead_h00, self.lead_h01_L, self.lead_tau_L, self.lead_h01_R, self.lead_tau_R,
@@ -177,6 +213,21 @@ class RGFSolver:
         if want_T:
             out["T"] = torch.zeros(P, dtype=torch.float64, device=self.device)
         return out
+
+    def batches(self):
+        """(p0, np) of each batch of bound points, in order."""
+        return [(p0, min(self.capacity, self.n_points - p0)) for p0 in range(0, self.n_points, self.capacity)]
+
+    def run_batch(self, out, p0, np_, full_blocks=False, want_T=False, scat_R=None, scat_L=None, stream=None):
+        """Forward + backward sweep of one batch of bound points on the first
+        lane's context (the mixed-precision point redo is not applied)."""
+        flags = N.NEGF_WANT_TRANSMISSION if want_T else 0
+        N.negf_rgf_forward(self.ctx, p0, np_, self.sigma_L, self.sigma_R, scat_R, scat_L, flags, stream=stream)
+        self._last_fwd = (p0, np_)
+        if self.resid is not None:
+            N.negf_mixed_point_residuals(self.ctx, self.resid[p0:p0 + np_], stream=stream)
+        N.negf_rgf_backward(self.ctx, p0, np_, out.get("GR"), out.get("GL"), out.get("GG"),
+                            int(full_blocks), self.slab_stride, out.get("bond"), out.get("T"), stream=stream)
 
     def run_batches(self, out, full_blocks=False, want_T=False, scat_R=None, scat_L=None, stream=None):
         flags = N.NEGF_WANT_TRANSMISSION if want_T else 0

@@ -68,3 +68,18 @@ def test_error_strings(lib):
     for code in (0, -1, -2, -3, -4, -5, 1, 2, 3, 4):
         assert lib.negf_error_string(code)
     assert lib.negf_error_string(999) == b"unknown status"
+
+
+def test_library_matches_its_sources(lib):
+    """The loaded library was built from the sources in the tree (a stale build
+    is refused by negf.lib())."""
+    from paper_1510_04686_amd import build
+    assert lib.negf_build_id().decode() == build.sources_sha1()
+
+
+def test_stale_library_is_refused(monkeypatch, lib):
+    from paper_1510_04686_amd import negf
+    monkeypatch.setattr(negf, "sources_sha1", lambda: "0" * 40)
+    monkeypatch.setattr(negf, "_lib", None)
+    with pytest.raises(RuntimeError, match="stale"):
+        negf.lib()
