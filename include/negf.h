@@ -66,11 +66,19 @@ typedef struct {
                          FP64-residual Newton-Schulz step per block inverse */
     int adjoint_segment; /* 0: no adjoint workspace; > 0: slabs per checkpoint segment of
                             negf_rgf_adjoint; -1: ceil(sqrt(n_slab_max)) */
+    int store_checkpoint;/* 0: the forward sweep keeps g and g^< of every slab (n_slab_max
+                            blocks each per point); 1: only of the last slab of every
+                            segment of K slabs (K = adjoint_segment if > 0, else
+                            ceil(sqrt(n_slab_max))) plus one segment buffer, about
+                            2 sqrt(n_slab_max) blocks each per point; the backward sweep
+                            and the adjoint then recompute each segment's g and g^< from
+                            its checkpoint (the same kernels, so the same values) */
 } negf_config;
 
 /* Create a context and allocate its device workspace (the only allocation of
  * the hot path): two stores of capacity * n_slab_max blocks for the
- * left-connected g^R and g^< plus per-point temporaries.
+ * left-connected g^R and g^< (or their checkpoints and one segment, with
+ * store_checkpoint = 1) plus per-point temporaries.
  * Errors: NEGF_EINVAL (bad sizes), NEGF_ENOMEM. */
 int negf_create(const negf_config* cfg, negf_ctx** out);
 void negf_destroy(negf_ctx* ctx);
@@ -216,6 +224,17 @@ int negf_scba_selfenergy(negf_ctx* ctx, void* stream,
                          const negf_c128* GR, const negf_c128* GL, int slab_stride,
                          const double* w_k, double D_ac, double M_op, int shift, double n_bose,
                          negf_c128* sig_R, negf_c128* sig_L, double* rel_change);
+
+/*
+ * The residual history of the self-consistent Born loop kept on the device:
+ * every negf_scba_selfenergy call appends its ||Sigma_new - Sigma_old||_F /
+ * ||Sigma_new||_F to a device list (the first 4096 are kept), so a loop
+ * replayed from a captured HIP graph needs no host read per iteration.  This
+ * call synchronises `stream`, copies min(count, 4096, max_n) entries to the
+ * HOST array out[max_n], returns in *n_out the number of calls since the
+ * previous read, and clears the list.
+ * Errors: NEGF_EINVAL (NULL context or n_out, max_n < 0, out NULL with max_n > 0). */
+int negf_scba_history(negf_ctx* ctx, void* stream, double* out, int max_n, int* n_out);
 
 /*
  * Observables of Eqs. (7)-(8) over the whole bound point set, summed in a

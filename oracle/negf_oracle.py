@@ -169,7 +169,7 @@ def _m3(a, b, c, right):
 
 
 def rgf(hd, hu, E, eta, sigL, sigR, fL, fR, v=None, scatR=None, scatL=None,
-        eta_fill=None, transmission=False, assoc_right=False):
+        eta_fill=None, transmission=False, assoc_right=False, bond_mag=False):
     """Diagonal blocks of G^R, G^<, G^> plus bond currents (and optionally the
     Caroli transmission) of one (sample, k, E) point by recursive Green's
     functions.
@@ -194,7 +194,11 @@ def rgf(hd, hu, E, eta, sigL, sigR, fL, fR, v=None, scatR=None, scatL=None,
     Pinned by: dense inversion (``dense``), Landauer, eta-sink current identity,
     spectral identity, reciprocity, integer transmission of ordered strips.
     ``assoc_right`` associates every triple product the other way; it only serves
-    the reproducibility estimate (two correct FP64 evaluations of one point)."""
+    the reproducibility estimate (two correct FP64 evaluations of one point).
+    ``bond_mag`` also returns, per bond, the sum of magnitudes of the terms the
+    bond trace adds, 2 Tr[|H_{i,i+1}| (|G_{i+1}| |H_{i+1,i}| |g^<_i| + |G^<_{i+1}| |L|^T)]
+    (|X| elementwise): the scale on which any FP64 evaluation of the trace, in
+    any order, rounds (test tolerances only; no result depends on it)."""
     N = len(hd)
     ar = assoc_right
     b = hd[0].shape[0]
@@ -216,6 +220,7 @@ def rgf(hd, hu, E, eta, sigL, sigR, fL, fR, v=None, scatR=None, scatL=None,
     GR[N - 1] = g[N - 1]
     GL[N - 1] = gl[N - 1]
     bond = np.zeros(max(N - 1, 0))
+    mag = np.zeros(max(N - 1, 0))
     for i in range(N - 2, -1, -1):
         hr = dag(hu[i])                # H_{i+1,i}
         L = g[i] @ hu[i]
@@ -225,10 +230,15 @@ def rgf(hd, hu, E, eta, sigL, sigR, fL, fR, v=None, scatR=None, scatL=None,
         GL[i] = gl[i] + _m3(L, GL[i + 1], dag(L), ar) + T - dag(T)
         gl_10 = _m3(GR[i + 1], hr, gl[i], ar) + GL[i + 1] @ dag(L)
         bond[i] = 2.0 * np.real(np.trace(hu[i] @ gl_10))
+        if bond_mag:
+            a = np.abs
+            mag[i] = 2.0 * np.trace(a(hu[i]) @ (a(GR[i + 1]) @ a(hr) @ a(gl[i]) + a(GL[i + 1]) @ a(L).T))
     GR = np.array(GR)
     GL = np.array(GL)
     GG = GL + GR - np.conj(np.transpose(GR, (0, 2, 1)))
     out = dict(GR=GR, GL=GL, GG=GG, bond=bond)
+    if bond_mag:
+        out["bond_mag"] = mag
     if transmission:
         col = g[0]
         for i in range(1, N):
@@ -336,7 +346,7 @@ def lead_tables(wl, tol=1e-14, max_iter=100, ks=None, es=None, variant=None):
 
 
 def solve_points(wl, points, leads=None, scatR=None, scatL=None, transmission=False, eta_fill=None,
-                 variant=None):
+                 variant=None, bond_mag=False):
     """RGF for a list of (sample, ik, ie) points.  scatR/scatL: [n_e, total_slabs, b].
     variant="alt": the reproducibility estimate, with the lead decimation and every
     triple product of the recursion associated the other way."""
@@ -355,7 +365,8 @@ def solve_points(wl, points, leads=None, scatR=None, scatL=None, transmission=Fa
         sl = None if scatL is None else scatL[ie, a0:a1]
         ef = None if eta_fill is None else float(fermi(E, eta_fill, wl.kT))
         res.append(rgf(hd, hu, E, wl.eta, sL, sR, fL, fR, v=v, scatR=sr, scatL=sl,
-                       transmission=transmission, eta_fill=ef, assoc_right=(variant == "alt")))
+                       transmission=transmission, eta_fill=ef, assoc_right=(variant == "alt"),
+                       bond_mag=bond_mag))
     return res
 
 

@@ -19,6 +19,7 @@ constexpr int NTMP = 24;
 constexpr int DUAL_NBLK = 64;   // blocks of the h01_L = h01_R^dagger check
 constexpr int NBMAX_INV = 32;   // widest Gauss-Jordan panel
 constexpr int EV_POOL = 2048;
+constexpr int SCBA_HMAX = 4096; // SCBA residual history entries kept on the device
 
 struct TimedLaunch {
     hipEvent_t a, b;
@@ -33,8 +34,14 @@ struct negf_ctx {
     int sdt = DT_C128;            // store element type
     size_t ce = 16;               // bytes per store element
     std::vector<void*> allocs;
-    void* gst = nullptr;          // [cap][nsm][nb][nb]  left-connected g^R
-    void* glst = nullptr;         // [cap][nsm][nb][nb]  left-connected g^<
+    void* gst = nullptr;          // [cap][nsm][nb][nb]  left-connected g^R (checkpoint mode: [cap][segK][nb][nb],
+                                  // the slabs of the segment being worked on, slab i in slot i % segK)
+    void* glst = nullptr;         // the same for the left-connected g^<
+    bool ckpt = false;            // checkpointed stores: only the last slab of every segment is kept
+    int segK = 0, segN = 0;       // slabs per segment and segments (checkpoint mode)
+    void* ckg = nullptr;          // [cap][segN][nb][nb]  g at the last slab of each segment
+    void* ckgl = nullptr;         // [cap][segN][nb][nb]  g^< at the last slab of each segment
+    int seg_loaded = -1;          // segment whose stores the segment buffers hold (checkpoint mode)
     double2* tmp[NTMP] = {};
     void* invE = nullptr;
     void* invP = nullptr;
@@ -58,6 +65,8 @@ struct negf_ctx {
     int* ns_flag = nullptr;       // [cap] fallback flag per point
     int* ns_count = nullptr;      // device fallback counter
     double* ns_max = nullptr;     // device: per-point max residual history (max)
+    double* scba_hist = nullptr;  // [SCBA_HMAX] ||dSigma|| / ||Sigma|| of each negf_scba_selfenergy call
+    int* scba_count = nullptr;    // entries appended since the last negf_scba_history
     double ns_thr = 1e-2;         // ||I - M X0||_F above which a block inverse is redone in FP64
     int adj_K = 0, adj_nseg = 0;  // adjoint checkpoint segment length and count
     double2* adj_yseg = nullptr;  // [cap][K][nb][nb]  y of the segment being swept
@@ -89,7 +98,11 @@ struct negf_ctx {
 
     // forward state
     bool fwd_done = false;
-    int fwd_p0 = -1, fwd_np = 0, fwd_flags = 0;
+    int fwd_p0 = -1, fwd_np = 0, fwd_flags = 0, fwd_maxN = 0;
+    const double2* fwd_sL = nullptr;   // the forward's inputs (checkpoint mode recomputes segments from them)
+    const double2* fwd_sR = nullptr;
+    const double2* fwd_scR = nullptr;
+    const double2* fwd_scL = nullptr;
 
     // timing of the GEMM family
     bool timing = false;
@@ -177,11 +190,21 @@ GemmArgs gargs(int n, int np, const Active& act) {
     return g;
 }
 
+// Slab `slab` of a working store (g or g^<): every slab in the full store, or
+// the slot of the segment buffer (checkpoint mode; valid while its segment is loaded).
 void* slot(const negf_ctx* c, void* store, int slab) {
-    return static_cast<char*>(store) + (size_t)slab * c->nb * c->nb * c->ce;
+    const int k = c->ckpt ? slab % c->segK : slab;
+    return static_cast<char*>(store) + (size_t)k * c->nb * c->nb * c->ce;
 }
 
-long long store_stride(const negf_ctx* c) { return (long long)c->nsm * c->nb * c->nb; }
+long long store_stride(const negf_ctx* c) { return (long long)(c->ckpt ? c->segK : c->nsm) * c->nb * c->nb; }
+
+// Checkpoint of segment `sg` (its last slab) in ckg / ckgl.
+void* ckslot(const negf_ctx* c, void* ck, int sg) {
+    return static_cast<char*>(ck) + (size_t)sg * c->nb * c->nb * c->ce;
+}
+
+long long ck_stride(const negf_ctx* c) { return (long long)c->segN * c->nb * c->nb; }
 
 // Active point counts and grid extents over [p0, p0+np) for predicate mode at step.
 void extent(const negf_ctx* c, int p0, int np, int mode, int step, int* hi, long long* cnt) {
@@ -285,8 +308,9 @@ __global__ __launch_bounds__(256) void ns_check_kernel(const double2* R, long lo
         if (on && r > res[q]) res[q] = r;
         int f = (on && !(r <= thr)) ? 1 : 0;
         flag[q] = f;
-        if (f) { atomicAdd(count, 1); raise_status(status, ST_FALLBACK); }
-        if (on && r > histmax[q]) histmax[q] = r;
+        if (f && count) atomicAdd(count, 1);
+        if (f) raise_status(status, ST_FALLBACK);
+        if (on && histmax && r > histmax[q]) histmax[q] = r;
     }
 }
 
@@ -320,6 +344,7 @@ int negf_create(const negf_config* cfg, negf_ctx** out) {
     if (!cfg || !out) return NEGF_EINVAL;
     *out = nullptr;
     if (cfg->nb < 1 || cfg->nb > INV_NMAX || cfg->n_slab_max < 1 || cfg->capacity < 1) return NEGF_EINVAL;
+    if (cfg->store_checkpoint != 0 && cfg->store_checkpoint != 1) return NEGF_EINVAL;
     if (cfg->precision != NEGF_FP64 && cfg->precision != NEGF_MIXED) return NEGF_EINVAL;
     negf_ctx* c = new (std::nothrow) negf_ctx();
     if (!c) return NEGF_ENOMEM;
@@ -332,8 +357,17 @@ int negf_create(const negf_config* cfg, negf_ctx** out) {
     c->ce = (c->prec == NEGF_MIXED) ? 8 : 16;
     const size_t nn = (size_t)c->nb * c->nb;
     const size_t cap = (size_t)c->cap;
-    bool ok = dev_alloc(c, &c->gst, cap * c->nsm * nn * c->ce, c->allocs) &&
-              dev_alloc(c, &c->glst, cap * c->nsm * nn * c->ce, c->allocs);
+    // checkpointed stores: segments of K slabs (K = adjoint_segment when given,
+    // else ceil(sqrt(n_slab_max))); the adjoint then uses the same segments
+    int K0 = cfg->adjoint_segment > 0 ? cfg->adjoint_segment : (int)std::ceil(std::sqrt((double)c->nsm));
+    K0 = std::max(1, std::min(K0, c->nsm));
+    c->ckpt = cfg->store_checkpoint != 0;
+    if (c->ckpt) { c->segK = K0; c->segN = (c->nsm + K0 - 1) / K0; }
+    const size_t slots = c->ckpt ? (size_t)c->segK : (size_t)c->nsm;
+    bool ok = dev_alloc(c, &c->gst, cap * slots * nn * c->ce, c->allocs) &&
+              dev_alloc(c, &c->glst, cap * slots * nn * c->ce, c->allocs) &&
+              (!c->ckpt || (dev_alloc(c, &c->ckg, cap * c->segN * nn * c->ce, c->allocs) &&
+                            dev_alloc(c, &c->ckgl, cap * c->segN * nn * c->ce, c->allocs)));
     for (int i = 0; ok && i < NTMP; ++i) ok = dev_alloc(c, &c->tmp[i], cap * nn * sizeof(double2), c->allocs);
     ok = ok && dev_alloc(c, &c->invE, cap * c->nb * NBMAX_INV * sizeof(double2), c->allocs) &&
          dev_alloc(c, &c->invP, cap * c->nb * NBMAX_INV * sizeof(double2), c->allocs) &&
@@ -356,11 +390,11 @@ int negf_create(const negf_config* cfg, negf_ctx** out) {
          dev_alloc(c, &c->ns_res, cap * sizeof(double), c->allocs) &&
          dev_alloc(c, &c->ns_flag, cap * sizeof(int), c->allocs) &&
          dev_alloc(c, &c->ns_count, 4 * sizeof(int), c->allocs) &&
-         dev_alloc(c, &c->ns_max, cap * sizeof(double), c->allocs);
+         dev_alloc(c, &c->ns_max, cap * sizeof(double), c->allocs) &&
+         dev_alloc(c, &c->scba_hist, SCBA_HMAX * sizeof(double), c->allocs) &&
+         dev_alloc(c, &c->scba_count, 4 * sizeof(int), c->allocs);
     if (ok && cfg->adjoint_segment != 0) {
-        int K = cfg->adjoint_segment;
-        if (K < 0) { K = (int)std::ceil(std::sqrt((double)c->nsm)); }
-        if (K > c->nsm) K = c->nsm;
+        const int K = K0;
         c->adj_K = K;
         c->adj_nseg = (c->nsm + K - 1) / K;
         ok = dev_alloc(c, &c->adj_yseg, cap * K * nn * sizeof(double2), c->allocs) &&
@@ -373,6 +407,7 @@ int negf_create(const negf_config* cfg, negf_ctx** out) {
     if (inverse_init() != hipSuccess || sandwich_init() != hipSuccess) { delete c; return NEGF_EHIP; }
     hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, 0, c->status, 0, 4);
     hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, 0, c->ns_count, 0, 4);
+    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, 0, c->scba_count, 0, 4);
     hipLaunchKernelGGL(zero_d_kernel, dim3((c->cap + 255) / 256), dim3(256), 0, 0, c->ns_max, c->cap);
     if (hipDeviceSynchronize() != hipSuccess) { delete c; return NEGF_EHIP; }
     *out = c;
@@ -600,6 +635,96 @@ int negf_lead_selfenergy_pair(negf_ctx* c, void* stream, int n_k, const negf_c12
     return std::max(a, b);
 }
 
+}  // extern "C"
+
+// One slab of the forward sweep for points [p0, p0 + np): reads g_{i-1} and
+// g^<_{i-1} at (gp, glp) with point stride sp (unused at i = 0) and writes g_i,
+// g^<_i to the working stores (slot(i)).  With `stats` false (a checkpoint
+// segment being recomputed) the mixed-precision fallback counter and residual
+// history are not touched again.
+static int fwd_slab(negf_ctx* c, hipStream_t s, int p0, int np, int i, const void* gp, const void* glp,
+                    long long sp, bool stats) {
+    const int n = c->nb;
+    const long long nn = (long long)n * n;
+    const long long sst = store_stride(c);
+    const bool mixed = c->prec == NEGF_MIXED;
+    const int sdt = c->sdt;
+    const GemmTypes TS{sdt, sdt, sdt, sdt};
+    int hi;
+    long long cnt;
+    extent(c, p0, np, PRED_FWD, i, &hi, &cnt);
+    if (cnt == 0) return NEGF_OK;
+    Active act{c->desc_d, p0, i, PRED_FWD, nullptr};
+    // M = A_ii - H_{i,i-1} g_{i-1} H_{i-1,i}   (FP64 assembly)
+    SandArgs sa = sand_base(c, p0, act, hi);
+    sa.sigL = c->fwd_sL; sa.sigR = c->fwd_sR;
+    sa.X = (i > 0) ? gp : nullptr; sa.sX = sp;
+    sa.uslab = i - 1; sa.opL = 2; sa.opR = 1; sa.sign = -1.0;
+    sa.O = c->tmp[0]; sa.sO = nn; sa.mode = 1; sa.slab = i;
+    sa.scat = c->fwd_scR;
+    NEGF_HIP_CHECK(sandwich_launch(s, sdt, DT_C128, sa));
+    if (!mixed) {
+        NEGF_HIP_CHECK(inverse_launch(s, DT_C128, c->tmp[0], nn, slot(c, c->gst, i), sst, n, hi, act,
+                                      invwork(c, c->tmp[3])));
+    } else {
+        // X0 = M^-1 in FP32, R = I - M X0 in FP64, X1 = X0 + X0 R in FP32.
+        Active all{c->desc_d, p0, i, PRED_FWD, nullptr};
+        NEGF_HIP_CHECK(copy_launch(s, DT_C128, DT_C64, c->tmp[0], nn, c->tmp[4], nn, nn, hi, act));
+        NEGF_HIP_CHECK(inverse_launch(s, DT_C64, c->tmp[4], nn, c->tmp[2], nn, n, hi, act,
+                                      invwork(c, c->tmp[3])));
+        GemmArgs G = gargs(n, hi, act);
+        G.A = c->tmp[0]; G.sA = nn; G.B = c->tmp[2]; G.sB = nn; G.C = c->tmp[1]; G.sC = nn;
+        NEGF_HIP_CHECK(run_gemm(c, s, GemmTypes{DT_C128, DT_C64, DT_C128, DT_C128}, OP_N, OP_N, EPI_IMINUS, G, cnt));
+        hipLaunchKernelGGL(ns_check_kernel, dim3(hi), dim3(256), 0, s, c->tmp[1], nn, n, hi, all, c->ns_thr,
+                           c->ns_res, c->ns_flag, stats ? c->ns_count : nullptr, stats ? c->ns_max : nullptr,
+                           c->status);
+        NEGF_HIP_CHECK(hipGetLastError());
+        G.A = c->tmp[2]; G.B = c->tmp[1]; G.D = c->tmp[2]; G.sD = nn; G.C = slot(c, c->gst, i); G.sC = sst;
+        NEGF_HIP_CHECK(run_gemm(c, s, GemmTypes{DT_C64, DT_C128, DT_C64, DT_C64}, OP_N, OP_N, EPI_ADD, G, cnt));
+        // FP64 fallback for flagged points (M is still in tmp[0]).
+        Active fb{c->desc_d, p0, i, PRED_SET, c->ns_flag};
+        NEGF_HIP_CHECK(inverse_launch(s, DT_C128, c->tmp[0], nn, c->tmp[1], nn, n, hi, fb, invwork(c, c->tmp[3])));
+        NEGF_HIP_CHECK(copy_launch(s, DT_C128, DT_C64, c->tmp[1], nn, slot(c, c->gst, i), sst, nn, hi, fb));
+    }
+    // X = Sigma^<_i + H_{i,i-1} g^<_{i-1} H_{i-1,i}
+    sa.X = (i > 0) ? glp : nullptr; sa.sX = sp;
+    sa.sign = 1.0; sa.mode = 2; sa.O = c->tmp[1];
+    sa.scat = c->fwd_scL;
+    sa.lesser_ref = mixed ? 1 : 0;
+    sa.scat2 = c->fwd_scR;
+    NEGF_HIP_CHECK(sandwich_launch(s, sdt, sdt, sa));
+    // g^<_i = g_i X g_i^dagger
+    GemmArgs G = gargs(n, hi, act);
+    G.A = slot(c, c->gst, i); G.sA = sst; G.B = c->tmp[1]; G.sB = nn; G.C = c->tmp[2]; G.sC = nn;
+    NEGF_HIP_CHECK(run_gemm(c, s, TS, OP_N, OP_N, EPI_STORE, G, cnt));
+    G.A = c->tmp[2]; G.sA = nn; G.B = slot(c, c->gst, i); G.sB = sst; G.C = slot(c, c->glst, i); G.sC = sst;
+    NEGF_HIP_CHECK(run_gemm(c, s, TS, OP_N, OP_C, EPI_STORE_AH, G, cnt));   // anti-Hermitian
+    return NEGF_OK;
+}
+
+// Checkpoint mode: make the segment buffers hold segment `sg` of the last
+// forward sweep, recomputing its slabs from the checkpoint of segment sg - 1.
+static int load_segment(negf_ctx* c, hipStream_t s, int sg) {
+    if (!c->ckpt || c->seg_loaded == sg) return NEGF_OK;
+    const int i0 = sg * c->segK, i1 = std::min((sg + 1) * c->segK, c->fwd_maxN);
+    const long long sst = store_stride(c), sck = ck_stride(c);
+    for (int i = i0; i < i1; ++i) {
+        const void *gp = nullptr, *glp = nullptr;
+        long long sp = sst;
+        if (i == i0 && sg > 0) {
+            gp = ckslot(c, c->ckg, sg - 1); glp = ckslot(c, c->ckgl, sg - 1); sp = sck;
+        } else if (i > i0) {
+            gp = slot(c, c->gst, i - 1); glp = slot(c, c->glst, i - 1);
+        }
+        const int st = fwd_slab(c, s, c->fwd_p0, c->fwd_np, i, gp, glp, sp, false);
+        if (st != NEGF_OK) return st;
+    }
+    c->seg_loaded = sg;
+    return NEGF_OK;
+}
+
+extern "C" {
+
 int negf_rgf_forward(negf_ctx* c, void* stream, int p0, int np, const negf_c128* sigma_L,
                      const negf_c128* sigma_R, const negf_c128* scat_R, const negf_c128* scat_L, int flags) {
     if (!c) return NEGF_EINVAL;
@@ -619,6 +744,15 @@ int negf_rgf_forward(negf_ctx* c, void* stream, int p0, int np, const negf_c128*
     const bool wantT = (flags & NEGF_WANT_TRANSMISSION) != 0;
     const double2* sL = reinterpret_cast<const double2*>(sigma_L);
     const double2* sR = reinterpret_cast<const double2*>(sigma_R);
+    c->fwd_done = false;
+    c->fwd_p0 = p0;
+    c->fwd_np = np;
+    c->fwd_maxN = maxN;
+    c->fwd_sL = sL;
+    c->fwd_sR = sR;
+    c->fwd_scR = reinterpret_cast<const double2*>(scat_R);
+    c->fwd_scL = reinterpret_cast<const double2*>(scat_L);
+    c->seg_loaded = -1;
     if (mixed) {
         hipLaunchKernelGGL(zero_d_kernel, dim3((np + 255) / 256), dim3(256), 0, s, c->ns_res, np);
         NEGF_HIP_CHECK(hipGetLastError());
@@ -628,49 +762,17 @@ int negf_rgf_forward(negf_ctx* c, void* stream, int p0, int np, const negf_c128*
         long long cnt;
         extent(c, p0, np, PRED_FWD, i, &hi, &cnt);
         Active act{c->desc_d, p0, i, PRED_FWD, nullptr};
-        // M = A_ii - H_{i,i-1} g_{i-1} H_{i-1,i}   (FP64 assembly)
-        SandArgs sa = sand_base(c, p0, act, hi);
-        sa.sigL = sL; sa.sigR = sR;
-        sa.X = (i > 0) ? slot(c, c->gst, i - 1) : nullptr; sa.sX = sst;
-        sa.uslab = i - 1; sa.opL = 2; sa.opR = 1; sa.sign = -1.0;
-        sa.O = c->tmp[0]; sa.sO = nn; sa.mode = 1; sa.slab = i;
-        sa.scat = reinterpret_cast<const double2*>(scat_R);
-        NEGF_HIP_CHECK(sandwich_launch(s, sdt, DT_C128, sa));
-        if (!mixed) {
-            NEGF_HIP_CHECK(inverse_launch(s, DT_C128, c->tmp[0], nn, slot(c, c->gst, i), sst, n, hi, act,
-                                          invwork(c, c->tmp[3])));
-        } else {
-            // X0 = M^-1 in FP32, R = I - M X0 in FP64, X1 = X0 + X0 R in FP32.
-            Active all{c->desc_d, p0, i, PRED_FWD, nullptr};
-            NEGF_HIP_CHECK(copy_launch(s, DT_C128, DT_C64, c->tmp[0], nn, c->tmp[4], nn, nn, hi, act));
-            NEGF_HIP_CHECK(inverse_launch(s, DT_C64, c->tmp[4], nn, c->tmp[2], nn, n, hi, act,
-                                          invwork(c, c->tmp[3])));
-            GemmArgs G = gargs(n, hi, act);
-            G.A = c->tmp[0]; G.sA = nn; G.B = c->tmp[2]; G.sB = nn; G.C = c->tmp[1]; G.sC = nn;
-            NEGF_HIP_CHECK(run_gemm(c, s, GemmTypes{DT_C128, DT_C64, DT_C128, DT_C128}, OP_N, OP_N, EPI_IMINUS, G, cnt));
-            hipLaunchKernelGGL(ns_check_kernel, dim3(hi), dim3(256), 0, s, c->tmp[1], nn, n, hi, all, c->ns_thr,
-                               c->ns_res, c->ns_flag, c->ns_count, c->ns_max, c->status);
-            NEGF_HIP_CHECK(hipGetLastError());
-            G.A = c->tmp[2]; G.B = c->tmp[1]; G.D = c->tmp[2]; G.sD = nn; G.C = slot(c, c->gst, i); G.sC = sst;
-            NEGF_HIP_CHECK(run_gemm(c, s, GemmTypes{DT_C64, DT_C128, DT_C64, DT_C64}, OP_N, OP_N, EPI_ADD, G, cnt));
-            // FP64 fallback for flagged points (M is still in tmp[0]).
-            Active fb{c->desc_d, p0, i, PRED_SET, c->ns_flag};
-            NEGF_HIP_CHECK(inverse_launch(s, DT_C128, c->tmp[0], nn, c->tmp[1], nn, n, hi, fb, invwork(c, c->tmp[3])));
-            NEGF_HIP_CHECK(copy_launch(s, DT_C128, DT_C64, c->tmp[1], nn, slot(c, c->gst, i), sst, nn, hi, fb));
+        const int st = fwd_slab(c, s, p0, np, i, i > 0 ? slot(c, c->gst, i - 1) : nullptr,
+                                i > 0 ? slot(c, c->glst, i - 1) : nullptr, sst, true);
+        if (st != NEGF_OK) return st;
+        if (c->ckpt && i % c->segK == c->segK - 1 && i + 1 < maxN) {
+            // checkpoint: the segment's last slab (the next one only overwrites its slot later)
+            const int sg = i / c->segK;
+            NEGF_HIP_CHECK(copy_launch(s, sdt, sdt, slot(c, c->gst, i), sst, ckslot(c, c->ckg, sg), ck_stride(c), nn,
+                                       hi, act));
+            NEGF_HIP_CHECK(copy_launch(s, sdt, sdt, slot(c, c->glst, i), sst, ckslot(c, c->ckgl, sg), ck_stride(c),
+                                       nn, hi, act));
         }
-        // X = Sigma^<_i + H_{i,i-1} g^<_{i-1} H_{i-1,i}
-        sa.X = (i > 0) ? slot(c, c->glst, i - 1) : nullptr;
-        sa.sign = 1.0; sa.mode = 2; sa.O = c->tmp[1];
-        sa.scat = reinterpret_cast<const double2*>(scat_L);
-        sa.lesser_ref = mixed ? 1 : 0;
-        sa.scat2 = reinterpret_cast<const double2*>(scat_R);
-        NEGF_HIP_CHECK(sandwich_launch(s, sdt, sdt, sa));
-        // g^<_i = g_i X g_i^dagger
-        GemmArgs G = gargs(n, hi, act);
-        G.A = slot(c, c->gst, i); G.sA = sst; G.B = c->tmp[1]; G.sB = nn; G.C = c->tmp[2]; G.sC = nn;
-        NEGF_HIP_CHECK(run_gemm(c, s, TS, OP_N, OP_N, EPI_STORE, G, cnt));
-        G.A = c->tmp[2]; G.sA = nn; G.B = slot(c, c->gst, i); G.sB = sst; G.C = slot(c, c->glst, i); G.sC = sst;
-        NEGF_HIP_CHECK(run_gemm(c, s, TS, OP_N, OP_C, EPI_STORE_AH, G, cnt));   // anti-Hermitian
         if (wantT) {
             // left-column chain G_{i,1} = g_i H_{i,i-1} G_{i-1,1}
             if (i == 0) {
@@ -686,6 +788,7 @@ int negf_rgf_forward(negf_ctx* c, void* stream, int p0, int np, const negf_c128*
             }
         }
     }
+    if (c->ckpt) c->seg_loaded = (maxN - 1) / c->segK;
     if (wantT) {
         // T = Tr[Gamma_R C Gamma_L C^dagger], C = G_{N,1}
         PointSet ps{c->desc_d, c->soff_d, p0};
@@ -700,8 +803,6 @@ int negf_rgf_forward(negf_ctx* c, void* stream, int p0, int np, const negf_c128*
         NEGF_HIP_CHECK(trace_prod_launch(s, sdt, c->tmp[9], c->tmp[10], nn, n, np, c->trans_d, p0));
     }
     c->fwd_done = true;
-    c->fwd_p0 = p0;
-    c->fwd_np = np;
     c->fwd_flags = flags;
     return NEGF_OK;
 }
@@ -724,6 +825,10 @@ int negf_rgf_backward(negf_ctx* c, void* stream, int p0, int np, negf_c128* GR, 
     double2* GLb[2] = {c->tmp[10], c->tmp[11]};
     PointSet ps{c->desc_d, c->soff_d, p0};
     for (int st = maxN - 1; st >= 0; --st) {
+        if (c->ckpt && (st == maxN - 1 || st % c->segK == c->segK - 1)) {
+            const int e = load_segment(c, s, st / c->segK);
+            if (e != NEGF_OK) return e;
+        }
         const int cur = st & 1, nxt = cur ^ 1;
         int hiF, hiB, hiI;
         long long cF, cB, cI;
@@ -812,7 +917,21 @@ int negf_scba_selfenergy(negf_ctx* c, void* stream, const negf_c128* GR, const n
     a.sigR = reinterpret_cast<double2*>(sig_R);
     a.sigL = reinterpret_cast<double2*>(sig_L);
     a.partial = c->scba_partial_d;
-    NEGF_HIP_CHECK(scba_launch((hipStream_t)stream, a, rel_change));
+    NEGF_HIP_CHECK(scba_launch((hipStream_t)stream, a, rel_change, c->scba_hist, c->scba_count, SCBA_HMAX));
+    return NEGF_OK;
+}
+
+int negf_scba_history(negf_ctx* c, void* stream, double* out, int max_n, int* n_out) {
+    if (!c || !n_out || max_n < 0 || (max_n > 0 && !out)) return NEGF_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    NEGF_HIP_CHECK(hipMemcpyAsync(c->h_pinned, c->scba_count, sizeof(int), hipMemcpyDeviceToHost, s));
+    NEGF_HIP_CHECK(hipStreamSynchronize(s));
+    const int cnt = c->h_pinned[0];
+    *n_out = cnt;
+    const int m = std::min(std::min(cnt, SCBA_HMAX), max_n);
+    if (m > 0) NEGF_HIP_CHECK(hipMemcpy(out, c->scba_hist, m * sizeof(double), hipMemcpyDeviceToHost));
+    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, s, c->scba_count, 0, 1);
+    NEGF_HIP_CHECK(hipGetLastError());
     return NEGF_OK;
 }
 
@@ -897,6 +1016,10 @@ int negf_rgf_adjoint(negf_ctx* c, void* stream, int p0, int np, const double* w_
     double2* yp[2] = {t[4], t[5]};
     double2* xp[2] = {t[6], t[7]};
     for (int i = 0; i < maxN; ++i) {
+        if (c->ckpt && i % c->segK == 0) {
+            const int e = load_segment(c, s, i / c->segK);
+            if (e != NEGF_OK) return e;
+        }
         int st = fwd_step(i, yp[(i + 1) & 1], xp[(i + 1) & 1], nn, yp[i & 1], xp[i & 1], nn);
         if (st != NEGF_OK) return st;
         if ((i + 1) % K == 0 && i + 1 < maxN) {
@@ -918,6 +1041,8 @@ int negf_rgf_adjoint(negf_ctx* c, void* stream, int p0, int np, const double* w_
     double2 *tL = t[16], *tR = t[17], *tQ = t[18], *tP = t[19], *tT = t[20], *tW = t[21], *tGR = t[22],
             *tK1 = t[23], *tK2 = t[0], *tLg = t[1], *tRy = t[2], *tLy = t[3], *tRx = t[4], *tLx = t[5];
     for (int sg = nseg - 1; sg >= 0; --sg) {
+        const int lst = load_segment(c, s, sg);
+        if (lst != NEGF_OK) return lst;
         const int i0 = sg * K, i1 = std::min((sg + 1) * K, maxN);
         for (int i = i0; i < i1; ++i) {
             const double2 *ypv, *xpv;

@@ -794,7 +794,8 @@ __global__ __launch_bounds__(256) void scba_kernel(ScbaArgs a) {
     if (threadIdx.x == 0) { a.partial[2 * blockIdx.x] = rd[0]; a.partial[2 * blockIdx.x + 1] = rn[0]; }
 }
 
-__global__ __launch_bounds__(256) void scba_final_kernel(const double* partial, int nblk, double* out) {
+__global__ __launch_bounds__(256) void scba_final_kernel(const double* partial, int nblk, double* out, double* hist,
+                                                         int* hcount, int hmax) {
     double d = 0.0, m = 0.0;
     for (int b = threadIdx.x; b < nblk; b += 256) { d += partial[2 * b]; m += partial[2 * b + 1]; }
     __shared__ double rd[256], rn[256];
@@ -805,16 +806,25 @@ __global__ __launch_bounds__(256) void scba_final_kernel(const double* partial, 
         if ((int)threadIdx.x < o) { rd[threadIdx.x] += rd[threadIdx.x + o]; rn[threadIdx.x] += rn[threadIdx.x + o]; }
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[0] = rn[0] > 0 ? sqrt(rd[0] / rn[0]) : 0.0;
+    if (threadIdx.x == 0) {
+        const double r = rn[0] > 0 ? sqrt(rd[0] / rn[0]) : 0.0;
+        if (out) out[0] = r;
+        // append to the device history (read back once after a captured loop)
+        const int c = *hcount;
+        if (c < hmax) hist[c] = r;
+        *hcount = c + 1;
+    }
 }
 
-hipError_t scba_launch(hipStream_t s, const ScbaArgs& a, double* rel_change) {
+hipError_t scba_launch(hipStream_t s, const ScbaArgs& a, double* rel_change, double* hist, int* hcount,
+                       int hmax) {
     const long long tot = (long long)a.n_e * a.N * a.n;
     const int nblk = (int)((tot + 255) / 256);
     hipLaunchKernelGGL(scba_kernel, dim3(nblk), dim3(256), 0, s, a);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !rel_change) return e;
-    hipLaunchKernelGGL(scba_final_kernel, dim3(1), dim3(256), 0, s, a.partial, nblk, rel_change);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(scba_final_kernel, dim3(1), dim3(256), 0, s, a.partial, nblk, rel_change, hist, hcount,
+                       hmax);
     return hipGetLastError();
 }
 

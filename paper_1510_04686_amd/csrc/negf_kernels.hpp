@@ -99,7 +99,9 @@ hipError_t sr_launch_init(hipStream_t s, const SrArgs& a);
 hipError_t sr_launch_zminus(hipStream_t s, const SrArgs& a, const double2* X, double2* M, const Active& act);
 hipError_t sr_launch_check(hipStream_t s, const SrArgs& a, const double2* alpha, const double2* beta, int it);
 hipError_t sr_launch_iters(hipStream_t s, const SrArgs& a, const int* it, int* out);
-hipError_t scba_launch(hipStream_t s, const ScbaArgs& a, double* rel_change);
+// rel_change (may be NULL) gets ||dSigma||_F / ||Sigma||_F; it is also appended to
+// hist[*hcount] (while *hcount < hmax) and *hcount incremented, on the device.
+hipError_t scba_launch(hipStream_t s, const ScbaArgs& a, double* rel_change, double* hist, int* hcount, int hmax);
 hipError_t observables_launch(hipStream_t s, const ObsArgs& a);
 // partial[2 b] = block-b maximum of |h01L - h01R^dagger|, partial[2 b + 1] = of |h01R|
 hipError_t lead_dual_check_launch(hipStream_t s, const double2* h01L, const double2* h01R, int n_k, int n,

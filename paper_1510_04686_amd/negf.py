@@ -35,7 +35,7 @@ class NegfError(RuntimeError):
 
 class negf_config(ctypes.Structure):
     _fields_ = [("nb", c_int), ("n_slab_max", c_int), ("capacity", c_int), ("precision", c_int),
-                ("adjoint_segment", c_int)]
+                ("adjoint_segment", c_int), ("store_checkpoint", c_int)]
 
 
 class negf_tuning(ctypes.Structure):
@@ -58,7 +58,7 @@ EXPORTS = [
     "negf_bind", "negf_lead_selfenergy", "negf_lead_selfenergy_pair", "negf_rgf_forward", "negf_rgf_backward",
     "negf_scba_selfenergy", "negf_observables", "negf_rgf_adjoint", "negf_zgemm_batched", "negf_zinv_batched", "negf_mixed_stats",
     "negf_set_mixed_threshold", "negf_mixed_point_residuals", "negf_gemm_timing_enable", "negf_gemm_timing", "negf_get_tuning", "negf_set_tuning", "negf_autotune",
-    "negf_build_id",
+    "negf_build_id", "negf_scba_history",
 ]
 
 
@@ -90,6 +90,7 @@ def lib():
         "negf_rgf_backward": (i, [vp, vp, i, i, vp, vp, vp, i, i, vp, vp]),
         "negf_scba_selfenergy": (i, [vp, vp, vp, vp, i, vp, d, d, i, d, vp, vp, vp]),
         "negf_observables": (i, [vp, vp, vp, vp, i, vp, vp, d, i, vp, vp, vp]),
+        "negf_scba_history": (i, [vp, vp, POINTER(d), i, POINTER(i)]),
         "negf_rgf_adjoint": (i, [vp, vp, i, i, vp, vp, i]),
         "negf_zgemm_batched": (i, [vp, vp, i, i, i, i, vp, vp, vp, i]),
         "negf_zinv_batched": (i, [vp, vp, i, i, vp, vp, i]),
@@ -153,8 +154,8 @@ class Context:
             self.handle = None
 
 
-def negf_create(nb, n_slab_max, capacity, precision=NEGF_FP64, adjoint_segment=0):
-    cfg = negf_config(nb, n_slab_max, capacity, precision, adjoint_segment)
+def negf_create(nb, n_slab_max, capacity, precision=NEGF_FP64, adjoint_segment=0, store_checkpoint=0):
+    cfg = negf_config(nb, n_slab_max, capacity, precision, adjoint_segment, int(store_checkpoint))
     h = c_void_p()
     _check("negf_create", lib().negf_create(ctypes.byref(cfg), ctypes.byref(h)))
     return Context(h, cfg)
@@ -236,6 +237,16 @@ def negf_scba_selfenergy(ctx, GR, GL, slab_stride, w_k, D_ac, M_op, shift, n_bos
         _ptr(sig_R, torch.complex128, "sig_R"), _ptr(sig_L, torch.complex128, "sig_L"),
         _ptr(rel_change, torch.float64, "rel_change"))
     _check("negf_scba_selfenergy", code)
+
+
+def negf_scba_history(ctx, max_n=4096, stream=None):
+    """Residuals ||dSigma|| / ||Sigma|| of the negf_scba_selfenergy calls since the
+    last read, oldest first (synchronises the stream and clears the list)."""
+    buf = (c_double * max_n)()
+    n = c_int(0)
+    _check("negf_scba_history", lib().negf_scba_history(ctx.handle, _stream(stream), buf, int(max_n),
+                                                         ctypes.byref(n)))
+    return [float(buf[j]) for j in range(min(n.value, max_n))]
 
 
 def negf_observables(ctx, GL, bond_j, slab_stride, w_e, w_k, g_s, orbs_per_atom, n=None, J=None, j_E=None,

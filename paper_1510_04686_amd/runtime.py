@@ -29,7 +29,7 @@ class RGFSolver:
     """Batched RGF over every (sample, k, E) point of a workload on one GPU."""
 
     def __init__(self, wl, precision="fp64", capacity=None, device="cuda", mem_fraction=0.75, adjoint_segment=0,
-                 tune=None, lanes=1, point_redo=0.03):
+                 tune=None, lanes=1, point_redo=0.03, store="full"):
         """tune: None keeps the library's default kernel shapes; "auto" measures
         them on this context once (negf_autotune) and caches the choice per
         (device, block, capacity, precision); a dict sets them explicitly.
@@ -42,7 +42,12 @@ class RGFSolver:
         solved again on an FP64 context and its outputs replaced.  The FP32
         recursion loses roughly that residual in relative accuracy on a point
         (its conditioning), so the bound trades accuracy against the share of
-        points redone; math.inf turns the redo off."""
+        points redone; math.inf turns the redo off.
+        store: "full" keeps g and g^< of every slab; "checkpoint" keeps them
+        only at the end of every segment of K = ceil(sqrt(N)) slabs (or
+        `adjoint_segment` slabs) plus one segment, and the backward sweep and
+        the adjoint recompute each segment (memory ~2 sqrt(N) blocks per point
+        and store instead of N)."""
         self.wl = wl
         self.device = torch.device(device)
         self.prec = N.NEGF_MIXED if precision == "mixed" else N.NEGF_FP64
@@ -69,9 +74,18 @@ class RGFSolver:
         rep = lambda m: _dev(np.broadcast_to(m, (nk, nb, nb)), c128, self.device)
         self.lead_h01_L, self.lead_tau_L = rep(wl.lead_h01_L), rep(wl.lead_tau_L)
         self.lead_h01_R, self.lead_tau_R = rep(wl.lead_h01_R), rep(wl.lead_tau_R)
+        if store not in ("full", "checkpoint"):
+            raise ValueError(f"store must be 'full' or 'checkpoint', not {store!r}")
+        self.store = store
+        nsm = self.n_slab_max
+        K = adjoint_segment if adjoint_segment > 0 else int(math.ceil(math.sqrt(nsm)))
+        K = max(1, min(K, nsm))
+        blocks = nsm if store == "full" else K + -(-nsm // K)        # per store
+        adj_blocks = 0 if adjoint_segment == 0 else 2 * (K + -(-nsm // K))
         if capacity is None:
             ce = 8 if self.prec == N.NEGF_MIXED else 16
-            per_point = 2 * self.n_slab_max * nb * nb * ce + 24 * nb * nb * 16 + (64 + 2 * 256 + 64) * nb * 16
+            per_point = (2 * blocks * nb * nb * ce + (24 + adj_blocks) * nb * nb * 16
+                         + (64 + 2 * 256 + 64) * nb * 16)
             free, _ = torch.cuda.mem_get_info(self.device)
             lanes = max(1, int(lanes))
             # up to 512 points per batch: two inverse panels per CU hide each other's latency
@@ -80,7 +94,8 @@ class RGFSolver:
         self.capacity = int(capacity)
         self.lanes = max(1, int(lanes))
         # the adjoint runs on the first lane only
-        self.ctxs = [N.negf_create(nb, self.n_slab_max, self.capacity, self.prec, adjoint_segment if i == 0 else 0)
+        self.ctxs = [N.negf_create(nb, self.n_slab_max, self.capacity, self.prec, adjoint_segment if i == 0 else 0,
+                                   store_checkpoint=(store == "checkpoint"))
                      for i in range(self.lanes)]
         self.ctx = self.ctxs[0]
         self.streams = [torch.cuda.Stream(self.device) for _ in range(self.lanes)] if self.lanes > 1 else None
@@ -359,20 +374,18 @@ class RGFSolver:
         self.scat_R = torch.zeros(shp, dtype=torch.complex128, device=self.device)
         self.scat_L = torch.zeros(shp, dtype=torch.complex128, device=self.device)
         out = self.alloc_outputs(want=("GR", "GL", "bond"))
-        rel = torch.zeros(1, dtype=torch.float64, device=self.device)
-        hist = []
+        N.negf_scba_history(self.ctx, 0)          # clear the device residual list
         # iteration 0: ballistic pass (Sigma_scat = 0)
         self.run_batches(out, scat_R=self.scat_R, scat_L=self.scat_L)
 
         def one_iteration(stream=None):
             N.negf_scba_selfenergy(self.ctx, out["GR"], out["GL"], self.slab_stride, self.w_k, wl.D_ac, wl.M_op,
-                                   wl.shift, wl.n_bose, self.scat_R, self.scat_L, rel, stream=stream)
+                                   wl.shift, wl.n_bose, self.scat_R, self.scat_L, None, stream=stream)
             self.run_batches(out, scat_R=self.scat_R, scat_L=self.scat_L, stream=stream)
 
         if n_iter <= 1 or not graph:
             for _ in range(n_iter - 1):
                 one_iteration()
-                hist.append(float(rel.item()))
         else:
             g = torch.cuda.CUDAGraph()
             s = torch.cuda.Stream()
@@ -382,13 +395,13 @@ class RGFSolver:
             with torch.cuda.graph(g, stream=s):
                 one_iteration(stream=s)
             torch.cuda.current_stream().wait_stream(s)
+            # the residuals stay on the device: no host read between replays
             for _ in range(n_iter - 1):
                 g.replay()
-                hist.append(float(rel.item()))
         # last update: Sigma_n from the n-th solve (the solve itself is not redone)
         N.negf_scba_selfenergy(self.ctx, out["GR"], out["GL"], self.slab_stride, self.w_k, wl.D_ac, wl.M_op,
-                               wl.shift, wl.n_bose, self.scat_R, self.scat_L, rel)
-        hist.append(float(rel.item()))
+                               wl.shift, wl.n_bose, self.scat_R, self.scat_L, None)
+        hist = N.negf_scba_history(self.ctx, max(n_iter, 1))
         self.scba_out = out
         return out, hist
 

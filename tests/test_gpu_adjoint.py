@@ -32,13 +32,14 @@ def _tiny(seed=3, nb=8, N=5, up=4, n_e=3):
     return wl
 
 
+@pytest.mark.parametrize("store", ["full", "checkpoint"])
 @pytest.mark.parametrize("segment", [1, 2, -1, 5])
-def test_adjoint_matches_dense_gradient(segment):
-    _say(f"adjoint tiny segment={segment}")
+def test_adjoint_matches_dense_gradient(segment, store):
+    _say(f"adjoint tiny segment={segment} store={store}")
     wl = _tiny()
     rng = np.random.default_rng(7)
     w = rng.normal(size=(wl.total_slabs, wl.atoms_per_slab))
-    s = _solver(wl, adjoint_segment=segment)
+    s = _solver(wl, adjoint_segment=segment, store=store)
     s.density()
     g = s.density_vjp(torch.from_numpy(w)).cpu().numpy()
     torch.cuda.synchronize()
@@ -48,15 +49,16 @@ def test_adjoint_matches_dense_gradient(segment):
     assert _rel(g, ref) < 1e-10
 
 
-def test_adjoint_ragged_samples_multi_batch():
-    _say("adjoint ragged multi-sample, 3 batches")
+@pytest.mark.parametrize("store", ["full", "checkpoint"])
+def test_adjoint_ragged_samples_multi_batch(store):
+    _say(f"adjoint ragged multi-sample, 3 batches, store={store}")
     wl = make_workload("C4", n_slab=5, n_e=2, n_z=1, n_y=2, n_samples=4)
     wl.eta = 1e-3
     wl.v_onsite = np.full((wl.total_slabs, wl.nb), 0.05)
     assert len(set(np.diff(wl.slab_offset).tolist())) > 1
     rng = np.random.default_rng(8)
     w = rng.normal(size=(wl.total_slabs, wl.atoms_per_slab))
-    s = _solver(wl, capacity=3, adjoint_segment=2)
+    s = _solver(wl, capacity=3, adjoint_segment=2, store=store)
     s.density()
     g = s.density_vjp(torch.from_numpy(w)).cpu().numpy()
     pts = [tuple(p) for p in s.points]
@@ -102,3 +104,33 @@ def test_autograd_function_backward():
     GLd = [np.diagonal(r["GL"], axis1=1, axis2=2) for r in res]
     rn, _, _ = O.observables(wl, [tuple(p) for p in s.points], GLd, [r["bond"] for r in res])
     assert _rel(n.detach().cpu().numpy(), rn) < 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("segment", [1, 2, 3, -1, 9])
+def test_checkpointed_stores_equal_full_stores(segment, precision):
+    """Checkpointed g / g^< stores (every segment recomputed from its
+    checkpoint in the backward sweep and the adjoint) give the full-store
+    results bit for bit: the same kernels on the same values.  Ragged samples
+    (5-11 slabs) in several batches, so segments end at different slabs of
+    different points; every output of the backward sweep, and the adjoint."""
+    _say(f"checkpointed vs full stores, segment={segment} {precision}")
+    wl = make_workload("C4", n_slab=10, n_e=3, n_z=1, n_y=2, n_samples=4)
+    wl.eta = 1e-3
+    wl.v_onsite = np.full((wl.total_slabs, wl.nb), 0.05)
+    assert len(set(np.diff(wl.slab_offset).tolist())) > 1
+    w = torch.from_numpy(np.random.default_rng(12).normal(size=(wl.total_slabs, wl.atoms_per_slab)))
+    res = {}
+    for store in ("full", "checkpoint"):
+        s = _solver(wl, capacity=5, adjoint_segment=segment, store=store,
+                    precision=precision, point_redo=float("inf"))
+        out = s.solve(want_T=True)
+        torch.cuda.synchronize()
+        assert s.status() in (0, 4)          # 4: mixed-precision block fallbacks (same in both)
+        r = {k: v.cpu().numpy() for k, v in out.items()}
+        if precision == "fp64":
+            s.density()
+            r["grad"] = s.density_vjp(w).cpu().numpy()
+        res[store] = r
+    for k in res["full"]:
+        assert np.array_equal(res["full"][k], res["checkpoint"][k]), k

@@ -3,9 +3,10 @@ launch configuration the benchmark times (512-point batches, measured kernel
 shapes): sampled points against the oracle one by one, and properties that
 hold at any size (current conservation with the eta sink, positivity of the
 spectral function and of the occupation, G^> = G^< + G^R - G^A) on every
-point.  The block-1200 device is checked through the adjoint's consistency
-with finite differences of the GPU forward path (its oracle would take minutes
-per point)."""
+point.  The block-1200 device's adjoint is checked against finite
+differences of the GPU forward path here; its forward results against the
+oracle in test_gpu_large_blocks.py."""
+import os
 import sys
 
 import numpy as np
@@ -13,6 +14,7 @@ import pytest
 import torch
 
 import oracle as O
+import parity as P
 from synth import make_workload
 
 pytestmark = pytest.mark.gpu
@@ -65,26 +67,13 @@ def test_block400_70_slabs_bench_configuration():
     jscale = max(np.max(np.abs(bond[:, :N - 1])), 1e-300)
     assert np.max(np.abs(lhs - sink[:, 1:N - 1])) < 1e-8 * jscale
 
-    # three sampled points against the oracle, tolerance from the point's own conditioning
+    # three sampled points against the oracle, tolerances from the points' own FP64 drift
     rng = np.random.default_rng(1510)
     pts = [tuple(int(x) for x in s.points[p]) for p in rng.choice(s.n_points, size=3, replace=False)]
-    idx = [s.index[p] for p in pts]
-    ref = O.solve_points(wl, pts, transmission=True)
-    alt = O.solve_points(wl, pts, variant="alt", transmission=True)
-    d = lambda x: np.diagonal(x, axis1=1, axis2=2)
-    for p, r, a in zip(idx, ref, alt):
-        spread = max(_rel(a[k], r[k]) for k in ("GR", "GL", "GG"))
-        tol = max(1e-10, 100 * spread)   # as in test_gpu_rgf: 100 x the oracle's own drift
-        _say(f"  point {s.points[p].tolist()} tol {tol:.1e}")
-        assert _rel(GR[p], d(r["GR"])) < tol
-        assert _rel(GL[p], d(r["GL"])) < tol
-        assert _rel(GG[p], d(r["GG"])) < tol
-        # the trace sums b * m products of size |H_{i,i+1}| |G^<|: its rounding scales with
-        # |G^<| even where the current itself is exponentially small (E far above mu), so
-        # it is compared on the scale of this point's G^< and of the device's current
-        ref_scale = max(np.max(np.abs(r["bond"])), 1e-3 * np.max(np.abs(d(r["GL"]))), 1e-6 * jscale)
-        assert np.max(np.abs(bond[p, :N - 1] - r["bond"])) < tol * 10 * ref_scale
-        assert abs(T[p] - r["T"]) < tol * max(1.0, abs(r["T"]))
+    ref, tols = P.reference(wl, pts, transmission=True)
+    for pt, r, t in zip(pts, ref, tols):
+        _say(f"  point {list(pt)} tol GR {t['GR']:.1e} GL {t['GL']:.1e} bond {t['bond']:.1e}")
+        P.check_point(out, s.index[pt], pt, r, N, t, T=True)
 
 
 def test_block1200_200_slabs_adjoint_against_gpu_differences():
@@ -159,15 +148,10 @@ def test_block240_120_slabs_scba_graph_configuration():
     _properties(wl, out, counts, s.points)
     rng = np.random.default_rng(240)
     pts = [tuple(int(x) for x in s.points[p]) for p in rng.choice(s.n_points, size=2, replace=False)]
-    ref = O.solve_points(wl, pts)
-    alt = O.solve_points(wl, pts, variant="alt")
-    d = lambda x: np.diagonal(x, axis1=1, axis2=2)
-    for pt, r, a in zip(pts, ref, alt):
-        p = s.index[pt]
-        tol = max(1e-10, 100 * max(_rel(a[k], r[k]) for k in ("GR", "GL")))
-        _say(f"  point {list(pt)} tol {tol:.1e}")
-        assert _rel(out["GR"][p].cpu().numpy(), d(r["GR"])) < tol
-        assert _rel(out["GL"][p].cpu().numpy(), d(r["GL"])) < tol
+    ref, tols = P.reference(wl, pts)
+    for pt, r, t in zip(pts, ref, tols):
+        _say(f"  point {list(pt)} tol GR {t['GR']:.1e} GL {t['GL']:.1e}")
+        P.check_point(out, s.index[pt], pt, r, wl.total_slabs, t)
     del out
     res = {}
     for graph in (True, False):
@@ -182,6 +166,21 @@ def test_block240_120_slabs_scba_graph_configuration():
     sigR, sigL = res[True][2], res[True][3]
     assert np.max(sigR.imag) <= 1e-14 * np.max(np.abs(sigR))
     assert np.min(sigL.imag) >= -1e-14 * np.max(np.abs(sigL))
+    # the second solve of the loop (with the first scattering update) at one point
+    # against the stored oracle chain (tests/golden/make_golden.py scba)
+    sys.path.insert(0, os.path.join(os.path.dirname(__file__), "golden"))
+    from make_golden import inputs_sha1
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "c3_scba.npz"))
+    assert inputs_sha1(wl) == str(g["inputs_sha1"]), "input generator changed: rerun make_golden.py"
+    pt = tuple(int(x) for x in g["point"])
+    p = s.index[pt]
+    for k in ("GR", "GL"):
+        drift = float(g[f"drift_{k}"])
+        tol = max(P.TOL, P.FACTOR * drift)
+        err = P.rel(res[True][0][k][p], g[k])
+        _say(f"  SCBA second solve at {list(pt)}: {k} err {err:.2e} tol {tol:.1e}")
+        P.record(pt, "scba2_" + k, err, tol, drift)
+        assert err < tol, (k, err, tol)
 
 
 def test_block400_ragged_alloy_samples_fp64():
@@ -200,13 +199,8 @@ def test_block400_ragged_alloy_samples_fp64():
     _properties(wl, out, counts, s.points)
     rng = np.random.default_rng(400)
     pts = [tuple(int(x) for x in s.points[p]) for p in rng.choice(s.n_points, size=2, replace=False)]
-    ref = O.solve_points(wl, pts)
-    alt = O.solve_points(wl, pts, variant="alt")
-    d = lambda x: np.diagonal(x, axis1=1, axis2=2)
-    for pt, r, a in zip(pts, ref, alt):
-        p = s.index[pt]
+    ref, tols = P.reference(wl, pts)
+    for pt, r, t in zip(pts, ref, tols):
         N = int(counts[pt[0]])
-        tol = max(1e-10, 100 * max(_rel(a[k], r[k]) for k in ("GR", "GL")))
-        _say(f"  point {list(pt)} ({N} slabs) tol {tol:.1e}")
-        assert _rel(out["GR"][p, :N].cpu().numpy(), d(r["GR"])) < tol
-        assert _rel(out["GL"][p, :N].cpu().numpy(), d(r["GL"])) < tol
+        _say(f"  point {list(pt)} ({N} slabs) tol GR {t['GR']:.1e} GL {t['GL']:.1e}")
+        P.check_point(out, s.index[pt], pt, r, N, t)

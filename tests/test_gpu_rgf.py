@@ -11,8 +11,9 @@ from synth import make_workload, random_tiny
 
 pytestmark = pytest.mark.gpu
 
-TOL = 1e-10   # relative, FP64 path
-SPREAD = 100  # x the oracle's own two-evaluation drift, for points that cannot meet TOL in FP64
+import parity as P
+
+TOL = P.TOL   # relative, FP64 path
 
 
 def _say(msg):
@@ -24,50 +25,20 @@ def _solver(wl, **kw):
     return RGFSolver(wl, **kw)
 
 
-def _rel(a, b):
-    a, b = np.asarray(a), np.asarray(b)
-    return float(np.max(np.abs(a - b)) / max(float(np.max(np.abs(b))), 1e-300))
+_rel = P.rel
 
 
-def _ref_and_tol(wl, pts, **kw):
-    """Oracle results plus a per-point tolerance: 1e-10 relative, or SPREAD x the
-    drift between two correct FP64 evaluations of the point by the oracle itself
-    (default vs alternate association in the lead decimation and the recursion)
-    where that drift is larger -- the point's own conditioning, measured without
-    the GPU.  One pair of evaluations samples the rounding only once, so the
-    factor is wide."""
-    ref = O.solve_points(wl, pts, **kw)
-    alt = O.solve_points(wl, pts, variant="alt", **kw)
-    tols = []
-    for r, a in zip(ref, alt):
-        spread = max(_rel(a[k], r[k]) for k in ("GR", "GL", "GG"))
-        if "T" in r:
-            spread = max(spread, abs(a["T"] - r["T"]) / max(1.0, abs(r["T"])))
-        tols.append(max(TOL, SPREAD * spread))
+def _ref_and_tol(wl, pts, full=False, **kw):
+    """Oracle results plus per-point, per-quantity tolerances: 1e-10 relative, or
+    10 x the point's FP64 drift measured by the oracle alone (tests/parity.py)."""
+    ref, tols = P.reference(wl, pts, full=full, **kw)
+    for t, p in zip(tols, pts):
+        t["point"] = p
     return ref, tols
 
 
-def _check_point(out, p, r, N, full=False, T=False, tol=TOL):
-    gr = out["GR"][p, :N].cpu().numpy()
-    gl = out["GL"][p, :N].cpu().numpy()
-    gg = out["GG"][p, :N].cpu().numpy()
-    if full:
-        rr, rl, rg = r["GR"], r["GL"], r["GG"]
-    else:
-        d = lambda x: np.diagonal(x, axis1=1, axis2=2)
-        rr, rl, rg = d(r["GR"]), d(r["GL"]), d(r["GG"])
-    assert _rel(gr, rr) < tol, ("GR", _rel(gr, rr))
-    assert _rel(gl, rl) < tol, ("GL", _rel(gl, rl))
-    assert _rel(gg, rg) < tol, ("GG", _rel(gg, rg))
-    if N > 1:
-        b = out["bond"][p, :N - 1].cpu().numpy()
-        scale = max(np.max(np.abs(r["bond"])), 1e-300)
-        # bond currents are small differences of O(|G^<|) terms: compare on that scale
-        ref_scale = max(scale, 1e-6 * np.max(np.abs(rl)))
-        assert np.max(np.abs(b - r["bond"])) < tol * 10 * ref_scale, ("bond", b, r["bond"])
-    if T:
-        t = float(out["T"][p])
-        assert abs(t - r["T"]) < tol * max(1.0, abs(r["T"])), ("T", t, r["T"])
+def _check_point(out, p, r, N, full=False, T=False, tol=None):
+    P.check_point(out, p, tol["point"], r, N, tol, full=full, T=T)
 
 
 # ---------------------------------------------------------------------------
@@ -84,14 +55,13 @@ def test_lead_selfenergy_matches_oracle(nb, seed):
     assert s.lead_status == 0
     for ie in range(wl.n_e):
         z = wl.energy[ie] + 1j * wl.eta
-        rL, itL, _ = O.lead_selfenergy(wl.lead_h00[0], wl.lead_h01_L, wl.lead_tau_L, z)
-        rR, itR, _ = O.lead_selfenergy(wl.lead_h00[0], wl.lead_h01_R, wl.lead_tau_R, z)
-        aL, _, _ = O.lead_selfenergy(wl.lead_h00[0], wl.lead_h01_L, wl.lead_tau_L, z, variant="alt")
-        aR, _, _ = O.lead_selfenergy(wl.lead_h00[0], wl.lead_h01_R, wl.lead_tau_R, z, variant="alt")
-        tL = max(TOL, SPREAD * _rel(aL, rL))
-        tR = max(TOL, SPREAD * _rel(aR, rR))
-        assert _rel(sL[0, ie].cpu().numpy(), rL) < tL
-        assert _rel(sR[0, ie].cpu().numpy(), rR) < tR
+        rL, itL, tL, dL = P.lead_reference(wl.lead_h00[0], wl.lead_h01_L, wl.lead_tau_L, z)
+        rR, itR, tR, dR = P.lead_reference(wl.lead_h00[0], wl.lead_h01_R, wl.lead_tau_R, z)
+        eL, eR = _rel(sL[0, ie].cpu().numpy(), rL), _rel(sR[0, ie].cpu().numpy(), rR)
+        P.record((0, 0, ie), "sigma_L", eL, tL, dL)
+        P.record((0, 0, ie), "sigma_R", eR, tR, dR)
+        assert eL < tL
+        assert eR < tR
         assert abs(int(s.iters_L[0, ie]) - itL) <= 1 and abs(int(s.iters_R[0, ie]) - itR) <= 1
 
 
@@ -114,10 +84,9 @@ def test_lead_pair_shared_decimation(complex_h):
             z = wl.energy[ie] + 1j * wl.eta
             for side, h01, tau, got, it, sep in (("L", wl.lead_h01_L, wl.lead_tau_L, sL, itL, qL),
                                                   ("R", wl.lead_h01_R, wl.lead_tau_R, sR, itR, qR)):
-                r, itr, _ = O.lead_selfenergy(wl.lead_h00[ik], h01, tau, z)
-                a, _, _ = O.lead_selfenergy(wl.lead_h00[ik], h01, tau, z, variant="alt")
-                tol = max(TOL, SPREAD * _rel(a, r))
+                r, itr, tol, dr = P.lead_reference(wl.lead_h00[ik], h01, tau, z)
                 g = got[ik, ie].cpu().numpy()
+                P.record((0, ik, ie), "sigma_" + side, _rel(g, r), tol, dr)
                 assert _rel(g, r) < tol, (side, ik, ie, _rel(g, r))
                 assert _rel(g, sep[ik, ie].cpu().numpy()) < tol, (side, "vs separate")
                 assert abs(int(it[ik, ie]) - itr) <= 1, (side, int(it[ik, ie]), itr)
@@ -175,7 +144,8 @@ def test_rgf_matches_oracle_tiny(nb, N, up, seed, full):
     out = s.solve(full_blocks=full, want_T=True, scat_R=dR, scat_L=dL)
     torch.cuda.synchronize()
     assert s.status() == 0
-    ref, tols = _ref_and_tol(wl, [tuple(p) for p in s.points], scatR=scR, scatL=scL, transmission=True)
+    ref, tols = _ref_and_tol(wl, [tuple(p) for p in s.points], full=full, scatR=scR, scatL=scL,
+                             transmission=True)
     for p, r in enumerate(ref):
         _check_point(out, p, r, N, full=full, T=True, tol=tols[p])
 
@@ -223,11 +193,21 @@ def test_rgf_ragged_samples_and_observables():
         _check_point(out, p, r, int(counts[pts[p][0]]), T=True, tol=tols[p])
     GLd = [np.diagonal(r["GL"], axis1=1, axis2=2) for r in ref]
     rn, rJ, rjE = O.observables(wl, pts, GLd, [r["bond"] for r in ref])
-    tol = max(tols)
-    assert _rel(n.cpu().numpy(), rn) < tol
-    assert np.max(np.abs(J.cpu().numpy() - rJ)) < tol * 10 * max(np.max(np.abs(rJ)), 1e-6 * np.max(np.abs(rn)))
-    jg = jE.cpu().numpy()
-    assert np.max(np.abs(jg[:, :, :rjE.shape[2]] - rjE)) < tol * 10 * max(np.max(np.abs(rjE)), 1e-6)
+    # The reductions sum the per-point outputs with weights c_p = g_s w_E w_k: the
+    # per-point bounds just checked bound their errors (plus the reductions' own
+    # rounding, a few ulps of the sums).
+    c = np.array([wl.g_s * wl.w_e[ie] * wl.w_k[ik] for (_, ik, ie) in pts])
+    gl_err = np.array([t["GL"] * np.max(np.abs(np.diagonal(r["GL"], axis1=1, axis2=2))) for t, r in zip(tols, ref)])
+    bd_err = np.array([t["bond"] * P._bond_scale(r) for t, r in zip(tols, ref)])
+    n_bound = np.sum(c * gl_err) * wl.orbs_per_atom / (2 * np.pi) + 1e-14 * np.max(np.abs(rn))
+    J_bound = np.sum(c * bd_err) + 1e-14 * np.max(np.abs(rJ))
+    assert np.max(np.abs(n.cpu().numpy() - rn)) <= n_bound
+    assert np.max(np.abs(J.cpu().numpy() - rJ)) <= J_bound
+    jg = jE.cpu().numpy()[:, :, :rjE.shape[2]]
+    for ie in range(wl.n_e):
+        sel = [q for q, (_, _, e) in enumerate(pts) if e == ie]
+        bound = np.sum((c / wl.w_e[ie])[sel] * bd_err[sel]) + 1e-14 * np.max(np.abs(rjE))
+        assert np.max(np.abs(jg[:, ie] - rjE[:, ie])) <= bound, ie
 
 
 def test_rgf_block400_reduced_length():
