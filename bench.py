@@ -105,6 +105,8 @@ def main():
                     help="mixed precision: redo points whose block-refinement residual exceeds this in FP64 (inf: off)")
     ap.add_argument("--lanes", type=int, default=1,
                     help="batches in flight at once, each on its own context and stream")
+    ap.add_argument("--store", default="full", choices=["full", "checkpoint"],
+                    help="g / g^< of every slab (full) or only at segment ends, recomputed per segment")
     ap.add_argument("--tune", default="auto", choices=["auto", "default"],
                     help="kernel shapes: measured on this GPU before timing (auto) or the library defaults")
     ap.add_argument("--cpu-points", type=int, default=16, help="oracle points at most (about 15 s of host time)")
@@ -141,7 +143,8 @@ def main():
           f"n_k={wl.n_k} n_e={wl.n_e} precision={args.precision}", file=sys.stderr, flush=True)
     adj_seg = -1 if args.workload == "C5" else 0
     solver = RGFSolver(wl, precision=args.precision, capacity=args.capacity, adjoint_segment=adj_seg,
-                       tune="auto" if args.tune == "auto" else None, lanes=args.lanes, point_redo=args.point_redo)
+                       tune="auto" if args.tune == "auto" else None, lanes=args.lanes, point_redo=args.point_redo,
+                       store=args.store)
     print(f"[bench] capacity={solver.capacity} points/batch, workspace "
           f"{sum(N.negf_workspace_bytes(c) for c in solver.ctxs) / 2**30:.1f} GiB", file=sys.stderr, flush=True)
     n_iter = (args.scba_iters or wl.n_scba) if args.workload == "C3" else 1
@@ -248,6 +251,7 @@ def main():
                    "points_per_pass": solver.n_points, "block": wl.nb, "slabs": int(wl.total_slabs),
                    "samples": wl.n_samples, "n_e": wl.n_e, "n_k": wl.n_k,
                    "batch_capacity": solver.capacity, "lanes": solver.lanes, "precision": args.precision,
+                   "store": args.store,
                    "parallelism": "single GPU, batched (sample,k,E) points"},
         "model_tflops": (rgf_f + lead_f) / dt / 1e12,
         "model_flops_per_step": {"rgf": rgf_f / args.steps, "leads": lead_f / args.steps},
@@ -279,17 +283,27 @@ def main():
         res["mixed"] = {"fp64_fallback_inverses": nfb, "max_block_refinement_residual": maxres,
                         "point_redo_bound": solver.point_redo, "points_redone_per_step": solver.points_redone}
     if args.workload == "C5":
-        # adjoint dn/dV: one VJP with a seeded cotangent over all atoms
+        # adjoint dn/dV: one VJP with a seeded cotangent over all atoms, against
+        # the forward RGF it differentiates (density from the stored lead
+        # self-energies: forward and backward sweeps and the reduction, no
+        # lead decimation), timed just before it
         wv = torch.from_numpy(np.random.default_rng(1510046865).normal(
             size=(wl.total_slabs, wl.atoms_per_slab))).cuda()
         torch.cuda.synchronize()
+        tf = time.perf_counter()
+        solver.density()
+        torch.cuda.synchronize()
+        t_rgf = time.perf_counter() - tf
         ta = time.perf_counter()
         g = solver.density_vjp(wv)
         torch.cuda.synchronize()
         t_adj = time.perf_counter() - ta
         t_fwd = dt / args.steps
-        res["adjoint"] = {"ms": t_adj * 1e3, "forward_ms": t_fwd * 1e3, "cost_ratio": t_adj / t_fwd,
-                          "checkpoint_segment": int(np.ceil(np.sqrt(wl.total_slabs))),
+        ws = N.negf_workspace_bytes(solver.ctx)
+        res["adjoint"] = {"ms": t_adj * 1e3, "forward_rgf_ms": t_rgf * 1e3, "cost_ratio": t_adj / t_rgf,
+                          "forward_step_ms": t_fwd * 1e3, "cost_ratio_vs_step_with_leads": t_adj / t_fwd,
+                          "store": args.store, "checkpoint_segment": int(np.ceil(np.sqrt(wl.total_slabs))),
+                          "workspace_bytes_per_point": ws / solver.capacity,
                           "grad_norm": float(torch.linalg.norm(g))}
     if args.workload in ("C2", "C4") and args.precision == "mixed":
         # per-sample density and current error of the mixed path against the FP64

@@ -207,6 +207,22 @@ int negf_rgf_backward(negf_ctx* ctx, void* stream, int p0, int np,
                       int slab_stride, double* bond_j, double* transmission);
 
 /*
+ * negf_rgf_forward followed by negf_rgf_backward for points [p0, p0+np), in
+ * one call (same arguments, outputs and errors as the two).  For blocks of at
+ * most 8 orbitals in FP64 with full stores the whole solve of every point --
+ * forward sweep, backward sweep, bond currents and Caroli T -- runs in ONE
+ * persistent launch: each wavefront takes the next point from a device work
+ * queue (bound order, longest sample first) and keeps that point's blocks in
+ * its registers and LDS.  The g and g^< stores are written as by
+ * negf_rgf_forward, so negf_rgf_adjoint may follow.  Larger blocks, mixed
+ * precision and checkpointed stores run the two calls' batched launches. */
+int negf_rgf_solve(negf_ctx* ctx, void* stream, int p0, int np,
+                   const negf_c128* sigma_L, const negf_c128* sigma_R,
+                   const negf_c128* scat_R, const negf_c128* scat_L, int flags,
+                   negf_c128* GR, negf_c128* GL, negf_c128* GG, int full_blocks,
+                   int slab_stride, double* bond_j, double* transmission);
+
+/*
  * Scattering self-energies of Eqs. (4)-(6) for a bound single-sample system
  * whose points are the full grid in (ik, ie) order (p = ik * n_e + ie):
  *   acoustic: Sigma^{R,<} = D_ac <G^{R,<}(E)>_k

@@ -169,7 +169,7 @@ def _m3(a, b, c, right):
 
 
 def rgf(hd, hu, E, eta, sigL, sigR, fL, fR, v=None, scatR=None, scatL=None,
-        eta_fill=None, transmission=False, assoc_right=False, bond_mag=False):
+        eta_fill=None, transmission=False, assoc_right=False, bond_mag=False, diag_only=False):
     """Diagonal blocks of G^R, G^<, G^> plus bond currents (and optionally the
     Caroli transmission) of one (sample, k, E) point by recursive Green's
     functions.
@@ -198,7 +198,10 @@ def rgf(hd, hu, E, eta, sigL, sigR, fL, fR, v=None, scatR=None, scatL=None,
     ``bond_mag`` also returns, per bond, the sum of magnitudes of the terms the
     bond trace adds, 2 Tr[|H_{i,i+1}| (|G_{i+1}| |H_{i+1,i}| |g^<_i| + |G^<_{i+1}| |L|^T)]
     (|X| elementwise): the scale on which any FP64 evaluation of the trace, in
-    any order, rounds (test tolerances only; no result depends on it)."""
+    any order, rounds (test tolerances only; no result depends on it).
+    ``diag_only`` returns GR, GL, GG as orbital diagonals [N, b] and lets each
+    block go once the backward sweep has used it (the same arithmetic, less
+    memory for long devices with large blocks)."""
     N = len(hd)
     ar = assoc_right
     b = hd[0].shape[0]
@@ -233,6 +236,19 @@ def rgf(hd, hu, E, eta, sigL, sigR, fL, fR, v=None, scatR=None, scatL=None,
         if bond_mag:
             a = np.abs
             mag[i] = 2.0 * np.trace(a(hu[i]) @ (a(GR[i + 1]) @ a(hr) @ a(gl[i]) + a(GL[i + 1]) @ a(L).T))
+        if diag_only and not transmission:
+            GR[i + 1] = np.diagonal(GR[i + 1]).copy()
+            GL[i + 1] = np.diagonal(GL[i + 1]).copy()
+            g[i + 1] = gl[i + 1] = None
+    if diag_only and not transmission:
+        GR[0] = np.diagonal(GR[0]).copy()
+        GL[0] = np.diagonal(GL[0]).copy()
+        GR = np.array(GR)
+        GL = np.array(GL)
+        out = dict(GR=GR, GL=GL, GG=GL + GR - np.conj(GR), bond=bond)
+        if bond_mag:
+            out["bond_mag"] = mag
+        return out
     GR = np.array(GR)
     GL = np.array(GL)
     GG = GL + GR - np.conj(np.transpose(GR, (0, 2, 1)))
@@ -346,7 +362,7 @@ def lead_tables(wl, tol=1e-14, max_iter=100, ks=None, es=None, variant=None):
 
 
 def solve_points(wl, points, leads=None, scatR=None, scatL=None, transmission=False, eta_fill=None,
-                 variant=None, bond_mag=False):
+                 variant=None, bond_mag=False, diag_only=False):
     """RGF for a list of (sample, ik, ie) points.  scatR/scatL: [n_e, total_slabs, b].
     variant="alt": the reproducibility estimate, with the lead decimation and every
     triple product of the recursion associated the other way."""
@@ -366,7 +382,7 @@ def solve_points(wl, points, leads=None, scatR=None, scatL=None, transmission=Fa
         ef = None if eta_fill is None else float(fermi(E, eta_fill, wl.kT))
         res.append(rgf(hd, hu, E, wl.eta, sL, sR, fL, fR, v=v, scatR=sr, scatL=sl,
                        transmission=transmission, eta_fill=ef, assoc_right=(variant == "alt"),
-                       bond_mag=bond_mag))
+                       bond_mag=bond_mag, diag_only=diag_only))
     return res
 
 

@@ -60,6 +60,7 @@ struct negf_ctx {
     double* sr_ref2 = nullptr;    // dual surface reference norms
     double* dual_partial = nullptr;
     int* d_count = nullptr;
+    int* queue = nullptr;         // work-queue counter of the one-launch small-block solve
     int* status = nullptr;
     double* ns_res = nullptr;     // [cap] largest refinement residual of each point in the last forward sweep
     int* ns_flag = nullptr;       // [cap] fallback flag per point
@@ -386,6 +387,7 @@ int negf_create(const negf_config* cfg, negf_ctx** out) {
          dev_alloc(c, &c->sr_ref2, cap * sizeof(double), c->allocs) &&
          dev_alloc(c, &c->dual_partial, 2 * DUAL_NBLK * sizeof(double), c->allocs) &&
          dev_alloc(c, &c->d_count, 4 * sizeof(int), c->allocs) &&
+         dev_alloc(c, &c->queue, 4 * sizeof(int), c->allocs) &&
          dev_alloc(c, &c->status, 4 * sizeof(int), c->allocs) &&
          dev_alloc(c, &c->ns_res, cap * sizeof(double), c->allocs) &&
          dev_alloc(c, &c->ns_flag, cap * sizeof(int), c->allocs) &&
@@ -898,6 +900,70 @@ int negf_rgf_backward(negf_ctx* c, void* stream, int p0, int np, negf_c128* GR, 
         hipLaunchKernelGGL(copy_d_kernel, dim3((np + 255) / 256), dim3(256), 0, s, c->trans_d + p0, transmission + p0, np);
         NEGF_HIP_CHECK(hipGetLastError());
     }
+    return NEGF_OK;
+}
+
+int negf_rgf_solve(negf_ctx* c, void* stream, int p0, int np, const negf_c128* sigma_L, const negf_c128* sigma_R,
+                   const negf_c128* scat_R, const negf_c128* scat_L, int flags, negf_c128* GR, negf_c128* GL,
+                   negf_c128* GG, int full_blocks, int slab_stride, double* bond_j, double* transmission) {
+    if (!c) return NEGF_EINVAL;
+    if (!c->bound) return NEGF_ESTATE;
+    if (!sigma_L || !sigma_R || p0 < 0 || np < 1 || p0 + np > c->n_points) return NEGF_EINVAL;
+    if (np > c->cap) return NEGF_ESHAPE;
+    if ((scat_R == nullptr) != (scat_L == nullptr)) return NEGF_EINVAL;
+    if (transmission && !(flags & NEGF_WANT_TRANSMISSION)) return NEGF_ESTATE;
+    int maxN = 0;
+    for (int q = 0; q < np; ++q) maxN = std::max(maxN, c->desc_h[p0 + q].w);
+    if (slab_stride < maxN) return NEGF_EINVAL;
+    const bool fused = c->nb <= SMALL_NMAX && c->prec == NEGF_FP64 && !c->ckpt;
+    if (!fused) {
+        const int st = negf_rgf_forward(c, stream, p0, np, sigma_L, sigma_R, scat_R, scat_L, flags);
+        if (st != NEGF_OK) return st;
+        return negf_rgf_backward(c, stream, p0, np, GR, GL, GG, full_blocks, slab_stride, bond_j, transmission);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const negf_system& S = c->sys;
+    SmallArgs a{};
+    a.hdiag = reinterpret_cast<const double2*>(S.h_diag);
+    a.hdiag_k = c->soff_h.back() * (long long)c->nb * c->nb;
+    a.hup = reinterpret_cast<const double2*>(S.h_up);
+    a.hup_k = S.h_up_k_stride;
+    a.ub = S.up_block;
+    a.v = S.v_onsite;
+    a.scatR = reinterpret_cast<const double2*>(scat_R);
+    a.scatL = reinterpret_cast<const double2*>(scat_L);
+    a.total = c->soff_h.back();
+    a.sigL = reinterpret_cast<const double2*>(sigma_L);
+    a.sigR = reinterpret_cast<const double2*>(sigma_R);
+    a.n_e = S.n_e;
+    a.energy = S.energy; a.eta = S.eta; a.muL = S.mu_L; a.muR = S.mu_R; a.kT = S.kT; a.eta_fill = S.eta_fill;
+    a.ps = PointSet{c->desc_d, c->soff_d, p0};
+    a.np = np; a.n = c->nb;
+    a.outR = reinterpret_cast<double2*>(GR); a.outL = reinterpret_cast<double2*>(GL);
+    a.outG = reinterpret_cast<double2*>(GG);
+    a.full = full_blocks ? 1 : 0; a.slab_stride = slab_stride;
+    a.bond = bond_j;
+    a.trans = (flags & NEGF_WANT_TRANSMISSION) ? c->trans_d : nullptr;
+    a.gst = static_cast<double2*>(c->gst); a.glst = static_cast<double2*>(c->glst); a.sst = store_stride(c);
+    a.queue = c->queue;
+    a.status = c->status;
+    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, s, c->queue, 0, 1);
+    NEGF_HIP_CHECK(hipGetLastError());
+    // persistent: enough wavefronts to fill every CU a few times over, each
+    // pulling points until the queue is drained
+    NEGF_HIP_CHECK(small_launch(s, a, std::min(np, 256 * 8)));
+    if (transmission) {
+        hipLaunchKernelGGL(copy_d_kernel, dim3((np + 255) / 256), dim3(256), 0, s, c->trans_d + p0, transmission + p0,
+                           np);
+        NEGF_HIP_CHECK(hipGetLastError());
+    }
+    c->fwd_done = true;
+    c->fwd_p0 = p0;
+    c->fwd_np = np;
+    c->fwd_maxN = maxN;
+    c->fwd_flags = flags;
+    c->fwd_sL = a.sigL; c->fwd_sR = a.sigR; c->fwd_scR = a.scatR; c->fwd_scL = a.scatL;
+    c->seg_loaded = -1;
     return NEGF_OK;
 }
 

@@ -59,6 +59,27 @@ struct SrArgs {
     int n, n_e, np;
 };
 
+// Whole-point RGF for blocks of at most 8 orbitals (one wavefront per point,
+// points pulled from a device work queue).
+constexpr int SMALL_NMAX = 8;
+struct SmallArgs {
+    const double2* hdiag; long long hdiag_k;   // [n_k][total][n][n]
+    const double2* hup; long long hup_k; int ub;
+    const double* v;                           // [total][n] or NULL
+    const double2* scatR; const double2* scatL;   // [n_e][total][n] or NULL
+    long long total;
+    const double2* sigL; const double2* sigR; int n_e;
+    const double* energy; double eta, muL, muR, kT; int eta_fill;
+    PointSet ps; int np, n;
+    double2* outR; double2* outL; double2* outG; int full, slab_stride;
+    double* bond;                              // [p][slab_stride] or NULL
+    double* trans;                             // [p] or NULL (no transmission)
+    double2* gst; double2* glst; long long sst;   // per-point stores of g, g^< (for the adjoint)
+    int* queue;                                // work-queue counter, zero at launch
+    int* status;
+};
+hipError_t small_launch(hipStream_t s, const SmallArgs& a, int grid);
+
 struct ScbaArgs {
     const double2* GR; const double2* GL;     // [n_k][n_e][slab_stride][n]
     const double* w_k;

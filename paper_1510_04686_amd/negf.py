@@ -58,7 +58,7 @@ EXPORTS = [
     "negf_bind", "negf_lead_selfenergy", "negf_lead_selfenergy_pair", "negf_rgf_forward", "negf_rgf_backward",
     "negf_scba_selfenergy", "negf_observables", "negf_rgf_adjoint", "negf_zgemm_batched", "negf_zinv_batched", "negf_mixed_stats",
     "negf_set_mixed_threshold", "negf_mixed_point_residuals", "negf_gemm_timing_enable", "negf_gemm_timing", "negf_get_tuning", "negf_set_tuning", "negf_autotune",
-    "negf_build_id", "negf_scba_history",
+    "negf_build_id", "negf_scba_history", "negf_rgf_solve",
 ]
 
 
@@ -88,6 +88,7 @@ def lib():
         "negf_lead_selfenergy_pair": (i, [vp, vp, i, vp, vp, vp, vp, vp, i, vp, d, d, i, vp, vp, vp, vp, vp]),
         "negf_rgf_forward": (i, [vp, vp, i, i, vp, vp, vp, vp, i]),
         "negf_rgf_backward": (i, [vp, vp, i, i, vp, vp, vp, i, i, vp, vp]),
+        "negf_rgf_solve": (i, [vp, vp, i, i, vp, vp, vp, vp, i, vp, vp, vp, i, i, vp, vp]),
         "negf_scba_selfenergy": (i, [vp, vp, vp, vp, i, vp, d, d, i, d, vp, vp, vp]),
         "negf_observables": (i, [vp, vp, vp, vp, i, vp, vp, d, i, vp, vp, vp]),
         "negf_scba_history": (i, [vp, vp, POINTER(d), i, POINTER(i)]),
@@ -237,6 +238,19 @@ def negf_scba_selfenergy(ctx, GR, GL, slab_stride, w_k, D_ac, M_op, shift, n_bos
         _ptr(sig_R, torch.complex128, "sig_R"), _ptr(sig_L, torch.complex128, "sig_L"),
         _ptr(rel_change, torch.float64, "rel_change"))
     _check("negf_scba_selfenergy", code)
+
+
+def negf_rgf_solve(ctx, p0, np_, sigma_L, sigma_R, scat_R=None, scat_L=None, flags=0, GR=None, GL=None, GG=None,
+                   full_blocks=0, slab_stride=1, bond_j=None, transmission=None, stream=None):
+    """negf_rgf_forward + negf_rgf_backward in one call (one persistent launch
+    for blocks of at most 8 orbitals)."""
+    code = lib().negf_rgf_solve(
+        ctx.handle, _stream(stream), int(p0), int(np_), _ptr(sigma_L, torch.complex128, "sigma_L"),
+        _ptr(sigma_R, torch.complex128, "sigma_R"), _ptr(scat_R, torch.complex128, "scat_R"),
+        _ptr(scat_L, torch.complex128, "scat_L"), int(flags), _ptr(GR, torch.complex128, "GR"),
+        _ptr(GL, torch.complex128, "GL"), _ptr(GG, torch.complex128, "GG"), int(full_blocks), int(slab_stride),
+        _ptr(bond_j, torch.float64, "bond_j"), _ptr(transmission, torch.float64, "transmission"))
+    _check("negf_rgf_solve", code)
 
 
 def negf_scba_history(ctx, max_n=4096, stream=None):

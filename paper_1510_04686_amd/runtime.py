@@ -237,12 +237,12 @@ class RGFSolver:
         """Forward + backward sweep of one batch of bound points on the first
         lane's context (the mixed-precision point redo is not applied)."""
         flags = N.NEGF_WANT_TRANSMISSION if want_T else 0
-        N.negf_rgf_forward(self.ctx, p0, np_, self.sigma_L, self.sigma_R, scat_R, scat_L, flags, stream=stream)
+        N.negf_rgf_solve(self.ctx, p0, np_, self.sigma_L, self.sigma_R, scat_R, scat_L, flags, out.get("GR"),
+                         out.get("GL"), out.get("GG"), int(full_blocks), self.slab_stride, out.get("bond"),
+                         out.get("T"), stream=stream)
         self._last_fwd = (p0, np_)
         if self.resid is not None:
             N.negf_mixed_point_residuals(self.ctx, self.resid[p0:p0 + np_], stream=stream)
-        N.negf_rgf_backward(self.ctx, p0, np_, out.get("GR"), out.get("GL"), out.get("GG"),
-                            int(full_blocks), self.slab_stride, out.get("bond"), out.get("T"), stream=stream)
 
     def run_batches(self, out, full_blocks=False, want_T=False, scat_R=None, scat_L=None, stream=None):
         flags = N.NEGF_WANT_TRANSMISSION if want_T else 0
@@ -255,13 +255,13 @@ class RGFSolver:
             lane = b % self.lanes
             ctx = self.ctxs[lane]
             st = base if self.lanes == 1 else self.streams[lane]
-            N.negf_rgf_forward(ctx, p0, np_, self.sigma_L, self.sigma_R, scat_R, scat_L, flags, stream=st)
+            N.negf_rgf_solve(ctx, p0, np_, self.sigma_L, self.sigma_R, scat_R, scat_L, flags, out.get("GR"),
+                             out.get("GL"), out.get("GG"), int(full_blocks), self.slab_stride, out.get("bond"),
+                             out.get("T"), stream=st)
             if lane == 0:
                 self._last_fwd = (p0, np_)
             if self.resid is not None:
                 N.negf_mixed_point_residuals(ctx, self.resid[p0:p0 + np_], stream=st)
-            N.negf_rgf_backward(ctx, p0, np_, out.get("GR"), out.get("GL"), out.get("GG"),
-                                int(full_blocks), self.slab_stride, out.get("bond"), out.get("T"), stream=st)
         if self.lanes > 1:
             for ls in self.streams:          # join
                 base.wait_stream(ls)

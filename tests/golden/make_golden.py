@@ -22,8 +22,7 @@ inputs so a test can tell when the generator has changed since:
   self-energy update, and the solve with it; orbital diagonals of G^R and G^<
   and their drifts.
 
-The full case takes tens of minutes and ~30 GB of host memory (the oracle keeps
-every block).
+The full case takes tens of minutes and ~20 GB of host memory.
 """
 from __future__ import annotations
 
@@ -87,9 +86,8 @@ def full_case():
     res = {}
     for name, w, var, seed in variants:
         leads = None if seed is None else P.perturbed_leads(wl, pts, seed, w)
-        r = O.solve_points(w, pts, variant=var, leads=leads)[0]
-        GLd = np.diagonal(r["GL"], axis1=1, axis2=2)
-        GRd = np.diagonal(r["GR"], axis1=1, axis2=2)
+        r = O.solve_points(w, pts, variant=var, leads=leads, diag_only=True)[0]
+        GLd, GRd = r["GL"], r["GR"]
         n, _, _ = O.observables(wl, pts, [GLd], [r["bond"]])
         res[name] = {"n": n, "GR": GRd[list(FULL_SLABS)].copy(), "GL": GLd[list(FULL_SLABS)].copy()}
         del r, GLd, GRd

@@ -500,3 +500,17 @@ def test_scba_optical_empty_level_continued_fraction():
     for j in range(len(E)):
         Gc[j] = 1.0 / (E[j] + 1j * eta - eps - (M * Gc[j - s] if j >= s else 0.0))
     assert np.max(np.abs(G - Gc)) < 1e-13 * np.max(np.abs(Gc))
+
+
+def test_rgf_diag_only_keeps_the_same_arithmetic():
+    """The memory-lean mode returns exactly the orbital diagonals and bond
+    currents of the full-block mode (it only drops blocks after use)."""
+    wl = random_tiny(6, 5, n_e=2, seed=21, up_block=3, eta=1e-3)
+    hd, hu, _ = wl.sample_blocks(0, 0)
+    E = float(wl.energy[0])
+    sL, sR = _leads(wl, 0, E)
+    a = O.rgf(hd, hu, E, wl.eta, sL, sR, 0.7, 0.2, bond_mag=True)
+    b = O.rgf(hd, hu, E, wl.eta, sL, sR, 0.7, 0.2, bond_mag=True, diag_only=True)
+    for k in ("GR", "GL", "GG"):
+        assert np.array_equal(np.diagonal(a[k], axis1=1, axis2=2), b[k]), k
+    assert np.array_equal(a["bond"], b["bond"]) and np.array_equal(a["bond_mag"], b["bond_mag"])
