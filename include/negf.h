@@ -303,6 +303,34 @@ int negf_zgemm_batched(negf_ctx* ctx, void* stream, int n, int batch, int opa, i
                        const void* A, const void* B, void* C, int dtype);
 int negf_zinv_batched(negf_ctx* ctx, void* stream, int n, int batch, void* A, void* Ainv, int dtype);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * negf_zinv_batched without a context.  Its scratch (the matrices' ping-pong
+ * partner, the panel transform, the pivot rows and the row and column maps)
+ * lives in one device array of NEGF_NOALLOC_SCRATCH_BYTES inside the library,
+ * one copy per GPU, held until the process ends.  The call allocates nothing
+ * and frees nothing; it looks the array's address up once per device (on the
+ * first call with that device current).
+ *   n, batch, A, Ainv, dtype   as negf_zinv_batched (A is overwritten); the
+ *                              one-level Gauss-Jordan scheme is used (bitwise
+ *                              the result of negf_zinv_batched with
+ *                              inv_outer = 0)
+ *   status  DEVICE int or NULL: zero/non-finite pivots OR the NEGF status bits
+ *           (1 singular, 2 non-finite) into it; the caller clears it.
+ * Requires negf_zinv_noalloc_bytes(n, batch, dtype) <= NEGF_NOALLOC_SCRATCH_BYTES
+ * (n = 400: up to 22 points in FP64, 45 in FP32; n = 1200: 2 and 5), else
+ * NEGF_ESHAPE; n <= 2048.
+ * All calls on one GPU share its array: calls that overlap in time on one GPU
+ * (different streams or host threads) race and give wrong results.  The
+ * array holds the last call's contents; every byte a call reads was written
+ * by that call.
+ * Errors: NEGF_EINVAL, NEGF_ESHAPE, NEGF_EHIP.
+ */
+#define NEGF_NOALLOC_SCRATCH_BYTES (64ll << 20)
+long long negf_zinv_noalloc_bytes(int n, int batch, int dtype);   /* -1 for bad arguments */
+int negf_zinv_batched_noalloc(void* stream, int n, int batch, void* A, void* Ainv, int dtype, int* status);
+
 /* Mixed-precision diagnostics of the last forward sweeps since the previous call:
  * number of block inverses redone in FP64 and the largest refinement residual
  * ||I - A X0||_F seen (host outputs; synchronises `stream`). */

@@ -58,7 +58,7 @@ EXPORTS = [
     "negf_bind", "negf_lead_selfenergy", "negf_lead_selfenergy_pair", "negf_rgf_forward", "negf_rgf_backward",
     "negf_scba_selfenergy", "negf_observables", "negf_rgf_adjoint", "negf_zgemm_batched", "negf_zinv_batched", "negf_mixed_stats",
     "negf_set_mixed_threshold", "negf_mixed_point_residuals", "negf_gemm_timing_enable", "negf_gemm_timing", "negf_get_tuning", "negf_set_tuning", "negf_autotune",
-    "negf_build_id", "negf_scba_history", "negf_rgf_solve",
+    "negf_build_id", "negf_scba_history", "negf_rgf_solve", "negf_zinv_noalloc_bytes", "negf_zinv_batched_noalloc",
 ]
 
 
@@ -95,6 +95,8 @@ def lib():
         "negf_rgf_adjoint": (i, [vp, vp, i, i, vp, vp, i]),
         "negf_zgemm_batched": (i, [vp, vp, i, i, i, i, vp, vp, vp, i]),
         "negf_zinv_batched": (i, [vp, vp, i, i, vp, vp, i]),
+        "negf_zinv_noalloc_bytes": (ll, [i, i, i]),
+        "negf_zinv_batched_noalloc": (i, [vp, i, i, vp, vp, i, vp]),
         "negf_mixed_stats": (i, [vp, vp, POINTER(ll), POINTER(d)]),
         "negf_set_mixed_threshold": (i, [vp, d]),
         "negf_mixed_point_residuals": (i, [vp, vp, i, vp]),
@@ -304,6 +306,24 @@ def negf_zinv_batched(ctx, A, Ainv, stream=None):
     code = lib().negf_zinv_batched(ctx.handle, _stream(stream), int(n), int(batch), _ptr(A, dt, "A"),
                                    _ptr(Ainv, dt, "Ainv"), _cdt(A))
     _check("negf_zinv_batched", code)
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20   # NEGF_NOALLOC_SCRATCH_BYTES
+
+
+def negf_zinv_noalloc_bytes(n, batch, dtype=torch.complex128):
+    return int(lib().negf_zinv_noalloc_bytes(int(n), int(batch), _cdt(torch.empty(0, dtype=dtype))))
+
+
+def negf_zinv_batched_noalloc(A, Ainv, status=None, stream=None):
+    """Ainv[b] = A[b]^-1 without a context: scratch in the library's static
+    device array (no allocation).  `status` (device int32 tensor of one element
+    or None) receives the OR of the pivot status bits."""
+    batch, n = A.shape[0], A.shape[-1]
+    dt = A.dtype
+    code = lib().negf_zinv_batched_noalloc(_stream(stream), int(n), int(batch), _ptr(A, dt, "A"),
+                                           _ptr(Ainv, dt, "Ainv"), _cdt(A), _ptr(status, torch.int32, "status"))
+    _check("negf_zinv_batched_noalloc", code)
 
 
 def negf_mixed_stats(ctx, stream=None):
