@@ -523,6 +523,26 @@ static int lead_sr(negf_ctx* c, hipStream_t s, int n_k, const negf_c128* h00, co
     const long long total = (long long)n_k * n_e;
     const GemmTypes T64{DT_C128, DT_C128, DT_C128, DT_C128};
     const bool dual = sigma2 != nullptr;
+    if (n <= SMALL_NMAX && total <= (1ll << 30)) {
+        // small leads: every (k, E) point decimated to convergence in one launch
+        SrSmallArgs a{};
+        a.h00 = reinterpret_cast<const double2*>(h00);
+        a.h01 = reinterpret_cast<const double2*>(h01);
+        a.tau = reinterpret_cast<const double2*>(tau);
+        a.tau2 = reinterpret_cast<const double2*>(tau2);
+        a.energy = energy; a.eta = eta; a.tol = tol; a.max_iter = max_iter;
+        a.n = n; a.n_e = n_e; a.total = (int)total;
+        a.sigma = reinterpret_cast<double2*>(sigma);
+        a.sigma2 = reinterpret_cast<double2*>(sigma2);
+        a.iters = iters; a.iters2 = iters2;
+        a.queue = c->queue; a.noconv = c->queue + 1; a.status = c->status;
+        hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, s, c->queue, 0, 2);
+        NEGF_HIP_CHECK(hipGetLastError());
+        NEGF_HIP_CHECK(sr_small_launch(s, a, (int)std::min<long long>(total, 256 * 8)));
+        NEGF_HIP_CHECK(hipMemcpyAsync(c->h_pinned, c->queue + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+        NEGF_HIP_CHECK(hipStreamSynchronize(s));
+        return c->h_pinned[0] > 0 ? NEGF_WNOCONV : NEGF_OK;
+    }
     bool noconv = false;
     for (long long f0 = 0; f0 < total; f0 += c->cap) {
         const int cnt = (int)std::min<long long>(c->cap, total - f0);

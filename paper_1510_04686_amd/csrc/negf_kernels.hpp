@@ -80,6 +80,19 @@ struct SmallArgs {
 };
 hipError_t small_launch(hipStream_t s, const SmallArgs& a, int grid);
 
+// Sancho-Rubio of one (k, E) point per wavefront for leads of at most 8
+// orbitals, over the whole grid f = ik * n_e + ie < total in one launch.
+struct SrSmallArgs {
+    const double2* h00; const double2* h01; const double2* tau;   // [n_k][n][n]
+    const double2* tau2;                        // dual surface's coupling, or NULL
+    const double* energy; double eta, tol; int max_iter;
+    int n, n_e, total;
+    double2* sigma; double2* sigma2;            // [total][n][n] (sigma2 NULL: one surface)
+    int* iters; int* iters2;                    // [total] or NULL
+    int* queue; int* noconv; int* status;
+};
+hipError_t sr_small_launch(hipStream_t s, const SrSmallArgs& a, int grid);
+
 struct ScbaArgs {
     const double2* GR; const double2* GL;     // [n_k][n_e][slab_stride][n]
     const double* w_k;

@@ -27,7 +27,6 @@ struct Lds {
     double2 a[SL];
     double2 b[SL];
     int perm[SB];
-    int q;
     int bad;
 };
 
@@ -77,6 +76,20 @@ __device__ inline double2 anti_herm(Lds& s, int lane, double2 x) {
     return make_double2(0.5 * (x.x - t.x), 0.5 * (x.y + t.y));
 }
 
+// Next work item of the queue, wave-uniform: every lane takes part in the
+// atomic (lane 0 adds 1, the others 0) and the value lane 0 got is read back
+// as a scalar.  No lane-dependent branch may sit in a persistent loop whose
+// lanes must stay together: with a branch that only lane 0 takes (the
+// atomic, a store of a per-point result) the compiler, which drops the
+// barriers of a one-wave workgroup, was free to split the loop so that lanes
+// 1-63 went round again without lane 0 -- and without its next atomic: a loop
+// that never ended.  Per-point results are therefore stored by every lane
+// (the same value to the same address).
+__device__ inline int next_item(int* queue, int lane) {
+    const int v = atomicAdd(queue, lane == 0 ? 1 : 0);
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
 // Wavefront sum (every lane gets it).
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -98,10 +111,8 @@ __device__ __noinline__ double2 inv8(Lds& s, int lane, double2 m) {
             const double mg = fabs(v.x) + fabs(v.y);
             if (mg > best) { best = mg; p = i; }
         }
-        if (lane == 0) {
-            s.perm[k] = p;
-            if (!(best > 0.0)) s.bad |= (best == 0.0) ? ST_SINGULAR : ST_NONFINITE;
-        }
+        s.perm[k] = p;                        // every lane writes the same value
+        if (!(best > 0.0)) s.bad |= (best == 0.0) ? ST_SINGULAR : ST_NONFINITE;
         double2 x = s.a[lane];
         if (p != k) {
             if (r == k) x = s.a[p * SB + c];
@@ -149,12 +160,9 @@ __global__ __launch_bounds__(SL) void rgf_small_kernel(SmallArgs a) {
     const int n = a.n;
     const bool in = r < n && c < n;
     const long long nn = (long long)n * n;
-    if (lane == 0) s.bad = 0;
+    s.bad = 0;
     for (;;) {
-        if (lane == 0) s.q = atomicAdd(a.queue, 1);
-        __syncthreads();
-        const int q = s.q;
-        __syncthreads();
+        const int q = next_item(a.queue, lane);
         if (q >= a.np) break;
         const int p = a.ps.p0 + q;
         const int4 d = a.ps.desc[p];
@@ -235,7 +243,7 @@ __global__ __launch_bounds__(SL) void rgf_small_kernel(SmallArgs a) {
                 const double2 Y = mm(s, lane, G, Q, false, false) + mm(s, lane, GL, L, false, true);
                 const double2 Yt = transposed(s, lane, Y);
                 const double j = 2.0 * wave_sum(u.x * Yt.x - u.y * Yt.y);
-                if (lane == 0 && a.bond) a.bond[(long long)p * a.slab_stride + i] = j;
+                if (a.bond) a.bond[(long long)p * a.slab_stride + i] = j;     // same value from every lane
                 const double2 Tt = transposed(s, lane, T);
                 G = gi + mm(s, lane, P, R, false, false);
                 GL = anti_herm(s, lane, gli + mm(s, lane, W, L, false, true) + T -
@@ -262,11 +270,103 @@ __global__ __launch_bounds__(SL) void rgf_small_kernel(SmallArgs a) {
             const double2 X2 = mm(s, lane, gamL, C, false, true);
             const double2 X2t = transposed(s, lane, X2);
             const double t = wave_sum(X1.x * X2t.x - X1.y * X2t.y);
-            if (lane == 0) a.trans[p] = t;
+            a.trans[p] = t;                                               // same value from every lane
         }
     }
     __syncthreads();
     if (lane == 0 && s.bad) raise_status(a.status, s.bad);
+}
+
+// Matrix 1-norm (largest column sum of |x|) and infinity norm (largest row
+// sum) of the block whose element (l / 8, l % 8) lane l holds.
+__device__ inline double norm1_8(double2 x) {
+    double v = hypot(x.x, x.y);
+#pragma unroll
+    for (int o = 8; o < SL; o <<= 1) v += __shfl_xor(v, o);     // column sums
+#pragma unroll
+    for (int o = 1; o < SB; o <<= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ inline double norminf_8(double2 x) {
+    double v = hypot(x.x, x.y);
+#pragma unroll
+    for (int o = 1; o < SB; o <<= 1) v += __shfl_xor(v, o);     // row sums
+#pragma unroll
+    for (int o = 8; o < SL; o <<= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+
+// Sancho-Rubio decimation of one (k, E) point per wavefront, iterated to
+// convergence inside the kernel (no host round trip per decimation step):
+// the same steps and stopping rule as the batched lead path.
+__global__ __launch_bounds__(SL) void sr_small_kernel(SrSmallArgs a) {
+    __shared__ Lds s;
+    const int lane = threadIdx.x;
+    const int r = lane >> 3, c = lane & 7;
+    const int n = a.n;
+    const bool in = r < n && c < n;
+    const long long nn = (long long)n * n;
+    const double2 zero = make_double2(0.0, 0.0);
+    const bool dual = a.sigma2 != nullptr;
+    s.bad = 0;
+    for (;;) {
+        const int f = next_item(a.queue, lane);
+        if (f >= a.total) break;
+        const int ik = f / a.n_e, ie = f - ik * a.n_e;
+        const double E = a.energy[ie];
+        const long long kb = (long long)ik * nn;
+        const double2 h = in ? a.h00[kb + r * n + c] : zero;
+        const double2 h01 = in ? a.h01[kb + r * n + c] : zero;
+        const double2 h01t = in ? a.h01[kb + c * n + r] : zero;
+        double2 eps_s = h, eps = h, eps_d = h;
+        double2 al = h01, be = cconj(h01t);
+        const double ref = norm1_8(h01), ref2 = norm1_8(cconj(h01t));   // ||h01||_1, ||h01^dagger||_1
+        auto zminus = [&](double2 x) -> double2 {   // z I - x (identity on the padding)
+            if (!in) return make_double2(r == c ? 1.0 : 0.0, 0.0);
+            double2 m = make_double2(-x.x, -x.y);
+            if (r == c) { m.x += E; m.y += a.eta; }
+            return m;
+        };
+        int it1 = 0, it2 = 0;
+        bool done = false;
+        for (int it = 1; it <= a.max_iter && !done; ++it) {
+            const double2 g = inv8(s, lane, zminus(eps));
+            const double2 X1 = mm(s, lane, al, g, false, false);
+            const double2 X2 = mm(s, lane, be, g, false, false);
+            const double2 t1 = mm(s, lane, X1, be, false, false);
+            eps_s = eps_s + t1;
+            eps = eps + t1;
+            const double2 t2 = mm(s, lane, X2, al, false, false);
+            if (dual) eps_d = eps_d + t2;
+            eps = eps + t2;
+            const double2 al2 = mm(s, lane, X1, al, false, false);
+            be = mm(s, lane, X2, be, false, false);
+            al = al2;
+            const double sum = norm1_8(al) + norm1_8(be);
+            if (it1 >= 0) it1 = sum < a.tol * ref ? -it : it;
+            if (dual && it2 >= 0) it2 = sum < a.tol * ref2 ? -it : it;
+            done = __builtin_amdgcn_readfirstlane((int)(it1 < 0 && (!dual || it2 < 0))) != 0;
+        }
+        atomicAdd(a.noconv, (!done && lane == 0) ? 1 : 0);
+        // Sigma = tau (z - eps_s)^-1 tau^dagger (and the dual surface's)
+        for (int side = 0; side < (dual ? 2 : 1); ++side) {
+            const double2* tin = side ? a.tau2 : a.tau;
+            const double2 t = in ? tin[kb + r * n + c] : zero;
+            const double2 gs = inv8(s, lane, zminus(side ? eps_d : eps_s));
+            const double2 sig = mm(s, lane, mm(s, lane, t, gs, false, false), t, false, true);
+            double2* out = side ? a.sigma2 : a.sigma;
+            if (in) out[(long long)f * nn + r * n + c] = sig;
+        }
+        if (a.iters) a.iters[f] = it1 < 0 ? -it1 : it1;                    // same value from every lane
+        if (dual && a.iters2) a.iters2[f] = it2 < 0 ? -it2 : it2;
+    }
+    __syncthreads();
+    if (lane == 0 && s.bad) raise_status(a.status, s.bad);
+}
+
+hipError_t sr_small_launch(hipStream_t st, const SrSmallArgs& a, int grid) {
+    hipLaunchKernelGGL(sr_small_kernel, dim3(grid), dim3(SL), 0, st, a);
+    return hipGetLastError();
 }
 
 hipError_t small_launch(hipStream_t st, const SmallArgs& a, int grid) {

@@ -65,13 +65,15 @@ def test_lead_selfenergy_matches_oracle(nb, seed):
         assert abs(int(s.iters_L[0, ie]) - itL) <= 1 and abs(int(s.iters_R[0, ie]) - itR) <= 1
 
 
+@pytest.mark.parametrize("nb", [6, 10])
 @pytest.mark.parametrize("complex_h", [False, True])
-def test_lead_pair_shared_decimation(complex_h):
+def test_lead_pair_shared_decimation(complex_h, nb):
     """h01_L = h01_R^dagger: one decimation serves both leads.  Each lead is
     checked against its own oracle decimation, and the shared run against two
-    independent GPU decimations."""
-    _say(f"leads shared decimation complex={complex_h}")
-    wl = random_tiny(10, 2, n_e=6, seed=11, eta=1e-3, complex_h=complex_h, n_k=2)
+    independent GPU decimations (nb = 6: the one-launch small-block
+    decimation, nb = 10: the batched one)."""
+    _say(f"leads shared decimation complex={complex_h} nb={nb}")
+    wl = random_tiny(nb, 2, n_e=6, seed=11, eta=1e-3, complex_h=complex_h, n_k=2)
     s = _solver(wl)
     sL, sR = [x.clone() for x in s.lead_selfenergies(shared_decimation=True)]
     itL, itR = s.iters_L.clone(), s.iters_R.clone()
