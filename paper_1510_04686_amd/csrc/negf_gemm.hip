@@ -16,14 +16,20 @@ namespace negf {
 
 static_assert(BM == 64, "gemm_tiles() assumes 64-wide tiles");
 
-template <typename Acc>
+// Products whose results are anti-Hermitian (the lesser functions) keep their
+// diagonal -- the occupation the density reads -- in the imaginary part, where
+// the 3M form's rounding bound u (|Ar| + |Ai|)(|Br| + |Bi|) is loose: they use
+// four real products, whose imaginary part is bounded by u (|Ar||Bi| + |Ai||Br|).
+template <int EPI> struct FourM { static constexpr bool value = EPI == EPI_STORE_AH || EPI == EPI_ADD_TTD_AH; };
+
+template <typename Acc, bool FM>
 __device__ inline void mma_tile(Acc (*As)[BK][LP], Acc (*Bs)[BK][LP], int lane, int am0, int bn0, int nmi, int nnj,
                                 typename MF<Acc>::V (&cr)[2][2], typename MF<Acc>::V (&ci)[2][2],
                                 typename MF<Acc>::V (&cs)[2][2]) {
-    if (nmi == 2 && nnj == 2) mma_slice<Acc, 2, 2>(As, Bs, lane, am0, bn0, cr, ci, cs);
-    else if (nmi == 2 && nnj == 1) mma_slice<Acc, 2, 1>(As, Bs, lane, am0, bn0, cr, ci, cs);
-    else if (nmi == 1 && nnj == 2) mma_slice<Acc, 1, 2>(As, Bs, lane, am0, bn0, cr, ci, cs);
-    else if (nmi == 1 && nnj == 1) mma_slice<Acc, 1, 1>(As, Bs, lane, am0, bn0, cr, ci, cs);
+    if (nmi == 2 && nnj == 2) mma_slice<Acc, 2, 2, FM>(As, Bs, lane, am0, bn0, cr, ci, cs);
+    else if (nmi == 2 && nnj == 1) mma_slice<Acc, 2, 1, FM>(As, Bs, lane, am0, bn0, cr, ci, cs);
+    else if (nmi == 1 && nnj == 2) mma_slice<Acc, 1, 2, FM>(As, Bs, lane, am0, bn0, cr, ci, cs);
+    else if (nmi == 1 && nnj == 1) mma_slice<Acc, 1, 1, FM>(As, Bs, lane, am0, bn0, cr, ci, cs);
 }
 
 // Output tile t of one point: row-major over all tiles, or over the lower
@@ -146,7 +152,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
                 load_slice<TA, AK>(A, n, m0, (kt + 1) * BK, tid, ra);
                 load_slice<TB, BKR>(B, n, n0, (kt + 1) * BK, tid, rb);
             }
-            mma_tile<Acc>(As[buf], Bs[buf], lane, am0, bn0, nmi, nnj, cr, ci, cs);
+            mma_tile<Acc, FourM<EPI>::value>(As[buf], Bs[buf], lane, am0, bn0, nmi, nnj, cr, ci, cs);
             if (more) {
                 store_slice<Acc, TA, AK, OPA == OP_C>(As[buf ^ 1], tid, ra);
                 store_slice<Acc, TB, BKR, OPB == OP_C>(Bs[buf ^ 1], tid, rb);
@@ -173,7 +179,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
             load_slice<TA, AK>(A, n, m0, ((KT) + 2) * BK, tid, ra[CUR]);                                  \
             load_slice<TB, BKR>(B, n, n0, ((KT) + 2) * BK, tid, rb[CUR]);                                 \
         }                                                                                                 \
-        mma_tile<Acc>(As[CUR], Bs[CUR], lane, am0, bn0, nmi, nnj, cr, ci, cs);                                  \
+        mma_tile<Acc, FourM<EPI>::value>(As[CUR], Bs[CUR], lane, am0, bn0, nmi, nnj, cr, ci, cs);                                  \
         if ((KT) + 1 < nkt) {                                                                             \
             store_slice<Acc, TA, AK, OPA == OP_C>(As[NXT], tid, ra[NXT]);                                 \
             store_slice<Acc, TB, BKR, OPB == OP_C>(Bs[NXT], tid, rb[NXT]);                                \
@@ -186,7 +192,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
         }
 #undef NEGF_GEMM_STEP
     }
-    finish_products<Acc>(cr, ci, cs);
+    finish_products<Acc, FourM<EPI>::value>(cr, ci, cs);
     gemm_epilogue<TC, Acc, EPI>(g, q, m0, n0, wt, lane, cr, ci);
 }
 
@@ -265,7 +271,8 @@ __global__ __launch_bounds__(256, 2) void gemm_persist_kernel(GemmArgs g) {
             ldA(nq, nm0, 0, ra[RC]); ldB(nq, nn0, 0, rb[RC]);                                             \
         }                                                                                                 \
         if constexpr (MI > 0 && NJ > 0)                                                                   \
-            mma_slice<Acc, (MI > 0 ? MI : 1), (NJ > 0 ? NJ : 1)>(As[lb], Bs[lb], lane, wt.am0, wt.bn0,     \
+            mma_slice<Acc, (MI > 0 ? MI : 1), (NJ > 0 ? NJ : 1), FourM<EPI>::value>(As[lb], Bs[lb], lane,   \
+                                                                                    wt.am0, wt.bn0,     \
                                                                  cr, ci, cs);                             \
         if ((KT) + 1 < nkt || ln < total) {                                                               \
             store_slice<Acc, TA, AK, OPA == OP_C>(As[lb ^ 1], tid, ra[RN]);                               \
@@ -299,7 +306,7 @@ __global__ __launch_bounds__(256, 2) void gemm_persist_kernel(GemmArgs g) {
         else if (wt.nmi == 1 && wt.nnj == 2) NEGF_PERSIST_TILE(1, 2)
         else if (wt.nmi == 1 && wt.nnj == 1) NEGF_PERSIST_TILE(1, 1)
         else NEGF_PERSIST_TILE(0, 0)
-        finish_products<Acc>(cr, ci, cs);
+        finish_products<Acc, FourM<EPI>::value>(cr, ci, cs);
         gemm_epilogue<TC, Acc, EPI>(g, cq, cm0, cn0, wt, lane, cr, ci);
         if (ln >= total) return;
         cq = nq; cm0 = nm0; cn0 = nn0;

@@ -121,7 +121,7 @@ __device__ inline WaveTile wave_tile(int wave, int vr, int vc) {
 // Accumulates one staged K slice into the (up to) 2 x 2 blocks of 16 x 16 at
 // tile-local (am0, bn0) that this wave owns; cr, ci, cs accumulate P1, P2, P3
 // of the 3M form until finish_products().
-template <typename Acc, int MI, int NJ>
+template <typename Acc, int MI, int NJ, bool FOURM = false>
 __device__ inline void mma_slice(Acc (*As)[BK][LP], Acc (*Bs)[BK][LP], int lane, int am0, int bn0,
                                  typename MF<Acc>::V (&cr)[2][2], typename MF<Acc>::V (&ci)[2][2],
                                  typename MF<Acc>::V (&cs)[2][2]) {
@@ -153,21 +153,37 @@ __device__ inline void mma_slice(Acc (*As)[BK][LP], Acc (*Bs)[BK][LP], int lane,
         for (int mi = 0; mi < MI; ++mi) sa[mi] = ar[c][mi] + ai[c][mi];
 #pragma unroll
         for (int nj = 0; nj < NJ; ++nj) sb[nj] = br[c][nj] + bi[c][nj];
+        if constexpr (FOURM) {
+            // four real products: cr += Ar Br - Ai Bi, ci += Ar Bi + Ai Br (cs unused)
+            (void)sa; (void)sb;
 #pragma unroll
-        for (int mi = 0; mi < MI; ++mi)
+            for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
-            for (int nj = 0; nj < NJ; ++nj) {
-                cr[mi][nj] = MF<Acc>::mma(ar[c][mi], br[c][nj], cr[mi][nj]);
-                ci[mi][nj] = MF<Acc>::mma(ai[c][mi], bi[c][nj], ci[mi][nj]);
-                cs[mi][nj] = MF<Acc>::mma(sa[mi], sb[nj], cs[mi][nj]);
-            }
+                for (int nj = 0; nj < NJ; ++nj) {
+                    const Acc nai = -ai[c][mi];
+                    cr[mi][nj] = MF<Acc>::mma(ar[c][mi], br[c][nj], cr[mi][nj]);
+                    cr[mi][nj] = MF<Acc>::mma(nai, bi[c][nj], cr[mi][nj]);
+                    ci[mi][nj] = MF<Acc>::mma(ar[c][mi], bi[c][nj], ci[mi][nj]);
+                    ci[mi][nj] = MF<Acc>::mma(ai[c][mi], br[c][nj], ci[mi][nj]);
+                }
+        } else {
+#pragma unroll
+            for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+                for (int nj = 0; nj < NJ; ++nj) {
+                    cr[mi][nj] = MF<Acc>::mma(ar[c][mi], br[c][nj], cr[mi][nj]);
+                    ci[mi][nj] = MF<Acc>::mma(ai[c][mi], bi[c][nj], ci[mi][nj]);
+                    cs[mi][nj] = MF<Acc>::mma(sa[mi], sb[nj], cs[mi][nj]);
+                }
+        }
     }
 }
 
 // Turns the partial products P1, P2, P3 into real and imaginary parts.
-template <typename Acc>
+template <typename Acc, bool FOURM = false>
 __device__ inline void finish_products(typename MF<Acc>::V (&cr)[2][2], typename MF<Acc>::V (&ci)[2][2],
                                        const typename MF<Acc>::V (&cs)[2][2]) {
+    if constexpr (FOURM) return;
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
 #pragma unroll

@@ -179,3 +179,32 @@ def check_point(out, p, point, r, N, tols, full=False, T=False):
         check(point, "bond", float(np.max(np.abs(b - r["bond"]))) / _bond_scale(r), tols)
     if T:
         check(point, "T", abs(float(out["T"][p]) - r["T"]) / max(1.0, abs(r["T"])), tols)
+
+
+def summarize(path):
+    """Markdown summary of a parity log: per quantity, the number of
+    comparisons, how many errors exceeded 1e-10, the largest error and
+    error / tolerance, error / drift (median, and largest where the error
+    exceeded 1e-10), and how many tolerances came from G^>'s parts rather than
+    its own drift."""
+    rows = [json.loads(ln) for ln in open(path)]
+    out = ["| quantity | comparisons | error > 1e-10 | max error | max error / tolerance | "
+           "median error / drift | max error / drift (error > 1e-10) | tolerance from the parts |",
+           "|---|---|---|---|---|---|---|---|"]
+    for q in sorted({r["qty"] for r in rows}):
+        v = [r for r in rows if r["qty"] == q]
+        e = np.array([r["err"] for r in v])
+        d = np.array([max(r["drift"], 1e-300) for r in v])
+        t = np.array([r["tol"] for r in v])
+        big = e > TOL
+        ed_big = f"{np.max(e[big] / d[big]):.1f}" if big.any() else "-"
+        parts = int(np.sum(t > np.maximum(TOL, FACTOR * d) * (1 + 1e-9)))
+        out.append(f"| {q} | {len(v)} | {int(big.sum())} | {e.max():.2e} | {np.max(e / t):.2f} | "
+                   f"{np.median(e / d):.2f} | {ed_big} | {parts if q == 'GG' else '-'} |")
+    return "\n".join(out)
+
+
+if __name__ == "__main__":
+    import sys
+    if len(sys.argv) == 3 and sys.argv[1] == "summarize":
+        print(summarize(sys.argv[2]))
