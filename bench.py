@@ -199,10 +199,10 @@ def main():
               flush=True)
     dt = time.perf_counter() - t0
     points *= n_iter
-    launches, gemm_ms, gemm_flops = 0, 0.0, 0.0
+    launches, gemm_ms, gemm_flops, gemm_mfma = 0, 0.0, 0.0, 0.0
     for c in solver.ctxs:
-        l_, m_, f_ = N.negf_gemm_timing(c)
-        launches, gemm_ms, gemm_flops = launches + l_, gemm_ms + m_, gemm_flops + f_
+        l_, m_, f_, x_ = N.negf_gemm_timing(c, executed=True)
+        launches, gemm_ms, gemm_flops, gemm_mfma = launches + l_, gemm_ms + m_, gemm_flops + f_, gemm_mfma + x_
         N.negf_gemm_timing_enable(c, False)
     st = solver.status()
     iters_L = solver.iters_L.cpu().numpy()
@@ -268,10 +268,10 @@ def main():
                      "launches": launches, "points_per_launch": point_launches / launches if launches else None,
                      "avg_launch_ms": gemm_ms / launches if launches else None,
                      # achieved counts 8 b^3 real flops per complex product (the algorithmic
-                     # count); complex products run as three real MFMA products (3M) in both
-                     # precisions, so the matrix cores execute 3/4 of that
-                     "mfma_flops_per_algorithmic_flop": 0.75,
-                     "executed_mfma_frac": 0.75 * achieved / peak if achieved else None},
+                     # count); complex products run as three real MFMA products (3M), except
+                     # the anti-Hermitian (lesser) products, which run as four
+                     "mfma_flops_per_algorithmic_flop": gemm_mfma / gemm_flops if gemm_flops else None,
+                     "executed_mfma_frac": (gemm_mfma / (gemm_ms * 1e-3)) / peak if gemm_ms > 0 else None},
         "status": N.STATUS.get(st, st),
     }
     if args.workload == "C3":

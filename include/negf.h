@@ -359,11 +359,15 @@ int negf_mixed_point_residuals(negf_ctx* ctx, void* stream, int n, double* out);
  * stream, 2 only around launches whose products run on FP64 matrix cores, 3
  * only around those on FP32 matrix cores (the block algebra of a mixed
  * context, whose lead decimation and residual products stay FP64); 0 stops.
- * negf_gemm_timing returns the launch count, summed kernel milliseconds and
- * summed algorithmic flops (8 n^3 per point per launch) since enabling.
+ * negf_gemm_timing returns the launch count, summed kernel milliseconds,
+ * summed algorithmic flops (8 n^3 per point per launch, of the output tiles a
+ * launch computes) and the flops its matrix-core products execute (3/4 of
+ * that in the three-product form, all of it for the anti-Hermitian products,
+ * which use four real products) since enabling; each output may be NULL.
  * Synchronises `stream`.  Errors: NEGF_EINVAL (NULL, enable outside 0..3). */
 int negf_gemm_timing_enable(negf_ctx* ctx, int enable);
-int negf_gemm_timing(negf_ctx* ctx, void* stream, long long* launches, double* ms, double* flops);
+int negf_gemm_timing(negf_ctx* ctx, void* stream, long long* launches, double* ms, double* flops,
+                     double* mfma_flops);
 
 /*
  * Kernel shape choices of a context (the batching form picks tile shapes by

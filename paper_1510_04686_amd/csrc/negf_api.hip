@@ -23,7 +23,8 @@ constexpr int SCBA_HMAX = 4096; // SCBA residual history entries kept on the dev
 
 struct TimedLaunch {
     hipEvent_t a, b;
-    double flops;
+    double flops;       // algorithmic: 8 n^3 per point (of the tiles computed)
+    double mfma;        // executed on matrix cores: 6 n^3 (3M form) or 8 n^3 (four products)
 };
 
 }  // namespace
@@ -111,7 +112,7 @@ struct negf_ctx {
     std::vector<TimedLaunch> pending;
     std::vector<hipEvent_t> ev_free;
     long long t_launches = 0;
-    double t_ms = 0.0, t_flops = 0.0;
+    double t_ms = 0.0, t_flops = 0.0, t_mfma = 0.0;
 
     ~negf_ctx() {
         for (auto& t : pending) { hipEventDestroy(t.a); hipEventDestroy(t.b); }
@@ -143,6 +144,7 @@ hipError_t drain_timing(negf_ctx* c) {
         hipEventElapsedTime(&ms, t.a, t.b);
         c->t_ms += ms;
         c->t_flops += t.flops;
+        c->t_mfma += t.mfma;
         c->t_launches += 1;
         c->ev_free.push_back(t.a);
         c->ev_free.push_back(t.b);
@@ -175,7 +177,9 @@ hipError_t run_gemm(negf_ctx* c, hipStream_t s, GemmTypes ty, int opa, int opb, 
     }
     const double tl = (double)((g.n + 63) / 64);
     const double frac = (double)gemm_tiles(g.n, epi) / (tl * tl);   // executed share of the full product
-    TimedLaunch t{get_event(c), get_event(c), 8.0 * (double)g.n * g.n * g.n * (double)active * frac};
+    const double fl = 8.0 * (double)g.n * g.n * g.n * (double)active * frac;
+    const bool four = epi == EPI_STORE_AH || epi == EPI_ADD_TTD_AH;   // the kernels' four-product launches
+    TimedLaunch t{get_event(c), get_event(c), fl, four ? fl : 0.75 * fl};
     hipEventRecord(t.a, s);
     hipError_t e = gemm_launch(s, ty, opa, opb, epi, gt);
     hipEventRecord(t.b, s);
@@ -1267,7 +1271,7 @@ int negf_gemm_timing_enable(negf_ctx* c, int enable) {
     if (!c || enable < 0 || enable > 3) return NEGF_EINVAL;
     c->timing = enable != 0;
     c->timing_acc = enable == 2 ? DT_C128 : (enable == 3 ? DT_C64 : -1);
-    if (c->timing) { c->t_launches = 0; c->t_ms = 0; c->t_flops = 0; }
+    if (c->timing) { c->t_launches = 0; c->t_ms = 0; c->t_flops = 0; c->t_mfma = 0; }
     return NEGF_OK;
 }
 
@@ -1362,13 +1366,15 @@ int negf_autotune(negf_ctx* c, void* stream, int reps, negf_tuning* out) {
     return NEGF_OK;
 }
 
-int negf_gemm_timing(negf_ctx* c, void* stream, long long* launches, double* ms, double* flops) {
+int negf_gemm_timing(negf_ctx* c, void* stream, long long* launches, double* ms, double* flops,
+                     double* mfma_flops) {
     if (!c) return NEGF_EINVAL;
     NEGF_HIP_CHECK(hipStreamSynchronize((hipStream_t)stream));
     NEGF_HIP_CHECK(drain_timing(c));
     if (launches) *launches = c->t_launches;
     if (ms) *ms = c->t_ms;
     if (flops) *flops = c->t_flops;
+    if (mfma_flops) *mfma_flops = c->t_mfma;
     return NEGF_OK;
 }
 

@@ -101,7 +101,7 @@ def lib():
         "negf_set_mixed_threshold": (i, [vp, d]),
         "negf_mixed_point_residuals": (i, [vp, vp, i, vp]),
         "negf_gemm_timing_enable": (i, [vp, i]),
-        "negf_gemm_timing": (i, [vp, vp, POINTER(ll), POINTER(d), POINTER(d)]),
+        "negf_gemm_timing": (i, [vp, vp, POINTER(ll), POINTER(d), POINTER(d), POINTER(d)]),
         "negf_get_tuning": (i, [vp, POINTER(negf_tuning)]),
         "negf_set_tuning": (i, [vp, POINTER(negf_tuning)]),
         "negf_autotune": (i, [vp, vp, i, POINTER(negf_tuning)]),
@@ -355,12 +355,17 @@ def negf_gemm_timing_enable(ctx, enable=True):
     _check("negf_gemm_timing_enable", lib().negf_gemm_timing_enable(ctx.handle, GEMM_TIMING[enable]))
 
 
-def negf_gemm_timing(ctx, stream=None):
+def negf_gemm_timing(ctx, stream=None, executed=False):
+    """(launches, ms, algorithmic flops), plus the executed matrix-core flops
+    when ``executed``."""
     n = c_longlong()
     ms = c_double()
     fl = c_double()
+    ex = c_double()
     _check("negf_gemm_timing", lib().negf_gemm_timing(ctx.handle, _stream(stream), ctypes.byref(n),
-                                                       ctypes.byref(ms), ctypes.byref(fl)))
+                                                       ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(ex)))
+    if executed:
+        return int(n.value), float(ms.value), float(fl.value), float(ex.value)
     return int(n.value), float(ms.value), float(fl.value)
 
 
