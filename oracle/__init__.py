@@ -24,3 +24,12 @@ from .negf_oracle import (  # noqa: F401
     dense_grad,
     density_objective,
 )
+from .poisson import (  # noqa: F401
+    PoissonGrid,
+    poisson_beta,
+    poisson_matrix,
+    poisson_boundary,
+    density_atoms,
+    density_jacobian,
+    newton_poisson,
+)

@@ -514,3 +514,90 @@ def test_rgf_diag_only_keeps_the_same_arithmetic():
     for k in ("GR", "GL", "GG"):
         assert np.array_equal(np.diagonal(a[k], axis1=1, axis2=2), b[k]), k
     assert np.array_equal(a["bond"], b["bond"]) and np.array_equal(a["bond_mag"], b["bond_mag"])
+
+
+# ---------------------------------------------------------------------------
+# NEGF-Poisson loop (Eq. 9)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("ny", [1, 2, 4])
+def test_poisson_operator_laplace_closed_form(ny):
+    """No charge, contacts at v_left / v_right, insulating z faces: the exact
+    solution is linear in x and constant across the section; with gates at the
+    contacts' common value the constant solves it."""
+    nx, nz = 7, 3
+    L = O.poisson_matrix(nx, nz, ny, False)
+    b = O.poisson_boundary(nx, nz, ny, False, 0.3, -0.2)
+    x = np.arange(nx)
+    v = np.repeat(0.3 + (-0.2 - 0.3) * (x + 1) / (nx + 1), nz * ny)
+    assert np.max(np.abs(L @ v - b)) < 1e-14
+    Lg = O.poisson_matrix(nx, nz, ny, True)
+    bg = O.poisson_boundary(nx, nz, ny, True, 0.1, 0.1, 0.1)
+    assert np.max(np.abs(Lg @ np.full(nx * nz * ny, 0.1) - bg)) < 1e-14
+    # symmetric, positive definite (every atom connects to a contact)
+    assert np.array_equal(L, L.T)
+    assert np.linalg.eigvalsh(L).min() > 0
+
+
+def test_poisson_operator_uniform_charge_parabola():
+    """Uniform charge q per atom between grounded contacts: the discrete
+    solution is q (x + 1)(N_x - x) / 2 (its second difference is exactly -q)."""
+    nx, nz, ny, q = 9, 2, 3, 0.37
+    L = O.poisson_matrix(nx, nz, ny, False)
+    x = np.arange(nx)
+    v = np.repeat(q * (x + 1) * (nx - x) / 2.0, nz * ny)
+    assert np.max(np.abs(L @ v - q)) < 1e-13
+
+
+def _poisson_tiny(eta=0.05):
+    import dataclasses
+    wl = make_workload("C2", n_slab=4, n_e=48, n_k=1, n_z=1, n_y=2)
+    return dataclasses.replace(wl, eta=eta, v_onsite=None)
+
+
+def test_density_jacobian_matches_finite_differences_and_vjp():
+    wl = _poisson_tiny()
+    pts = [(0, 0, e) for e in range(wl.n_e)]
+    leads = O.lead_tables(wl)
+    rng = np.random.default_rng(9)
+    v = rng.uniform(0.0, 0.2, size=(wl.total_slabs, wl.atoms_per_slab))
+    D = O.density_jacobian(wl, v, pts, leads)
+    h = 1e-5
+    fd = np.zeros_like(D)
+    for j in range(v.size):
+        vp, vm = v.copy().reshape(-1), v.copy().reshape(-1)
+        vp[j] += h
+        vm[j] -= h
+        fd[:, j] = (O.density_atoms(wl, vp.reshape(v.shape), pts, leads).reshape(-1)
+                    - O.density_atoms(wl, vm.reshape(v.shape), pts, leads).reshape(-1)) / (2 * h)
+    assert np.max(np.abs(D - fd)) < 1e-6 * np.max(np.abs(D))
+    w = rng.normal(size=v.shape)
+    g = O.dense_grad(wl, w, np.repeat(v, wl.orbs_per_atom, axis=1), pts, leads)
+    assert np.max(np.abs(w.reshape(-1) @ D - g.reshape(-1))) < 1e-12 * np.max(np.abs(g))
+
+
+def test_newton_poisson_pinned_by_its_residual():
+    """The converged potential satisfies the discretised Eq. (9) with the
+    density evaluated afresh (solve_points + observables), Newton converges
+    quadratically, and a vanishing coupling beta returns the Laplace solution."""
+    wl = _poisson_tiny()
+    grid = O.PoissonGrid(nz=1, ny=2, v_left=0.0, v_right=-0.05)
+    pts = [(0, 0, e) for e in range(wl.n_e)]
+    leads = O.lead_tables(wl)
+    beta = O.poisson_beta(11.7, 0.2715)
+    n0 = O.density_atoms(wl, np.zeros((wl.total_slabs, 2)), pts, leads)
+    nd = n0 + 0.02                # a small donor excess over the density at V = 0
+    V, hist = O.newton_poisson(wl, grid, beta, nd, np.zeros(n0.shape), pts, leads, tol=1e-12)
+    assert hist[-1] <= 1e-12 and len(hist) <= 8
+    for a, b_ in zip(hist[1:], hist[2:]):          # quadratic once in the basin
+        if a < 1e-3:
+            assert b_ <= 10.0 * a * a + 1e-13
+    L = O.poisson_matrix(wl.total_slabs, 1, 2, False)
+    bb = O.poisson_boundary(wl.total_slabs, 1, 2, False, 0.0, -0.05)
+    n = O.density_atoms(wl, V, pts, leads)
+    F = L @ V.reshape(-1) - bb - beta * (n - nd).reshape(-1)
+    assert np.max(np.abs(F)) < 1e-11
+    V0, _ = O.newton_poisson(wl, grid, 1e-12, nd, np.zeros(n0.shape), pts, leads, tol=1e-14)
+    x = np.arange(wl.total_slabs)
+    lin = np.repeat(-0.05 * (x + 1) / (wl.total_slabs + 1), 2).reshape(V0.shape)
+    assert np.max(np.abs(V0 - lin)) < 1e-12
