@@ -354,6 +354,23 @@ int negf_set_mixed_threshold(negf_ctx* ctx, double thr);
  * forward sweep yet), NEGF_ESHAPE (n larger than the sweep). */
 int negf_mixed_point_residuals(negf_ctx* ctx, void* stream, int n, double* out);
 
+/* Mixed precision: a redo score for every bound point p (the bind's order),
+ * written to the DEVICE array score[n_points] on `stream`:
+ *   score[p] = resid[p] * w_e[e_p] * w_k[k_p] * max_j |Im G^<_jj(p)|,
+ * the point's largest refinement residual (resid, device, one per bound point,
+ * as collected from negf_mixed_point_residuals) times its largest weighted
+ * contribution to the density sum of Eq. 7.  GL holds the orbital diagonals of
+ * G^< of all bound points, [n_points][slab_stride][nb] complex128 (device),
+ * as negf_rgf_backward writes them; w_e, w_k are the quadrature weights
+ * (device).  A non-finite input gives +inf.  The FP32 error of a point's
+ * density contribution grows with both factors, so a caller redoes the
+ * highest-scoring points in FP64 (the residual alone misses weakly occupied
+ * but ill-conditioned points and over-ranks empty ones).
+ * Errors: NEGF_EINVAL (NULL pointer, slab_stride below the longest sample),
+ * NEGF_ESTATE (no bound system). */
+int negf_mixed_point_scores(negf_ctx* ctx, void* stream, const negf_c128* GL, int slab_stride,
+                            const double* w_e, const double* w_k, const double* resid, double* score);
+
 /* Kernel timing of the dominant kernel family (the batched complex GEMM):
  * enable = 1 records a HIP event pair around every GEMM launch on the launch
  * stream, 2 only around launches whose products run on FP64 matrix cores, 3
@@ -400,6 +417,63 @@ typedef struct {
 int negf_get_tuning(const negf_ctx* ctx, negf_tuning* out);
 int negf_set_tuning(negf_ctx* ctx, const negf_tuning* tuning);
 int negf_autotune(negf_ctx* ctx, void* stream, int reps, negf_tuning* out);
+
+/* ---------------------------------------------------------------------------
+ * The NEGF-Poisson loop (Eq. 9: div(eps grad Phi) = e (n - N_D), iterated with
+ * Eqs. (1)-(8) until the two agree).  With V = -e Phi the electron's potential
+ * energy per atom (eV, the onsite potential of Eq. 1), n and N_D in electrons
+ * per atom and a finite-difference grid whose nodes are the atoms (spacing h):
+ *     (L V)_a = beta (n_a - N_D,a),   beta = e^2 / (eps h),
+ *     (L V)_a = sum over the six neighbours b of (V_a - V_b).
+ * Atom (x, z, y) has index (x * n_z + z) * n_y + y: x the slab (transport), z
+ * across the body, y along the transverse direction of the k grid (periodic),
+ * the same order as the density's [slab][atom] with atom = z * n_y + y.  A
+ * neighbour beyond x = 0 / x = n_x - 1 is a contact held at v_left / v_right;
+ * beyond a z face it is a gate at v_gate (z_gate = 1) or absent (insulating
+ * face, z_gate = 0).  L0 denotes L with every boundary value zero (symmetric
+ * positive definite).  All vectors are DEVICE arrays of n_x n_z n_y doubles;
+ * the calls issue their kernels on `stream` and allocate nothing.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int n_x, n_z, n_y;
+    int z_gate;
+    double v_left, v_right, v_gate;
+} negf_poisson_grid;
+
+/* out = L V (with_boundary = 1) or L0 V (0).  Errors: NEGF_EINVAL. */
+int negf_poisson_apply(void* stream, const negf_poisson_grid* grid, const double* V, int with_boundary,
+                       double* out);
+
+/* The loop's residual F = L V - beta (n - N_D).  Errors: NEGF_EINVAL. */
+int negf_poisson_residual(void* stream, const negf_poisson_grid* grid, const double* V, const double* n_atom,
+                          const double* n_d, double beta, double* F);
+
+/* Device bytes of the `work` argument of negf_poisson_solve (-1: bad grid). */
+long long negf_poisson_work_bytes(const negf_poisson_grid* grid);
+
+/* x = L0^-1 rhs by conjugate gradients from x = 0, until ||r|| <= tol ||rhs||
+ * or max_iter iterations (checked every 16).  Writes the iteration count and
+ * the final relative residual (host outputs; synchronises `stream`).  `work`:
+ * negf_poisson_work_bytes bytes of device memory, owned by the caller.
+ * Errors: NEGF_EINVAL, NEGF_EHIP. */
+int negf_poisson_solve(void* stream, const negf_poisson_grid* grid, const double* rhs, double* x, double tol,
+                       int max_iter, void* work, int* iters, double* rel_res);
+
+/* Vector kernels of the Newton step's Krylov solver (device arrays; X holds m
+ * vectors of length n, row j at X + j * ld).
+ *   negf_vec_dots:    out[j] = sum_i X[j, i] y[i], j < m (out on the device);
+ *                     `work`: negf_vec_work_bytes(n, m) bytes of device memory.
+ *   negf_vec_combine: y = b y + sum_j c[j] X[j, :] (c: m device doubles; y is
+ *                     not read when b = 0).
+ *   negf_vec_norms:   out[0] = x . x, out[1] = max_i |x_i| (out on the device;
+ *                     `work` as for negf_vec_dots with m = 1).
+ * Deterministic: fixed reduction order.  Errors: NEGF_EINVAL. */
+long long negf_vec_work_bytes(long long n, int m);
+int negf_vec_dots(void* stream, long long n, int m, const double* X, long long ld, const double* y, double* out,
+                  void* work);
+int negf_vec_combine(void* stream, long long n, int m, const double* X, long long ld, const double* c, double b,
+                     double* y);
+int negf_vec_norms(void* stream, long long n, const double* x, double* out, void* work);
 
 #ifdef __cplusplus
 }

@@ -94,23 +94,27 @@ def poisson_boundary(nx: int, nz: int, ny: int, z_gate: bool, v_left: float, v_r
     return b
 
 
-def density_atoms(wl, v_atom, points, leads):
+def density_atoms(wl, v_atom, points, leads, eta_fill=None):
     """n per atom (Eq. 7) of a single-sample workload at the per-atom potential
-    v_atom [N_x, atoms], through solve_points and observables."""
+    v_atom [N_x, atoms], through solve_points and observables (eta_fill: the
+    Fermi level that fills the device's eta sink, None for an empty sink)."""
     v_orb = np.repeat(np.asarray(v_atom, dtype=np.float64), wl.orbs_per_atom, axis=1)
     w = dataclasses.replace(wl, v_onsite=v_orb)
-    res = solve_points(w, points, leads=leads, diag_only=True)
+    res = solve_points(w, points, leads=leads, diag_only=True, eta_fill=eta_fill)
     n, _, _ = observables(w, points, [r["GL"] for r in res], [r["bond"] for r in res])
     return n
 
 
-def density_jacobian(wl, v_atom, points, leads):
+def density_jacobian(wl, v_atom, points, leads, eta_fill=None):
     """dn_a/dV_b (atoms x atoms) of a single-sample workload.
 
     From dG^R = G^R dV G^R and dG^< = G^R dV G^< + G^< dV G^A (dV diagonal,
     the same on the orbitals of one atom):
       dn_a/dV_b = sum_points c_p sum_{o in a, o' in b} Im(G_oo' G^<_o'o + G^<_oo' conj(G_oo')),
-    c_p = g_s w_E w_k / 2pi.  Dense inversion; tiny systems only."""
+    c_p = g_s w_E w_k / 2pi.  In equilibrium (one Fermi level f for both
+    leads and the eta sink) G^< = -f (G - G^dagger) and each term becomes
+    -2 f Im(G_oo' G_o'o), symmetric in (a, b).  Dense inversion; tiny systems
+    only."""
     nat, opa = wl.atoms_per_slab, wl.orbs_per_atom
     N = wl.total_slabs
     na = N * nat
@@ -120,8 +124,9 @@ def density_jacobian(wl, v_atom, points, leads):
         hd, hu, _ = wl.sample_blocks(int(s), int(ik))
         E = float(wl.energy[ie])
         sL, sR = leads[(int(ik), int(ie))][:2]
+        ef = None if eta_fill is None else float(fermi(E, eta_fill, wl.kT))
         r = dense(hd, hu, E, wl.eta, sL, sR, float(fermi(E, wl.mu_L, wl.kT)), float(fermi(E, wl.mu_R, wl.kT)),
-                  v=[v_orb[i] for i in range(N)], full=True)
+                  v=[v_orb[i] for i in range(N)], full=True, eta_fill=ef)
         G, Gl = r["G"], r["Gl"]
         M = np.imag(G * Gl.T + Gl * np.conj(G))
         c = wl.g_s * wl.w_e[ie] * wl.w_k[ik] / (2 * np.pi)
@@ -140,7 +145,7 @@ class PoissonGrid:
 
 
 def newton_poisson(wl, grid: PoissonGrid, beta: float, n_d, v0, points=None, leads=None, tol=1e-9,
-                   max_iter=30, max_step=0.1):
+                   max_iter=30, max_step=0.1, eta_fill=None):
     """Newton's method on F(V) = L V - beta (n(V) - N_D) for a single-sample
     workload; V per atom [N_x, atoms].  Each step solves (L - beta dn/dV) dV = -F
     with the dense Jacobian; a step larger than max_step (eV, on any atom) is
@@ -158,12 +163,12 @@ def newton_poisson(wl, grid: PoissonGrid, beta: float, n_d, v0, points=None, lea
     V = np.asarray(v0, dtype=np.float64).reshape(-1).copy()
     hist = []
     for _ in range(max_iter + 1):
-        n = density_atoms(wl, V.reshape(nx, nat), points, leads).reshape(-1)
+        n = density_atoms(wl, V.reshape(nx, nat), points, leads, eta_fill).reshape(-1)
         F = L @ V - b - beta * (n - nd)
         hist.append(float(np.max(np.abs(F))))
         if hist[-1] <= tol:
             break
-        J = L - beta * density_jacobian(wl, V.reshape(nx, nat), points, leads)
+        J = L - beta * density_jacobian(wl, V.reshape(nx, nat), points, leads, eta_fill)
         dV = np.linalg.solve(J, -F)
         V = V + dV * min(1.0, max_step / max(float(np.max(np.abs(dV))), 1e-300))
     return V.reshape(nx, nat), hist

@@ -324,6 +324,39 @@ __global__ void zero_d_kernel(double* p, int n) {
     if (i < n) p[i] = 0.0;
 }
 
+// Mixed precision: per-point redo score = (largest block refinement residual of
+// the point) x (its energy and k weights) x (largest |Im G^<_jj| over its
+// orbitals), i.e. the residual times the point's largest contribution to the
+// density sum of Eq. 7.  One workgroup per point; a non-finite entry gives +inf.
+__global__ __launch_bounds__(256) void mixed_score_kernel(const double2* GL, int slab_stride, int n,
+                                                          const int4* desc, const double* w_e, const double* w_k,
+                                                          const double* resid, double* score) {
+    const int p = blockIdx.x;
+    const int4 d = desc[p];
+    const long long m = (long long)d.w * n;
+    const double2* X = GL + (long long)p * slab_stride * n;
+    __shared__ double red[256];
+    double mx = 0.0;
+    for (long long i = threadIdx.x; i < m; i += 256) {
+        const double v = fabs(X[i].y);
+        mx = (v <= mx) ? mx : v;          // NaN propagates
+    }
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            const double u = red[threadIdx.x + o];
+            if (!(u <= red[threadIdx.x])) red[threadIdx.x] = u;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double r = resid[p] * w_e[d.z] * w_k[d.y] * red[0];
+        if (!(r == r) || !(red[0] < INFINITY) || !(resid[p] < INFINITY)) r = INFINITY;
+        score[p] = r;
+    }
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1257,6 +1290,19 @@ int negf_mixed_point_residuals(negf_ctx* c, void* stream, int n, double* out) {
     if (c->prec != NEGF_MIXED || !c->fwd_done) return NEGF_ESTATE;
     if (n > c->fwd_np) return NEGF_ESHAPE;
     hipLaunchKernelGGL(copy_d_kernel, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, c->ns_res, out, n);
+    NEGF_HIP_CHECK(hipGetLastError());
+    return NEGF_OK;
+}
+
+int negf_mixed_point_scores(negf_ctx* c, void* stream, const negf_c128* GL, int slab_stride, const double* w_e,
+                            const double* w_k, const double* resid, double* score) {
+    if (!c || !GL || !w_e || !w_k || !resid || !score) return NEGF_EINVAL;
+    if (!c->bound) return NEGF_ESTATE;
+    int maxN = 0;
+    for (size_t s = 0; s + 1 < c->soff_h.size(); ++s) maxN = std::max<long long>(maxN, c->soff_h[s + 1] - c->soff_h[s]);
+    if (slab_stride < maxN) return NEGF_EINVAL;
+    hipLaunchKernelGGL(mixed_score_kernel, dim3(c->n_points), dim3(256), 0, (hipStream_t)stream,
+                       reinterpret_cast<const double2*>(GL), slab_stride, c->nb, c->desc_d, w_e, w_k, resid, score);
     NEGF_HIP_CHECK(hipGetLastError());
     return NEGF_OK;
 }

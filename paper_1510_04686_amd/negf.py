@@ -53,12 +53,21 @@ class negf_system(ctypes.Structure):
     ]
 
 
+class negf_poisson_grid(ctypes.Structure):
+    _fields_ = [
+        ("n_x", c_int), ("n_z", c_int), ("n_y", c_int), ("z_gate", c_int),
+        ("v_left", c_double), ("v_right", c_double), ("v_gate", c_double),
+    ]
+
+
 EXPORTS = [
     "negf_create", "negf_destroy", "negf_workspace_bytes", "negf_sync_status", "negf_error_string",
     "negf_bind", "negf_lead_selfenergy", "negf_lead_selfenergy_pair", "negf_rgf_forward", "negf_rgf_backward",
     "negf_scba_selfenergy", "negf_observables", "negf_rgf_adjoint", "negf_zgemm_batched", "negf_zinv_batched", "negf_mixed_stats",
-    "negf_set_mixed_threshold", "negf_mixed_point_residuals", "negf_gemm_timing_enable", "negf_gemm_timing", "negf_get_tuning", "negf_set_tuning", "negf_autotune",
+    "negf_set_mixed_threshold", "negf_mixed_point_residuals", "negf_mixed_point_scores", "negf_gemm_timing_enable", "negf_gemm_timing", "negf_get_tuning", "negf_set_tuning", "negf_autotune",
     "negf_build_id", "negf_scba_history", "negf_rgf_solve", "negf_zinv_noalloc_bytes", "negf_zinv_batched_noalloc",
+    "negf_poisson_apply", "negf_poisson_residual", "negf_poisson_work_bytes", "negf_poisson_solve",
+    "negf_vec_work_bytes", "negf_vec_dots", "negf_vec_combine", "negf_vec_norms",
 ]
 
 
@@ -100,11 +109,20 @@ def lib():
         "negf_mixed_stats": (i, [vp, vp, POINTER(ll), POINTER(d)]),
         "negf_set_mixed_threshold": (i, [vp, d]),
         "negf_mixed_point_residuals": (i, [vp, vp, i, vp]),
+        "negf_mixed_point_scores": (i, [vp, vp, vp, i, vp, vp, vp, vp]),
         "negf_gemm_timing_enable": (i, [vp, i]),
         "negf_gemm_timing": (i, [vp, vp, POINTER(ll), POINTER(d), POINTER(d), POINTER(d)]),
         "negf_get_tuning": (i, [vp, POINTER(negf_tuning)]),
         "negf_set_tuning": (i, [vp, POINTER(negf_tuning)]),
         "negf_autotune": (i, [vp, vp, i, POINTER(negf_tuning)]),
+        "negf_poisson_apply": (i, [vp, POINTER(negf_poisson_grid), vp, i, vp]),
+        "negf_poisson_residual": (i, [vp, POINTER(negf_poisson_grid), vp, vp, vp, d, vp]),
+        "negf_poisson_work_bytes": (ll, [POINTER(negf_poisson_grid)]),
+        "negf_poisson_solve": (i, [vp, POINTER(negf_poisson_grid), vp, vp, d, i, vp, POINTER(i), POINTER(d)]),
+        "negf_vec_work_bytes": (ll, [ll, i]),
+        "negf_vec_dots": (i, [vp, ll, i, vp, ll, vp, vp, vp]),
+        "negf_vec_combine": (i, [vp, ll, i, vp, ll, vp, d, vp]),
+        "negf_vec_norms": (i, [vp, ll, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -345,6 +363,103 @@ def negf_mixed_point_residuals(ctx, out, n=None, stream=None):
     n = out.numel() if n is None else int(n)
     _check("negf_mixed_point_residuals",
            lib().negf_mixed_point_residuals(ctx.handle, _stream(stream), n, _ptr(out, torch.float64, "out")))
+
+
+def negf_mixed_point_scores(ctx, GL, slab_stride, w_e, w_k, resid, score, stream=None):
+    """Redo score of every bound point into the float64 device tensor `score`:
+    residual x quadrature weight x largest |Im G^<_jj| of the point."""
+    _check("negf_mixed_point_scores",
+           lib().negf_mixed_point_scores(ctx.handle, _stream(stream), _ptr(GL, torch.complex128, "GL"),
+                                         int(slab_stride), _ptr(w_e, torch.float64, "w_e"),
+                                         _ptr(w_k, torch.float64, "w_k"), _ptr(resid, torch.float64, "resid"),
+                                         _ptr(score, torch.float64, "score")))
+
+
+# ------------------------------------------------------------------ Poisson (Eq. 9)
+def poisson_grid(n_x, n_z, n_y, z_gate=False, v_left=0.0, v_right=0.0, v_gate=0.0):
+    return negf_poisson_grid(int(n_x), int(n_z), int(n_y), int(bool(z_gate)), float(v_left), float(v_right),
+                             float(v_gate))
+
+
+def _vec(t, n, name):
+    p = _ptr(t, torch.float64, name)
+    if t.numel() != n:
+        raise ValueError(f"{name} must hold {n} doubles, got {t.numel()}")
+    return p
+
+
+def _atoms(g):
+    return g.n_x * g.n_z * g.n_y
+
+
+def negf_poisson_apply(grid, V, out, with_boundary=True, stream=None):
+    n = _atoms(grid)
+    _check("negf_poisson_apply", lib().negf_poisson_apply(_stream(stream), ctypes.byref(grid), _vec(V, n, "V"),
+                                                          int(bool(with_boundary)), _vec(out, n, "out")))
+
+
+def negf_poisson_residual(grid, V, n_atom, n_d, beta, F, stream=None):
+    n = _atoms(grid)
+    _check("negf_poisson_residual",
+           lib().negf_poisson_residual(_stream(stream), ctypes.byref(grid), _vec(V, n, "V"),
+                                       _vec(n_atom, n, "n_atom"), _vec(n_d, n, "n_d"), float(beta),
+                                       _vec(F, n, "F")))
+
+
+def negf_poisson_work_bytes(grid):
+    return int(lib().negf_poisson_work_bytes(ctypes.byref(grid)))
+
+
+def negf_poisson_solve(grid, rhs, x, work, tol=1e-12, max_iter=10000, stream=None):
+    """x = L0^-1 rhs (conjugate gradients); returns (iterations, relative residual)."""
+    n = _atoms(grid)
+    if work.numel() * work.element_size() < negf_poisson_work_bytes(grid):
+        raise ValueError("work too small")
+    it, rr = c_int(0), c_double(0.0)
+    _check("negf_poisson_solve",
+           lib().negf_poisson_solve(_stream(stream), ctypes.byref(grid), _vec(rhs, n, "rhs"), _vec(x, n, "x"),
+                                    float(tol), int(max_iter), _ptr(work, None, "work"), ctypes.byref(it),
+                                    ctypes.byref(rr)))
+    return it.value, rr.value
+
+
+def negf_vec_work_bytes(n, m):
+    return int(lib().negf_vec_work_bytes(int(n), int(m)))
+
+
+def _rows(X, m, n):
+    p = _ptr(X, torch.float64, "X")
+    if X.dim() != 2 or X.shape[0] < m or X.shape[1] != n:
+        raise ValueError(f"X must be [>= {m}, {n}]")
+    return p
+
+
+def negf_vec_dots(X, m, y, out, work, stream=None):
+    """out[:m] = X[:m] @ y on the device."""
+    n = y.numel()
+    if out.numel() < m or work.numel() * work.element_size() < negf_vec_work_bytes(n, m):
+        raise ValueError("out / work too small")
+    _check("negf_vec_dots", lib().negf_vec_dots(_stream(stream), n, int(m), _rows(X, m, n), n, _vec(y, n, "y"),
+                                                _ptr(out, torch.float64, "out"), _ptr(work, None, "work")))
+
+
+def negf_vec_norms(x, out, work, stream=None):
+    """out[0] = x . x, out[1] = max |x_i| on the device."""
+    n = x.numel()
+    if out.numel() < 2 or work.numel() * work.element_size() < negf_vec_work_bytes(n, 1):
+        raise ValueError("out / work too small")
+    _check("negf_vec_norms", lib().negf_vec_norms(_stream(stream), n, _vec(x, n, "x"),
+                                                  _ptr(out, torch.float64, "out"), _ptr(work, None, "work")))
+
+
+def negf_vec_combine(X, m, c, b, y, stream=None):
+    """y = b y + sum_j c[j] X[j] on the device."""
+    n = y.numel()
+    if m > 0 and c.numel() < m:
+        raise ValueError("c too small")
+    _check("negf_vec_combine", lib().negf_vec_combine(_stream(stream), n, int(m), _rows(X, m, n) if m else None, n,
+                                                      _ptr(c, torch.float64, "c") if m else None, float(b),
+                                                      _vec(y, n, "y")))
 
 
 GEMM_TIMING = {False: 0, True: 1, "all": 1, "fp64": 2, "fp32": 3}

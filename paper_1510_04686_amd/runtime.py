@@ -29,7 +29,7 @@ class RGFSolver:
     """Batched RGF over every (sample, k, E) point of a workload on one GPU."""
 
     def __init__(self, wl, precision="fp64", capacity=None, device="cuda", mem_fraction=0.75, adjoint_segment=0,
-                 tune=None, lanes=1, point_redo=0.03, store="full"):
+                 tune=None, lanes=1, point_redo=math.inf, store="full", redo_frac=0.05):
         """tune: None keeps the library's default kernel shapes; "auto" measures
         them on this context once (negf_autotune) and caches the choice per
         (device, block, capacity, precision); a dict sets them explicitly.
@@ -42,7 +42,14 @@ class RGFSolver:
         solved again on an FP64 context and its outputs replaced.  The FP32
         recursion loses roughly that residual in relative accuracy on a point
         (its conditioning), so the bound trades accuracy against the share of
-        points redone; math.inf turns the redo off.
+        points redone; math.inf (the default) turns this rule off.
+        redo_frac (mixed precision only, default 0.05): also redo, in FP64, this
+        fraction of the points with the highest redo score
+        (negf_mixed_point_scores: the residual times the point's largest
+        weighted |Im G^<_jj|), and every point with a non-finite score, when the
+        pass writes the G^< diagonals.  The score ranks the points by their
+        likely FP32 error in the density, which the residual alone does not;
+        0 turns this rule off.
         store: "full" keeps g and g^< of every slab; "checkpoint" keeps them
         only at the end of every segment of K = ceil(sqrt(N)) slabs (or
         `adjoint_segment` slabs) plus one segment, and the backward sweep and
@@ -106,6 +113,9 @@ class RGFSolver:
         self.eta_fill = 0
         mixed = self.prec == N.NEGF_MIXED
         self.point_redo = float(point_redo) if mixed else math.inf
+        self.redo_frac = float(redo_frac) if (mixed and redo_frac) else 0.0
+        if not 0.0 <= self.redo_frac <= 1.0:
+            raise ValueError("redo_frac must lie in [0, 1]")
         self.resid = torch.zeros(self.n_points, dtype=torch.float64, device=self.device) if mixed else None
         self.redo_ctx = None
         self.points_redone = 0
@@ -265,14 +275,26 @@ class RGFSolver:
         if self.lanes > 1:
             for ls in self.streams:          # join
                 base.wait_stream(ls)
-        if math.isfinite(self.point_redo) and not torch.cuda.is_current_stream_capturing():
+        if self._redo_on() and not torch.cuda.is_current_stream_capturing():
             self._redo(out, full_blocks, want_T, scat_R, scat_L, base)
+
+    def _redo_on(self):
+        return math.isfinite(self.point_redo) or self.redo_frac > 0
 
     def _redo(self, out, full_blocks, want_T, scat_R, scat_L, stream):
         """FP64 pass over the points whose mixed-precision residual exceeded
-        `point_redo`; their outputs replace the mixed ones in place."""
+        `point_redo`, and over the `redo_frac` share of points with the highest
+        redo score; their outputs replace the mixed ones in place."""
         with torch.cuda.stream(stream):
-            idx = torch.nonzero(self.resid > self.point_redo).flatten()
+            sel = self.resid > self.point_redo
+            k = int(math.ceil(self.redo_frac * self.n_points))
+            if k > 0 and "GL" in out and not full_blocks:
+                score = torch.empty_like(self.resid)
+                N.negf_mixed_point_scores(self.ctx, out["GL"], self.slab_stride, self.w_e, self.w_k, self.resid,
+                                          score, stream=stream)
+                sel[torch.topk(score, k).indices] = True
+                sel |= ~torch.isfinite(score)
+            idx = torch.nonzero(sel).flatten()
         self.points_redone = int(idx.numel())          # synchronises the stream
         if self.points_redone == 0:
             return
@@ -365,7 +387,7 @@ class RGFSolver:
         wl = self.wl
         assert wl.n_samples == 1
         n_iter = wl.n_scba if n_iter is None else n_iter
-        if math.isfinite(self.point_redo):
+        if self._redo_on():
             graph = False      # the mixed-precision point redo decides on the host after every pass
         if self.sigma_L is None:
             self.lead_selfenergies()
@@ -424,3 +446,191 @@ class RGFDensity(torch.autograd.Function):
     def backward(ctx, grad_n):
         g = ctx.solver.density_vjp(grad_n.contiguous())
         return g, None
+
+
+class NewtonPoisson:
+    """The NEGF-Poisson loop (Eq. 9 iterated with Eqs. 1-8) on one device.
+
+    Unknown: the electron's potential energy V per atom (eV), the onsite
+    potential of Eq. (1).  Residual, on the atom grid (negf_poisson_residual):
+        F(V) = L V - beta (n(V) - N_D),
+    n from the RGF density (Eq. 7) of `solver`, a single-sample RGFSolver.
+    Each Newton step solves (L0 - beta dn/dV) dV = -F by GMRES, right-
+    preconditioned with L0 (conjugate gradients, negf_poisson_solve).  The
+    density's Jacobian enters each Krylov iteration in one of two ways:
+      jacobian="adjoint": one VJP of the adjoint RGF (the solver needs
+        adjoint_segment != 0), i.e. the operator L0 - beta (dn/dV)^T.  In
+        equilibrium (one Fermi level) dn/dV is symmetric -- its (a, b) entry
+        is a sum of Im(G_ab G_ba) terms -- so this is the exact Newton step;
+        under bias the lesser part makes dn/dV non-symmetric, the step is an
+        inexact Newton step and the loop converges linearly to the same root
+        (F is always evaluated exactly);
+      jacobian="fd": the central difference (n(V + h z) - n(V - h z)) / 2h,
+        two forward densities per iteration, exact to O(h^2) with or without
+        bias (h z at most fd_step eV on any atom).
+    A step whose largest change exceeds max_step (eV) is scaled down to it.
+    Every vector operation runs in the library's kernels; the host keeps the
+    small Hessenberg least-squares problem of GMRES."""
+
+    def __init__(self, solver, n_z, n_y, beta, n_d, z_gate=False, v_left=0.0, v_right=0.0, v_gate=0.0,
+                 max_step=0.1, krylov_dim=20, krylov_tol=1e-3, cg_tol=1e-13, jacobian="adjoint",
+                 fd_step=1e-5):
+        wl = solver.wl
+        if wl.n_samples != 1:
+            raise ValueError("the NEGF-Poisson loop runs one device (one sample)")
+        if wl.atoms_per_slab != n_z * n_y:
+            raise ValueError("atoms per slab must equal n_z * n_y")
+        if jacobian not in ("adjoint", "fd"):
+            raise ValueError("jacobian must be 'adjoint' or 'fd'")
+        self.s, self.wl = solver, wl
+        self.mode, self.fd_step = jacobian, float(fd_step)
+        self._V = None
+        self.grid = N.poisson_grid(wl.total_slabs, n_z, n_y, z_gate, v_left, v_right, v_gate)
+        self.n = wl.total_slabs * wl.atoms_per_slab
+        dev = solver.device
+        f64 = dict(dtype=torch.float64, device=dev)
+        self.beta = float(beta)
+        self.nd = torch.as_tensor(np.asarray(n_d, dtype=np.float64).reshape(-1), **f64).contiguous()
+        if self.nd.numel() != self.n:
+            raise ValueError("n_d must hold one value per atom")
+        self.max_step, self.m, self.ktol, self.cg_tol = float(max_step), int(krylov_dim), float(krylov_tol), cg_tol
+        self.pwork = torch.empty(N.negf_poisson_work_bytes(self.grid), dtype=torch.uint8, device=dev)
+        self.vwork = torch.empty(N.negf_vec_work_bytes(self.n, self.m + 1), dtype=torch.uint8, device=dev)
+        self.Q = torch.empty((self.m + 1, self.n), **f64)      # Krylov basis
+        self.Z = torch.empty((self.m, self.n), **f64)          # preconditioned directions L0^-1 q_j
+        self.F = torch.empty(self.n, **f64)
+        self.w = torch.empty(self.n, **f64)
+        self.h = torch.empty(self.m + 1, **f64)
+        self.c = torch.empty(self.m + 1, **f64)
+        self.nrm = torch.empty(2, **f64)
+        self.stats = {"newton": 0, "krylov": 0, "cg": 0, "density_s": 0.0, "jacobian_s": 0.0}
+        self.vp = torch.empty(self.n, **f64)
+
+    # -- small helpers (device kernels; one host read each where noted)
+    def _norms(self, x):
+        N.negf_vec_norms(x, self.nrm, self.vwork)
+        a = self.nrm.cpu().numpy()
+        return math.sqrt(max(float(a[0]), 0.0)), float(a[1])
+
+    def _combine(self, X, coef, b, y):
+        m = len(coef)
+        if m:
+            self.c[:m].copy_(torch.from_numpy(np.asarray(coef, dtype=np.float64)))
+        N.negf_vec_combine(X, m, self.c, b, y)
+
+    def _set_v(self, V):
+        wl = self.wl
+        self.s.set_potential(V.view(wl.total_slabs, wl.atoms_per_slab).repeat_interleave(wl.orbs_per_atom, dim=1))
+
+    def residual(self, V):
+        """F(V) into self.F; returns (F, n)."""
+        import time
+        t = time.perf_counter()
+        self._set_v(V)
+        self._V = V
+        n = self.s.density().reshape(-1).contiguous()
+        torch.cuda.synchronize(self.s.device)
+        self.stats["density_s"] += time.perf_counter() - t
+        N.negf_poisson_residual(self.grid, V, n, self.nd, self.beta, self.F)
+        return self.F, n
+
+    def _jac(self, z, out):
+        """out = L0 z - beta J_n z at the potential of the last residual, J_n
+        = (dn/dV)^T (adjoint) or the central difference of n along z (fd)."""
+        import time
+        N.negf_poisson_apply(self.grid, z, out, with_boundary=False)
+        t = time.perf_counter()
+        if self.mode == "adjoint":
+            g = self.s.density_vjp(z.view(self.wl.total_slabs, -1)).reshape(1, -1).contiguous()
+            self._combine(g, [-self.beta], 1.0, out)
+        else:
+            _, zmax = self._norms(z)
+            h = self.fd_step / max(zmax, 1e-300)
+            dn = []
+            for sgn in (1.0, -1.0):
+                self.vp.copy_(self._V)
+                self._combine(z.view(1, -1), [sgn * h], 1.0, self.vp)
+                self._set_v(self.vp)
+                dn.append(self.s.density().reshape(1, -1).contiguous())
+            self._combine(torch.cat(dn), [-self.beta / (2 * h), self.beta / (2 * h)], 1.0, out)
+            self._set_v(self._V)
+        torch.cuda.synchronize(self.s.device)
+        self.stats["jacobian_s"] += time.perf_counter() - t
+
+    def _precond(self, q, z):
+        it, _ = N.negf_poisson_solve(self.grid, q, z, self.pwork, tol=self.cg_tol, max_iter=20 * self.n + 100)
+        self.stats["cg"] += it
+
+    def _gmres(self, rhs, out):
+        """out ~= J^-1 rhs: one GMRES cycle of at most krylov_dim iterations,
+        classical Gram-Schmidt applied twice, Givens rotations on the host."""
+        m = self.m
+        b0, _ = self._norms(rhs)
+        out.zero_()
+        if b0 == 0.0:
+            return 0
+        self.Q[0].copy_(rhs)
+        self._combine(self.Q, [], 1.0 / b0, self.Q[0])
+        H = np.zeros((m + 1, m))
+        cs, sn = np.zeros(m), np.zeros(m)
+        g = np.zeros(m + 1)
+        g[0] = b0
+        k = 0
+        for j in range(m):
+            self._precond(self.Q[j], self.Z[j])
+            self._jac(self.Z[j], self.w)
+            hj = np.zeros(j + 1)
+            for _ in range(2):
+                N.negf_vec_dots(self.Q, j + 1, self.w, self.h, self.vwork)
+                hh = self.h[:j + 1].cpu().numpy().copy()
+                self._combine(self.Q, list(-hh), 1.0, self.w)
+                hj += hh
+            wn, _ = self._norms(self.w)
+            H[:j + 1, j] = hj
+            H[j + 1, j] = wn
+            for i in range(j):                     # previous rotations
+                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+                H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
+                H[i, j] = t
+            r = math.hypot(H[j, j], H[j + 1, j])
+            cs[j], sn[j] = (H[j, j] / r, H[j + 1, j] / r) if r > 0 else (1.0, 0.0)
+            H[j, j] = r
+            H[j + 1, j] = 0.0
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            k = j + 1
+            self.stats["krylov"] += 1
+            if abs(g[j + 1]) <= self.ktol * b0 or wn == 0.0:
+                break
+            self.Q[j + 1].copy_(self.w)
+            self._combine(self.Q, [], 1.0 / wn, self.Q[j + 1])
+        y = np.zeros(k)
+        for i in range(k - 1, -1, -1):
+            y[i] = (g[i] - H[i, i + 1:k] @ y[i + 1:k]) / H[i, i]
+        self._combine(self.Z, list(y), 0.0, out)
+        return k
+
+    def solve(self, V0, tol=1e-9, max_newton=30, log=None):
+        """Newton iterations from V0 (per atom, [N_x, atoms] or flat) until
+        max |F| <= tol.  Returns (V [N_x, atoms], history of max |F|)."""
+        V = torch.as_tensor(np.asarray(V0, dtype=np.float64) if not torch.is_tensor(V0) else V0,
+                            dtype=torch.float64, device=self.s.device).reshape(-1).clone()
+        dV = torch.empty_like(V)
+        rhs = torch.empty_like(V)
+        hist = []
+        for it in range(max_newton + 1):
+            F, _ = self.residual(V)
+            _, fmax = self._norms(F)
+            hist.append(fmax)
+            if log:
+                log(f"newton {it}: max|F| = {fmax:.3e}")
+            if not math.isfinite(fmax) or fmax <= tol or it == max_newton:
+                break
+            rhs.copy_(F)
+            self._combine(self.Q, [], -1.0, rhs)           # rhs = -F
+            self._gmres(rhs, dV)
+            _, dmax = self._norms(dV)
+            scale = min(1.0, self.max_step / max(dmax, 1e-300))
+            self._combine(dV.view(1, -1), [scale], 1.0, V)
+            self.stats["newton"] += 1
+        return V.view(self.wl.total_slabs, -1), hist

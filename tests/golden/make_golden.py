@@ -1,10 +1,10 @@
 """Write the oracle references of the GPU parity tests whose oracle runs take
 minutes (block 1200, or a chain of SCBA solves at block 240).
 
-    python tests/golden/make_golden.py [slice|full|scba|all]
+    python tests/golden/make_golden.py [slice|full|scba|c4|all]
 
 Calls only the oracle (and the seeded input generators): no value here comes
-from the GPU path.  Two files, each stamped with a SHA-1 of the generated
+from the GPU path.  Each file is stamped with a SHA-1 of the generated
 inputs so a test can tell when the generator has changed since:
 
 * c5_slice.npz -- the paper-shaped cross-section (120 atoms x 10 orbitals,
@@ -22,7 +22,14 @@ inputs so a test can tell when the generator has changed since:
   self-energy update, and the solve with it; orbital diagonals of G^R and G^<
   and their drifts.
 
-The full case takes tens of minutes and ~20 GB of host memory.
+* c4_density.npz -- two alloy samples of the random-alloy ensemble (block 400,
+  their own slab counts, all 256 energies): the electron density per atom
+  (Eq. 7) and the bond current per slab (Eq. 8) of each sample, with their
+  drift over the variants of tests/parity.py.  The reference of the
+  mixed-precision accuracy figures.
+
+The full case takes tens of minutes and ~20 GB of host memory; the C4 case
+about an hour on 8 cores.
 """
 from __future__ import annotations
 
@@ -143,6 +150,54 @@ def scba_case():
     print(f"c3_scba.npz written ({time.time() - t0:.0f} s)", file=sys.stderr)
 
 
+C4_SAMPLES = (0, 1)
+
+
+def _c4_chunk(args):
+    samples, pts, variant, seed = args
+    os.environ.setdefault("OMP_NUM_THREADS", "2")
+    wl = make_workload("C4", samples=list(samples))
+    leads = None
+    if seed is not None:          # inputs and lead self-energies perturbed as in tests/parity.py
+        w = P._perturbed(wl, seed)
+        leads = P.perturbed_leads(wl, pts, seed, w)
+        wl = w
+    res = O.solve_points(wl, pts, variant=variant, leads=leads, diag_only=True)
+    return [r["GL"] for r in res], [r["bond"] for r in res]
+
+
+def c4_case(workers=4):
+    """Per-sample density and current of two alloy samples, and their drift over
+    the same variants as tests/parity.py (the alternative association and
+    N_PERTURB perturbed inputs), each variant's points spread over a process
+    pool in 16 fixed chunks."""
+    from concurrent.futures import ProcessPoolExecutor
+    wl = make_workload("C4", samples=list(C4_SAMPLES))
+    pts = [(s, 0, e) for s in range(wl.n_samples) for e in range(wl.n_e)]
+    t0 = time.time()
+    out = {"inputs_sha1": inputs_sha1(wl), "samples": np.array(C4_SAMPLES),
+           "slab_offset": wl.slab_offset.copy()}
+    chunks = [pts[i::16] for i in range(16)]
+    variants = [("ref", None, None), ("alt", "alt", None)] + [(f"perturb{k}", None, k) for k in range(P.N_PERTURB)]
+    res = {}
+    with ProcessPoolExecutor(workers) as ex:
+        for name, variant, seed in variants:
+            GL, bond = [None] * len(pts), [None] * len(pts)
+            jobs = [(C4_SAMPLES, c, variant, None if seed is None else seed * 100 + ci) for ci, c in enumerate(chunks)]
+            for ci, (gl, bd) in enumerate(ex.map(_c4_chunk, jobs)):
+                for j, (g, b) in enumerate(zip(gl, bd)):
+                    GL[ci + 16 * j], bond[ci + 16 * j] = g, b
+            n, J, _ = O.observables(wl, pts, GL, bond)
+            res[name] = (n, J)
+            print(f"  c4 {name} done ({time.time() - t0:.0f} s)", file=sys.stderr, flush=True)
+    n, J = res.pop("ref")
+    out["n"], out["J"] = n, J
+    out["drift_n"] = np.array(max(P.rel(v[0], n) for v in res.values()))
+    out["drift_J"] = np.array(max(P.rel(v[1], J) for v in res.values()))
+    np.savez_compressed(os.path.join(HERE, "c4_density.npz"), **out)
+    print(f"c4_density.npz written ({time.time() - t0:.0f} s)", file=sys.stderr)
+
+
 if __name__ == "__main__":
     what = sys.argv[1] if len(sys.argv) > 1 else "all"
     if what in ("slice", "all"):
@@ -151,3 +206,5 @@ if __name__ == "__main__":
         full_case()
     if what in ("scba", "all"):
         scba_case()
+    if what in ("c4", "all"):
+        c4_case()

@@ -601,3 +601,17 @@ def test_newton_poisson_pinned_by_its_residual():
     x = np.arange(wl.total_slabs)
     lin = np.repeat(-0.05 * (x + 1) / (wl.total_slabs + 1), 2).reshape(V0.shape)
     assert np.max(np.abs(V0 - lin)) < 1e-12
+
+
+def test_density_jacobian_symmetric_in_equilibrium_only():
+    """One Fermi level for both leads and the eta sink: dn/dV is symmetric (its
+    entries are sums of Im(G_ab G_ba)); under bias it is not."""
+    import dataclasses
+    wl = _poisson_tiny()
+    pts = [(0, 0, e) for e in range(wl.n_e)]
+    v = np.random.default_rng(2).uniform(0.0, 0.1, size=(wl.total_slabs, wl.atoms_per_slab))
+    eq = dataclasses.replace(wl, mu_R=wl.mu_L)
+    D = O.density_jacobian(eq, v, pts, O.lead_tables(eq), eta_fill=eq.mu_L)
+    assert np.max(np.abs(D - D.T)) < 1e-12 * np.max(np.abs(D))
+    Db = O.density_jacobian(wl, v, pts, O.lead_tables(wl))
+    assert np.max(np.abs(Db - Db.T)) > 1e-3 * np.max(np.abs(Db))
