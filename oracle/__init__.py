@@ -19,6 +19,7 @@ from .negf_oracle import (  # noqa: F401
     scba_selfenergy,
     solve_points,
     lead_tables,
+    cap_selfenergy,
     scba,
     observables,
     dense_grad,

@@ -347,11 +347,41 @@ def scba_selfenergy(GRd, GLd, w_k, D_ac, M_op, shift, n_bose):
 # Drivers over many points
 # ---------------------------------------------------------------------------
 
+def cap_selfenergy(wl):
+    """Contact self-energies of a workload whose contacts are complex
+    absorbing potentials (the paper's treatment of random-alloy leads, in the
+    paragraph after Eq. 6, whose form it does not give; reading: an imaginary
+    onsite potential -i W on every orbital of a contact slab, and the
+    reservoir injection that the fluctuation-dissipation relation pairs with
+    it, Sigma^< = -(Sigma^R - Sigma^A) f = 2 i W f(E; mu of that contact)).
+    Returns (Sigma^R, Sigma^<), each [n_e, total_slabs, nb], orbital-diagonal.
+    Pinned by: ordered devices reproduce the Sancho-Rubio transmission, and
+    the equilibrium (KMS) identity."""
+    W = np.asarray(wl.cap_w, dtype=np.float64)
+    side = np.asarray(wl.cap_side)
+    sR = np.zeros((wl.n_e, wl.total_slabs, wl.nb), dtype=np.complex128)
+    sL = np.zeros_like(sR)
+    for ie, E in enumerate(wl.energy):
+        fL = float(fermi(E, wl.mu_L, wl.kT))
+        fR = float(fermi(E, wl.mu_R, wl.kT))
+        for i in range(wl.total_slabs):
+            if W[i] == 0.0:
+                continue
+            f = fL if side[i] < 0 else fR
+            sR[ie, i, :] = -1j * W[i]
+            sL[ie, i, :] = 2j * W[i] * f
+    return sR, sL
+
+
 def lead_tables(wl, tol=1e-14, max_iter=100, ks=None, es=None, variant=None):
-    """Sigma_L, Sigma_R for the (k, E) grid (or the listed subsets)."""
+    """Sigma_L, Sigma_R for the (k, E) grid (or the listed subsets).  Zero
+    for a workload with absorbing-potential contacts (no semi-infinite leads)."""
     ks = range(wl.n_k) if ks is None else ks
     es = range(wl.n_e) if es is None else es
     out = {}
+    if getattr(wl, "cap_w", None) is not None:
+        z0 = np.zeros((wl.nb, wl.nb), dtype=np.complex128)
+        return {(ik, ie): (z0, z0, 0, 0) for ik in ks for ie in es}
     for ik in ks:
         for ie in es:
             z = wl.energy[ie] + 1j * wl.eta
@@ -369,6 +399,10 @@ def solve_points(wl, points, leads=None, scatR=None, scatL=None, transmission=Fa
     if leads is None:
         leads = lead_tables(wl, ks=sorted({int(p[1]) for p in points}),
                             es=sorted({int(p[2]) for p in points}), variant=variant)
+    if getattr(wl, "cap_w", None) is not None:       # absorbing contacts enter as self-energies
+        cR, cL = cap_selfenergy(wl)
+        scatR = cR if scatR is None else scatR + cR
+        scatL = cL if scatL is None else scatL + cL
     res = []
     for s, ik, ie in points:
         hd, hu, v = wl.sample_blocks(int(s), int(ik))

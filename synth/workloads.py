@@ -80,6 +80,9 @@ class Workload:
     shift: int = 0
     n_bose: float = 0.0
     n_scba: int = 0
+    # complex absorbing potential contacts (None: Sancho-Rubio leads)
+    cap_w: Optional[np.ndarray] = None      # float64 [total_slabs] absorbing strength W per slab (eV)
+    cap_side: Optional[np.ndarray] = None   # int8 [total_slabs]: -1 left contact region, +1 right, 0 device
 
     @property
     def n_samples(self) -> int:
@@ -242,9 +245,57 @@ def _smooth_potential(rng, n_slab, n_z, n_y, vmax=0.3):
     return v.reshape(n_slab, n_z * n_y)
 
 
+def cap_profile(n_dev: int, n_cap: int, w_max: float, power: float = 2.0):
+    """Absorbing strength and side of every slab of one sample extended by
+    n_cap contact slabs on each side: W = w_max (d / n_cap)^power at depth d =
+    1..n_cap into a contact region, 0 in the n_dev device slabs."""
+    n = n_dev + 2 * n_cap
+    w = np.zeros(n)
+    side = np.zeros(n, dtype=np.int8)
+    for d in range(1, n_cap + 1):
+        v = w_max * (d / n_cap) ** power
+        w[n_cap - d], side[n_cap - d] = v, -1
+        w[n_cap + n_dev - 1 + d], side[n_cap + n_dev - 1 + d] = v, 1
+    return w, side
+
+
+def with_cap(wl: Workload, n_cap: int, w_max: float, power: float = 2.0) -> Workload:
+    """The workload with its ordered leads made explicit: every sample gets
+    n_cap slabs of lead material on each side (onsite blocks lead_h00, the
+    leads' couplings), carrying the absorbing profile of ``cap_profile`` --
+    the complex-absorbing-potential stand-in for the semi-infinite leads."""
+    counts = np.diff(wl.slab_offset)
+    hd, hu, vv, ww, ss = [], [], [], [], []
+    for smp in range(wl.n_samples):
+        a0, a1 = int(wl.slab_offset[smp]), int(wl.slab_offset[smp + 1])
+        n = a1 - a0
+        lead = np.repeat(wl.lead_h00[:, None], n_cap, axis=1)
+        hd.append(np.concatenate([lead, wl.h_diag[:, a0:a1], lead], axis=1))
+        up = np.zeros((n + 2 * n_cap, wl.nb, wl.nb), dtype=np.complex128)
+        # left contact slabs: H_{j,j+1} = (h01_L)^dagger inside, tau_L^dagger onto the device
+        up[:n_cap - 1] = wl.lead_h01_L.conj().T
+        up[n_cap - 1] = wl.lead_tau_L.conj().T
+        up[n_cap:n_cap + n - 1] = wl.h_up[a0:a1 - 1]
+        up[n_cap + n - 1] = wl.lead_tau_R
+        up[n_cap + n:n + 2 * n_cap - 1] = wl.lead_h01_R
+        hu.append(up)
+        if wl.v_onsite is not None:
+            z = np.zeros((n_cap, wl.nb))
+            vv.append(np.concatenate([z, wl.v_onsite[a0:a1], z]))
+        w, side = cap_profile(n, n_cap, w_max, power)
+        ww.append(w)
+        ss.append(side)
+    off = np.concatenate([[0], np.cumsum(counts + 2 * n_cap)]).astype(np.int64)
+    return dataclasses.replace(
+        wl, slab_offset=off, h_diag=np.concatenate(hd, axis=1), h_up=np.concatenate(hu),
+        v_onsite=np.concatenate(vv) if vv else None, species=None,
+        cap_w=np.concatenate(ww), cap_side=np.concatenate(ss))
+
+
 def cross_section_workload(name: str, n_z: int, n_y: int, n_slabs, n_k: int, energy: np.ndarray,
                            seed: int, ge_fraction: float = 0.1, potential: bool = False,
-                           eta: float = 1e-6, samples=None, **params) -> Workload:
+                           eta: float = 1e-6, samples=None, cap_slabs: int = 0, cap_w: float = 1.0,
+                           cap_power: float = 2.0, **params) -> Workload:
     """Si/Ge cross-section device.  ``n_slabs`` is one slab count per sample.
 
     Ge sites are drawn per sample (own seeded stream), exactly
@@ -252,12 +303,18 @@ def cross_section_workload(name: str, n_z: int, n_y: int, n_slabs, n_k: int, ene
     interior slabs 2..N-1; the two edge slabs stay pure Si so that the
     ordered pure-Si leads (and their self-energies) are shared by all samples.
     ``samples`` restricts generation to a subset of sample indices (the draws of
-    each sample do not depend on the others)."""
+    each sample do not depend on the others).
+    ``cap_slabs`` > 0: disordered contacts -- every sample is extended by that
+    many slabs on each side, the random alloy runs through them (Ge drawn among
+    all slabs, own stream), and they carry the absorbing profile of
+    ``cap_profile`` instead of ordered leads."""
     E, C = _material(seed)
     nat = n_z * n_y
     nb = nat * ORB
     n_slabs = list(n_slabs)
     sample_ids = list(range(len(n_slabs))) if samples is None else list(samples)
+    if cap_slabs > 0:
+        n_slabs = [n + 2 * cap_slabs for n in n_slabs]
     counts = [n_slabs[s] for s in sample_ids]
     slab_offset = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
     total = int(slab_offset[-1])
@@ -265,6 +322,14 @@ def cross_section_workload(name: str, n_z: int, n_y: int, n_slabs, n_k: int, ene
     species = np.zeros((total, nat), dtype=np.int8)
     for j, s in enumerate(sample_ids):
         n = n_slabs[s]
+        if cap_slabs > 0:          # the alloy runs through the contact regions
+            rng = np.random.default_rng([seed, 1000 + s, 7])
+            n_ge = int(round(ge_fraction * n * nat))
+            sp = np.zeros(n * nat, dtype=np.int8)
+            sp[rng.choice(n * nat, size=n_ge, replace=False)] = 1
+            blk = sp.reshape(n, nat)
+            species[slab_offset[j]:slab_offset[j + 1]] = blk
+            continue
         rng = np.random.default_rng([seed, 1000 + s])
         interior = max(n - 2, 0) * nat
         n_ge = int(round(ge_fraction * interior))
@@ -301,7 +366,13 @@ def cross_section_workload(name: str, n_z: int, n_y: int, n_slabs, n_k: int, ene
         v_atom = np.concatenate([vfull[s] for s in sample_ids], axis=0)
         v_onsite = np.repeat(v_atom, ORB, axis=1)
     de = float(energy[1] - energy[0]) if len(energy) > 1 else 1.0
+    cw = cs = None
+    if cap_slabs > 0:
+        prof = [cap_profile(n_slabs[s] - 2 * cap_slabs, cap_slabs, cap_w, cap_power) for s in sample_ids]
+        cw = np.concatenate([p[0] for p in prof])
+        cs = np.concatenate([p[1] for p in prof])
     return Workload(
+        cap_w=cw, cap_side=cs,
         name=name, seed=seed, nb=nb, orbs_per_atom=ORB, slab_offset=slab_offset,
         kpts=kpts, w_k=np.full(n_k, 1.0 / n_k), energy=np.asarray(energy, dtype=np.float64),
         w_e=np.full(len(energy), de), h_diag=h_diag, h_up=h_up, up_block=ORB,

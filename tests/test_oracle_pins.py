@@ -615,3 +615,56 @@ def test_density_jacobian_symmetric_in_equilibrium_only():
     assert np.max(np.abs(D - D.T)) < 1e-12 * np.max(np.abs(D))
     Db = O.density_jacobian(wl, v, pts, O.lead_tables(wl))
     assert np.max(np.abs(Db - Db.T)) > 1e-3 * np.max(np.abs(Db))
+
+
+# ---------------------------------------------------------------------------
+# Complex-absorbing-potential contacts
+# ---------------------------------------------------------------------------
+
+def _cap_vs_leads(wl, energies, n_cap=80, w_max=1.0):
+    """Bond current at the central device bond with absorbing contacts and
+    with the exact (Sancho-Rubio) leads, for a wide bias window."""
+    import dataclasses
+    from synth.workloads import with_cap
+    wl = dataclasses.replace(wl, energy=np.asarray(energies, dtype=np.float64), mu_L=6.0, mu_R=-6.0,
+                             eta=1e-9)
+    pts = [(0, 0, e) for e in range(len(energies))]
+    exact = O.solve_points(wl, pts)
+    capw = with_cap(wl, n_cap, w_max)
+    cap = O.solve_points(capw, pts)
+    mid = wl.total_slabs // 2
+    return (np.array([r["bond"][mid] for r in exact]), np.array([r["bond"][n_cap + mid] for r in cap]))
+
+
+def test_cap_contacts_reproduce_sancho_rubio_on_ordered_strip():
+    """Long, smooth absorbing contacts on an ordered strip: the current is the
+    exact open-boundary (Landauer) one to within the contacts' reflection."""
+    wl = strip_workload(n_slab=6, disorder=0.0, n_e=4)
+    ex, cap = _cap_vs_leads(wl, [-2.1, -0.7, 0.3, 1.9])
+    assert np.all(np.abs(ex) > 1.0)
+    assert np.max(np.abs(cap - ex) / np.abs(ex)) < 2e-3
+
+
+def test_cap_contacts_reproduce_sancho_rubio_on_ordered_cross_section():
+    """The same on a pure-Si cross-section, whose slab couplings are not
+    symmetric: pins the orientation of the contact couplings too."""
+    from synth.workloads import cross_section_workload
+    wl = cross_section_workload("cap", 1, 2, [4], 1, np.zeros(1), 7, ge_fraction=0.0)
+    ex, cap = _cap_vs_leads(wl, [-1.0, -0.1, 0.5, 1.2])     # 1, 2, 1, 1 open channels
+    assert np.all(np.abs(ex) > 0.5)
+    assert np.max(np.abs(cap - ex) / np.abs(ex)) < 1e-4
+
+
+def test_cap_contacts_equilibrium_kms():
+    """One Fermi level for both contacts and the eta sink: G^< = -f (G - G^dagger)
+    on every slab of a disordered device with disordered absorbing contacts."""
+    import dataclasses
+    from synth.workloads import cross_section_workload
+    wl = cross_section_workload("cap", 1, 2, [5], 1, np.linspace(-1, 1, 3), 11, cap_slabs=6, cap_w=0.5)
+    wl = dataclasses.replace(wl, mu_R=wl.mu_L, eta=1e-3)
+    pts = [(0, 0, e) for e in range(wl.n_e)]
+    res = O.solve_points(wl, pts, eta_fill=wl.mu_L)
+    for (s, k, e), r in zip(pts, res):
+        f = float(O.fermi(wl.energy[e], wl.mu_L, wl.kT))
+        A = r["GR"] - np.conj(np.swapaxes(r["GR"], 1, 2))
+        assert np.max(np.abs(r["GL"] + f * A)) < 1e-12 * np.max(np.abs(A))
