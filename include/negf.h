@@ -354,6 +354,23 @@ int negf_set_mixed_threshold(negf_ctx* ctx, double thr);
  * forward sweep yet), NEGF_ESHAPE (n larger than the sweep). */
 int negf_mixed_point_residuals(negf_ctx* ctx, void* stream, int n, double* out);
 
+/* Absorbing-potential contacts (the paper treats random-alloy leads with a
+ * complex absorbing potential, paragraph after Eq. 6): the contact regions are
+ * slabs of the bound device itself, each carrying an imaginary onsite potential
+ * -i W on every orbital, and each contact region is a reservoir at its lead's
+ * Fermi level.  Writes, for every energy e, global slab s and orbital o,
+ *   scat_R[e][s][o] = -i W_s,   scat_L[e][s][o] = 2 i W_s f(E_e; mu_side(s), kT)
+ * (the fluctuation-dissipation pair of an absorbing self-energy), to be passed
+ * as the scat_R / scat_L of negf_rgf_forward / negf_rgf_solve together with
+ * ZERO lead self-energy tables (no semi-infinite leads).  w_slab: DEVICE
+ * [total_slabs] W >= 0 (0 in the device region); side: DEVICE int [total_slabs],
+ * < 0 for the left contact (mu_L), otherwise mu_R.  Outputs: DEVICE
+ * [n_e][total_slabs][nb] complex128, every entry written.  The Caroli
+ * transmission is not defined for such contacts; currents come from the bond
+ * currents (Eq. 8).  Errors: NEGF_EINVAL (NULL), NEGF_ESTATE (no bound system). */
+int negf_cap_selfenergy(negf_ctx* ctx, void* stream, const double* w_slab, const int* side,
+                        negf_c128* scat_R, negf_c128* scat_L);
+
 /* Mixed precision: a redo score for every bound point p (the bind's order),
  * written to the DEVICE array score[n_points] on `stream`:
  *   score[p] = resid[p] * w_e[e_p] * w_k[k_p] * max_j |Im G^<_jj(p)|,

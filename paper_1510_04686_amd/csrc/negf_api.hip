@@ -324,6 +324,26 @@ __global__ void zero_d_kernel(double* p, int n) {
     if (i < n) p[i] = 0.0;
 }
 
+// Absorbing-potential contact self-energies, one thread per (energy, slab,
+// orbital): Sigma^R = -i W_s, Sigma^< = 2 i W_s f(E; mu of the slab's contact).
+__global__ __launch_bounds__(256) void cap_kernel(const double* energy, int n_e, long long total, int n,
+                                                  const double* w, const int* side, double muL, double muR,
+                                                  double kT, double2* sR, double2* sL) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    const long long per_e = total * n;
+    if (i >= per_e * n_e) return;
+    const int ie = (int)(i / per_e);
+    const long long s = (i - ie * per_e) / n;
+    const double W = w[s];
+    double f = 0.0;
+    if (W != 0.0) {
+        const double mu = side[s] < 0 ? muL : muR;
+        f = 1.0 / (1.0 + exp((energy[ie] - mu) / kT));
+    }
+    sR[i] = make_double2(0.0, -W);
+    sL[i] = make_double2(0.0, 2.0 * W * f);
+}
+
 // Mixed precision: per-point redo score = (largest block refinement residual of
 // the point) x (its energy and k weights) x (largest |Im G^<_jj| over its
 // orbitals), i.e. the residual times the point's largest contribution to the
@@ -1303,6 +1323,19 @@ int negf_mixed_point_scores(negf_ctx* c, void* stream, const negf_c128* GL, int 
     if (slab_stride < maxN) return NEGF_EINVAL;
     hipLaunchKernelGGL(mixed_score_kernel, dim3(c->n_points), dim3(256), 0, (hipStream_t)stream,
                        reinterpret_cast<const double2*>(GL), slab_stride, c->nb, c->desc_d, w_e, w_k, resid, score);
+    NEGF_HIP_CHECK(hipGetLastError());
+    return NEGF_OK;
+}
+
+int negf_cap_selfenergy(negf_ctx* c, void* stream, const double* w_slab, const int* side, negf_c128* scat_R,
+                        negf_c128* scat_L) {
+    if (!c || !w_slab || !side || !scat_R || !scat_L) return NEGF_EINVAL;
+    if (!c->bound) return NEGF_ESTATE;
+    const long long total = c->soff_h.back();
+    const long long m = (long long)c->sys.n_e * total * c->nb;
+    hipLaunchKernelGGL(cap_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                       c->sys.energy, c->sys.n_e, total, c->nb, w_slab, side, c->sys.mu_L, c->sys.mu_R, c->sys.kT,
+                       reinterpret_cast<double2*>(scat_R), reinterpret_cast<double2*>(scat_L));
     NEGF_HIP_CHECK(hipGetLastError());
     return NEGF_OK;
 }

@@ -64,7 +64,7 @@ EXPORTS = [
     "negf_create", "negf_destroy", "negf_workspace_bytes", "negf_sync_status", "negf_error_string",
     "negf_bind", "negf_lead_selfenergy", "negf_lead_selfenergy_pair", "negf_rgf_forward", "negf_rgf_backward",
     "negf_scba_selfenergy", "negf_observables", "negf_rgf_adjoint", "negf_zgemm_batched", "negf_zinv_batched", "negf_mixed_stats",
-    "negf_set_mixed_threshold", "negf_mixed_point_residuals", "negf_mixed_point_scores", "negf_gemm_timing_enable", "negf_gemm_timing", "negf_get_tuning", "negf_set_tuning", "negf_autotune",
+    "negf_set_mixed_threshold", "negf_mixed_point_residuals", "negf_mixed_point_scores", "negf_cap_selfenergy", "negf_gemm_timing_enable", "negf_gemm_timing", "negf_get_tuning", "negf_set_tuning", "negf_autotune",
     "negf_build_id", "negf_scba_history", "negf_rgf_solve", "negf_zinv_noalloc_bytes", "negf_zinv_batched_noalloc",
     "negf_poisson_apply", "negf_poisson_residual", "negf_poisson_work_bytes", "negf_poisson_solve",
     "negf_vec_work_bytes", "negf_vec_dots", "negf_vec_combine", "negf_vec_norms",
@@ -110,6 +110,7 @@ def lib():
         "negf_set_mixed_threshold": (i, [vp, d]),
         "negf_mixed_point_residuals": (i, [vp, vp, i, vp]),
         "negf_mixed_point_scores": (i, [vp, vp, vp, i, vp, vp, vp, vp]),
+        "negf_cap_selfenergy": (i, [vp, vp, vp, vp, vp, vp]),
         "negf_gemm_timing_enable": (i, [vp, i]),
         "negf_gemm_timing": (i, [vp, vp, POINTER(ll), POINTER(d), POINTER(d), POINTER(d)]),
         "negf_get_tuning": (i, [vp, POINTER(negf_tuning)]),
@@ -363,6 +364,14 @@ def negf_mixed_point_residuals(ctx, out, n=None, stream=None):
     n = out.numel() if n is None else int(n)
     _check("negf_mixed_point_residuals",
            lib().negf_mixed_point_residuals(ctx.handle, _stream(stream), n, _ptr(out, torch.float64, "out")))
+
+
+def negf_cap_selfenergy(ctx, w_slab, side, scat_R, scat_L, stream=None):
+    """Absorbing-contact self-energies into scat_R / scat_L [n_e][total_slabs][nb]."""
+    _check("negf_cap_selfenergy",
+           lib().negf_cap_selfenergy(ctx.handle, _stream(stream), _ptr(w_slab, torch.float64, "w_slab"),
+                                     _ptr(side, torch.int32, "side"), _ptr(scat_R, torch.complex128, "scat_R"),
+                                     _ptr(scat_L, torch.complex128, "scat_L")))
 
 
 def negf_mixed_point_scores(ctx, GL, slab_stride, w_e, w_k, resid, score, stream=None):

@@ -73,6 +73,12 @@ class RGFSolver:
         self.h_diag = _dev(wl.h_diag, c128, self.device)
         self.h_up = _dev(wl.h_up, c128, self.device)
         self.energy = _dev(wl.energy, f64, self.device)
+        # absorbing-potential contacts instead of semi-infinite leads
+        self.cap = getattr(wl, "cap_w", None) is not None
+        self.cap_R = self.cap_L = None
+        if self.cap:
+            self.cap_w = _dev(np.asarray(wl.cap_w, dtype=np.float64), f64, self.device)
+            self.cap_side = torch.from_numpy(np.asarray(wl.cap_side, dtype=np.int32)).to(self.device)
         self.w_e = _dev(wl.w_e, f64, self.device)
         self.w_k = _dev(wl.w_k, f64, self.device)
         self.v = None if wl.v_onsite is None else _dev(wl.v_onsite, f64, self.device)
@@ -190,11 +196,36 @@ class RGFSolver:
             out.append((int(ik), int(es.min()), int(es.max()) + 1))
         return out
 
+    def _cap_contacts(self):
+        """Zero lead tables and the absorbing contacts' self-energies
+        (negf_cap_selfenergy), once: they depend on neither k nor the batch."""
+        self._alloc_lead_tables()
+        if self.cap_R is None:
+            wl = self.wl
+            shp = (wl.n_e, wl.total_slabs, wl.nb)
+            self.cap_R = torch.empty(shp, dtype=torch.complex128, device=self.device)
+            self.cap_L = torch.empty(shp, dtype=torch.complex128, device=self.device)
+            N.negf_cap_selfenergy(self.ctx, self.cap_w, self.cap_side, self.cap_R, self.cap_L)
+        self.lead_status, self.lead_dual = 0, 0
+        return self.sigma_L, self.sigma_R
+
+    def _scat(self, scat_R, scat_L):
+        if not self.cap:
+            return scat_R, scat_L
+        if scat_R is not None or scat_L is not None:
+            raise NotImplementedError("scattering self-energies on top of absorbing contacts")
+        if self.cap_R is None:
+            self._cap_contacts()
+        return self.cap_R, self.cap_L
+
     def lead_selfenergies_for(self, p0, np_, tol=1e-14, max_iter=100):
         """Lead self-energies of only the (k, E) points that the batch [p0, p0 + np_)
         reads, written into their slots of the full tables (one shared
         decimation call per k-point of the batch).  Returns the (ik, e0, e1)
         ranges computed."""
+        if self.cap:
+            self._cap_contacts()
+            return []
         self._alloc_lead_tables()
         ranges = self.lead_ranges(p0, np_)
         status, dual = 0, 1
@@ -210,6 +241,8 @@ class RGFSolver:
         return ranges
 
     def lead_selfenergies(self, tol=1e-14, max_iter=100, shared_decimation=True):
+        if self.cap:
+            return self._cap_contacts()
         self.sigma_L = None
         self._alloc_lead_tables()
         wl = self.wl
@@ -246,6 +279,7 @@ class RGFSolver:
     def run_batch(self, out, p0, np_, full_blocks=False, want_T=False, scat_R=None, scat_L=None, stream=None):
         """Forward + backward sweep of one batch of bound points on the first
         lane's context (the mixed-precision point redo is not applied)."""
+        scat_R, scat_L = self._scat(scat_R, scat_L)
         flags = N.NEGF_WANT_TRANSMISSION if want_T else 0
         N.negf_rgf_solve(self.ctx, p0, np_, self.sigma_L, self.sigma_R, scat_R, scat_L, flags, out.get("GR"),
                          out.get("GL"), out.get("GG"), int(full_blocks), self.slab_stride, out.get("bond"),
@@ -255,6 +289,7 @@ class RGFSolver:
             N.negf_mixed_point_residuals(self.ctx, self.resid[p0:p0 + np_], stream=stream)
 
     def run_batches(self, out, full_blocks=False, want_T=False, scat_R=None, scat_L=None, stream=None):
+        scat_R, scat_L = self._scat(scat_R, scat_L)
         flags = N.NEGF_WANT_TRANSMISSION if want_T else 0
         base = torch.cuda.current_stream(self.device) if stream is None else stream
         if self.lanes > 1:
@@ -362,7 +397,7 @@ class RGFSolver:
             batches.insert(0, self._last_fwd)
         for p0, np_ in batches:
             if self._last_fwd != (p0, np_):
-                N.negf_rgf_forward(self.ctx, p0, np_, self.sigma_L, self.sigma_R)
+                N.negf_rgf_forward(self.ctx, p0, np_, self.sigma_L, self.sigma_R, *self._scat(None, None))
                 self._last_fwd = (p0, np_)
             N.negf_rgf_adjoint(self.ctx, p0, np_, w_orb, dX, self.slab_stride)
         g, _, _ = self.observables(dX, None)
