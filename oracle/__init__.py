@@ -17,6 +17,8 @@ from .negf_oracle import (  # noqa: F401
     rgf,
     dense,
     scba_selfenergy,
+    scat_matrix,
+    atom_blocks,
     solve_points,
     lead_tables,
     cap_selfenergy,

@@ -133,6 +133,31 @@ def lead_lesser(sigma, f):
 # RGF (Eqs. 1-2 solved block-tridiagonally) -- the plain recursions
 # ---------------------------------------------------------------------------
 
+def scat_matrix(s):
+    """The b x b self-energy block of one slab from its stored form: an
+    orbital diagonal [b], or atom blocks [b, opa] (row o holds the entries of o
+    with the orbitals of its own atom: a block-diagonal matrix with opa x opa
+    blocks on the diagonal)."""
+    s = np.asarray(s)
+    if s.ndim == 1:
+        return np.diag(s)
+    b, opa = s.shape
+    M = np.zeros((b, b), dtype=np.complex128)
+    for a0 in range(0, b, opa):
+        M[a0:a0 + opa, a0:a0 + opa] = s[a0:a0 + opa]
+    return M
+
+
+def atom_blocks(X, opa):
+    """[..., b, b] diagonal blocks -> their atom blocks [..., b, opa]."""
+    X = np.asarray(X)
+    b = X.shape[-1]
+    out = np.zeros(X.shape[:-1] + (opa,), dtype=X.dtype)
+    for a0 in range(0, b, opa):
+        out[..., a0:a0 + opa, :] = X[..., a0:a0 + opa, a0:a0 + opa]
+    return out
+
+
 def _assemble(hd, z, sigL, sigR, v, scatR):
     N = len(hd)
     b = hd[0].shape[0]
@@ -142,7 +167,7 @@ def _assemble(hd, z, sigL, sigR, v, scatR):
         if v is not None:
             a = a - np.diag(v[i])
         if scatR is not None:
-            a = a - np.diag(scatR[i])
+            a = a - scat_matrix(scatR[i])
         A.append(a)
     A[0] = A[0] - sigL
     A[N - 1] = A[N - 1] - sigR
@@ -154,7 +179,7 @@ def _lesser_sources(N, b, sigL, sigR, fL, fR, scatL, eta, eta_fill):
     for i in range(N):
         s = np.zeros((b, b), dtype=np.complex128)
         if scatL is not None:
-            s = s + np.diag(scatL[i])
+            s = s + scat_matrix(scatL[i])
         if eta_fill is not None:
             s = s + 2j * eta * eta_fill * np.eye(b)
         S.append(s)
@@ -420,26 +445,35 @@ def solve_points(wl, points, leads=None, scatR=None, scatL=None, transmission=Fa
     return res
 
 
-def scba(wl, n_iter, leads=None, eta_fill=None, tol=None):
+def scba(wl, n_iter, leads=None, eta_fill=None, tol=None, atom_block_sigma=False):
     """Self-consistent Born loop (Eqs. 1-6) for a single-sample workload.
 
     Sigma_scat starts at zero (ballistic first pass); each iteration solves all
     (k, E) points with the current Sigma_scat, then rebuilds Sigma_scat from the
-    orbital diagonals (no mixing).  Runs ``n_iter`` iterations, or stops early
-    once ||dSigma|| / ||Sigma|| < tol when ``tol`` is given.  Returns the last
-    solution's diagonals and the residual history."""
+    orbital diagonals (no mixing) -- or, with ``atom_block_sigma``, from the atom
+    blocks (orbs_per_atom x orbs_per_atom) of the diagonal blocks, the other
+    reading of "diag G" in Eqs. (4)-(6): Sigma_scat is then block-diagonal
+    with one block per atom, each entry given by the same formulas.  Runs
+    ``n_iter`` iterations, or stops early once ||dSigma|| / ||Sigma|| < tol
+    when ``tol`` is given.  Returns the last solution's diagonals (or atom
+    blocks) and the residual history."""
     assert wl.n_samples == 1
     N, b = wl.total_slabs, wl.nb
     if leads is None:
         leads = lead_tables(wl)
     pts = [(0, ik, ie) for ik in range(wl.n_k) for ie in range(wl.n_e)]
-    scatR = np.zeros((wl.n_e, N, b), dtype=np.complex128)
-    scatL = np.zeros((wl.n_e, N, b), dtype=np.complex128)
+    tail = (b, wl.orbs_per_atom) if atom_block_sigma else (b,)
+    scatR = np.zeros((wl.n_e, N) + tail, dtype=np.complex128)
+    scatL = np.zeros((wl.n_e, N) + tail, dtype=np.complex128)
+    if atom_block_sigma:
+        pick = lambda X: atom_blocks(X, wl.orbs_per_atom)
+    else:
+        pick = lambda X: np.diagonal(X, axis1=1, axis2=2)
     hist = []
     for _ in range(n_iter):
         res = solve_points(wl, pts, leads, scatR, scatL, eta_fill=eta_fill)
-        GRd = np.array([np.diagonal(r["GR"], axis1=1, axis2=2) for r in res]).reshape(wl.n_k, wl.n_e, N, b)
-        GLd = np.array([np.diagonal(r["GL"], axis1=1, axis2=2) for r in res]).reshape(wl.n_k, wl.n_e, N, b)
+        GRd = np.array([pick(r["GR"]) for r in res]).reshape((wl.n_k, wl.n_e, N) + tail)
+        GLd = np.array([pick(r["GL"]) for r in res]).reshape((wl.n_k, wl.n_e, N) + tail)
         newR, newL = scba_selfenergy(GRd, GLd, wl.w_k, wl.D_ac, wl.M_op, wl.shift, wl.n_bose)
         num = np.linalg.norm(newR - scatR) ** 2 + np.linalg.norm(newL - scatL) ** 2
         den = np.linalg.norm(newR) ** 2 + np.linalg.norm(newL) ** 2

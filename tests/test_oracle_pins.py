@@ -668,3 +668,83 @@ def test_cap_contacts_equilibrium_kms():
         f = float(O.fermi(wl.energy[e], wl.mu_L, wl.kT))
         A = r["GR"] - np.conj(np.swapaxes(r["GR"], 1, 2))
         assert np.max(np.abs(r["GL"] + f * A)) < 1e-12 * np.max(np.abs(A))
+
+
+# ---------------------------------------------------------------------------
+# Atom-block local scattering self-energies (the other reading of "diag G")
+# ---------------------------------------------------------------------------
+
+def _tiny_block_scba(seed=5, n_e=9, shift=2, D=0.02, M=0.03, eta=0.05, n_y=2):
+    import dataclasses
+    from synth.workloads import cross_section_workload
+    energy = np.linspace(-0.2, 0.2, n_e)
+    hw = shift * (energy[1] - energy[0])            # the phonon energy on the grid, Bose factor at kT
+    wl = cross_section_workload("blk", 1, n_y, [3], 1, energy, seed, eta=eta, D_ac=D, M_op=M, hw_op=hw,
+                                shift=shift, n_bose=1.0 / np.expm1(hw / 0.025852), n_scba=0)
+    return dataclasses.replace(wl, species=None)
+
+
+def test_scba_atom_blocks_reduce_to_orbital_diagonal_for_one_orbital_atoms():
+    wl = _tiny_scba_workload(seed=13, n_e=7, shift=2, D=0.05, M=0.08)
+    assert wl.orbs_per_atom == 1
+    a = O.scba(wl, 3, atom_block_sigma=True)
+    b = O.scba(wl, 3)
+    assert np.array_equal(a["sigR"][..., 0], b["sigR"]) and np.array_equal(a["sigL"][..., 0], b["sigL"])
+
+
+def test_scba_atom_blocks_kms_every_iterate():
+    """Equilibrium with the eta contact filled: G^< = -f (G^R - G^A) on every
+    diagonal block at every iterate of the atom-block loop."""
+    wl = _tiny_block_scba()
+    wl.mu_L = wl.mu_R = 0.1
+    leads = O.lead_tables(wl)
+    pts = [(0, 0, e) for e in range(wl.n_e)]
+    opa, N, b = wl.orbs_per_atom, wl.total_slabs, wl.nb
+    sR = np.zeros((wl.n_e, N, b, opa), dtype=complex)
+    sL = np.zeros_like(sR)
+    for it in range(3):
+        res = O.solve_points(wl, pts, leads, sR, sL, eta_fill=wl.mu_L)
+        for (s, ik, ie), r in zip(pts, res):
+            f = O.fermi(wl.energy[ie], wl.mu_L, wl.kT)
+            A = r["GR"] - np.conj(np.transpose(r["GR"], (0, 2, 1)))
+            assert np.max(np.abs(r["GL"] + f * A)) < 1e-10 * np.max(np.abs(A)), (it, ie)
+        GR = np.array([O.atom_blocks(r["GR"], opa) for r in res]).reshape(1, wl.n_e, N, b, opa)
+        GL = np.array([O.atom_blocks(r["GL"], opa) for r in res]).reshape(1, wl.n_e, N, b, opa)
+        sR, sL = O.scba_selfenergy(GR, GL, wl.w_k, wl.D_ac, wl.M_op, wl.shift, wl.n_bose)
+        assert np.max(np.abs(sL[..., 1:])) > 0        # off-diagonal entries inside the atom blocks
+
+
+def test_scba_atom_blocks_invariant_under_orbital_rotations_of_each_atom():
+    """A unitary change of basis inside each atom (the same for that atom site
+    in every slab and in the leads) maps G to U G U^dagger.  The atom-block
+    self-energy transforms the same way, so the per-atom density and the bond
+    currents of the Born loop do not change; with orbital-diagonal blocks they
+    do -- which separates the two readings."""
+    import dataclasses
+    wl = _tiny_block_scba()
+    opa, b = wl.orbs_per_atom, wl.nb
+    rng = np.random.default_rng(77)
+    U = np.zeros((b, b), dtype=complex)
+    for a0 in range(0, b, opa):
+        q, _ = np.linalg.qr(rng.normal(size=(opa, opa)) + 1j * rng.normal(size=(opa, opa)))
+        U[a0:a0 + opa, a0:a0 + opa] = q
+    rot = lambda X: U @ X @ U.conj().T
+    wr = dataclasses.replace(
+        wl, h_diag=np.array([[rot(h) for h in hk] for hk in wl.h_diag]), h_up=np.array([rot(h) for h in wl.h_up]),
+        lead_h00=np.array([rot(h) for h in wl.lead_h00]), lead_h01_L=rot(wl.lead_h01_L),
+        lead_h01_R=rot(wl.lead_h01_R), lead_tau_L=rot(wl.lead_tau_L), lead_tau_R=rot(wl.lead_tau_R))
+    pts = [(0, 0, e) for e in range(wl.n_e)]
+
+    def obs(w, blocks):
+        out = O.scba(w, 4, atom_block_sigma=blocks)
+        res = out["res"]
+        return O.observables(w, pts, [np.diagonal(r["GL"], axis1=1, axis2=2) for r in res],
+                             [r["bond"] for r in res])[:2]
+
+    n0, J0 = obs(wl, True)
+    n1, J1 = obs(wr, True)
+    assert np.max(np.abs(n1 - n0)) < 1e-11 * np.max(np.abs(n0))
+    assert np.max(np.abs(J1 - J0)) < 1e-11 * np.max(np.abs(n0))
+    d0, _ = obs(wl, False)
+    d1, _ = obs(wr, False)
+    assert np.max(np.abs(d1 - d0)) > 1e-6 * np.max(np.abs(d0))
