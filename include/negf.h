@@ -180,7 +180,9 @@ int negf_lead_selfenergy_pair(negf_ctx* ctx, void* stream, int n_k, const negf_c
  * - Sigma_R (i=N-1) and Sigma^<_i = diag(Sigma^<_scat,i) + lead terms i f Gamma.
  *   sigma_L, sigma_R  [n_k][n_e][nb][nb] lead self-energies (negf_lead_selfenergy)
  *   scat_R, scat_L    [n_e][total_slabs][nb] orbital-diagonal scattering
- *                     self-energies (Eqs. 4-6), or NULL (ballistic)
+ *                     self-energies (Eqs. 4-6), or NULL (ballistic); atom
+ *                     blocks [n_e][total_slabs][nb][opa] after
+ *                     negf_set_scattering_blocks(opa > 1)
  *   flags             NEGF_WANT_TRANSMISSION keeps the left-column chain G_{N,1}.
  * g and g^< stay in the context for negf_rgf_backward.  Errors: NEGF_ESTATE,
  * NEGF_EINVAL, NEGF_ESHAPE. */
@@ -197,7 +199,10 @@ int negf_rgf_forward(negf_ctx* ctx, void* stream, int p0, int np,
  *   j_i    = 2 Re Tr[H_{i,i+1} G^<_{i+1,i}]  bond current (units e/h per spin, Eq. 8)
  * Outputs (each may be NULL), indexed by bound point p:
  *   GR, GL, GG   full_blocks = 0: [p][slab_stride][nb] orbital diagonals,
- *                full_blocks = 1: [p][slab_stride][nb][nb] diagonal blocks
+ *                full_blocks = 1: [p][slab_stride][nb][nb] diagonal blocks,
+ *                full_blocks = 2: [p][slab_stride][nb][opa] atom blocks (opa of
+ *                negf_set_scattering_blocks; row o holds o's entries with the
+ *                orbitals of its own atom)
  *   bond_j       [p][slab_stride] (entry i = bond i -> i+1, i < N_p - 1)
  *   transmission [p] Caroli T = Tr[Gamma_R G_{N1} Gamma_L G_{N1}^dagger]
  *                (requires NEGF_WANT_TRANSMISSION in the forward call)
@@ -231,9 +236,12 @@ int negf_rgf_solve(negf_ctx* ctx, void* stream, int p0, int np,
  *                              + G^<(E-hw)/2 - G^<(E+hw)/2>_k
  * with hw = `shift` energy-grid steps and <.>_k = sum_k w_k (.).  A (E-hw) or
  * (E+hw) group that falls off the grid is dropped from both Sigma^R and Sigma^<.
- *   GR, GL   [n_k][n_e][slab_stride][nb] orbital diagonals (negf_rgf_backward)
+ *   GR, GL   [n_k][n_e][slab_stride][nb] orbital diagonals (negf_rgf_backward),
+ *            or with atom blocks set (negf_set_scattering_blocks, opa > 1) the
+ *            atom blocks [n_k][n_e][slab_stride][nb][opa] (full_blocks = 2):
+ *            every entry of a block follows the same formulas
  *   w_k      [n_k] (device)
- *   sig_R, sig_L  [n_e][N][nb], updated in place
+ *   sig_R, sig_L  [n_e][N][nb] (or [n_e][N][nb][opa]), updated in place
  *   rel_change    device double[1]: ||Sigma_new - Sigma_old||_F / ||Sigma_new||_F, or NULL
  * Errors: NEGF_ESTATE (not a single-sample full grid), NEGF_EINVAL. */
 int negf_scba_selfenergy(negf_ctx* ctx, void* stream,
@@ -259,12 +267,26 @@ int negf_scba_history(negf_ctx* ctx, void* stream, double* out, int max_n, int* 
  *   J[s_glob]    = g_s sum_p w_e[ie] w_k[ik] j_i                         (units e/h)
  *   j_E[sample][ie][i] = g_s sum_{p at ie} w_k[ik] j_i        (spectral current, or NULL)
  * Atoms are consecutive groups of orbs_per_atom orbitals of a slab.
- *   GL [p][slab_stride][nb], bond_j [p][slab_stride] (negf_rgf_backward layout)
+ *   GL [p][slab_stride][nb] orbital diagonals (gl_opa = 1) or atom blocks
+ *      [p][slab_stride][nb][gl_opa] (full_blocks = 2), bond_j [p][slab_stride]
+ *      (negf_rgf_backward layout)
  *   n  [total_slabs][nb / orbs_per_atom], J [total_slabs], j_E [n_samples][n_e][slab_stride]
  * Errors: NEGF_ESTATE, NEGF_EINVAL. */
 int negf_observables(negf_ctx* ctx, void* stream, const negf_c128* GL, const double* bond_j,
                      int slab_stride, const double* w_e, const double* w_k, double g_s,
-                     int orbs_per_atom, double* n, double* J, double* j_E);
+                     int orbs_per_atom, double* n, double* J, double* j_E, int gl_opa);
+
+/*
+ * Form of the local scattering self-energies (Eqs. 4-6 read "diag G"):
+ * opa = 1 (default) keeps the orbital diagonal; opa > 1 keeps the opa x opa
+ * atom blocks on the diagonal of every diagonal block (atoms are consecutive
+ * groups of opa orbitals), so Sigma_scat is block-diagonal with one block per
+ * atom.  Then scat_R / scat_L of negf_rgf_forward are [n_e][total_slabs][nb][opa]
+ * (row o: o's entries with the orbitals of its atom), negf_rgf_backward writes
+ * atom blocks with full_blocks = 2 and negf_scba_selfenergy builds the blocks
+ * from them.  The one-launch small-block solve is not used with opa > 1.
+ * Errors: NEGF_EINVAL (opa < 1, opa > 64, nb not a multiple), NEGF_ENOMEM. */
+int negf_set_scattering_blocks(negf_ctx* ctx, int opa);
 
 /*
  * Vector-Jacobian product of the density with respect to the onsite potential

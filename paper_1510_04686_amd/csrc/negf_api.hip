@@ -70,6 +70,7 @@ struct negf_ctx {
     double* scba_hist = nullptr;  // [SCBA_HMAX] ||dSigma|| / ||Sigma|| of each negf_scba_selfenergy call
     int* scba_count = nullptr;    // entries appended since the last negf_scba_history
     double ns_thr = 1e-2;         // ||I - M X0||_F above which a block inverse is redone in FP64
+    int scat_opa = 1;             // scattering self-energies: 1 orbital-diagonal, > 1 atom blocks of that size
     int adj_K = 0, adj_nseg = 0;  // adjoint checkpoint segment length and count
     double2* adj_yseg = nullptr;  // [cap][K][nb][nb]  y of the segment being swept
     double2* adj_xseg = nullptr;  // [cap][K][nb][nb]  x of the segment being swept
@@ -243,6 +244,7 @@ SandArgs sand_base(const negf_ctx* c, int p0, const Active& act, int np) {
     a.muR = S.mu_R;
     a.kT = S.kT;
     a.eta_fill = S.eta_fill;
+    a.sopa = c->scat_opa;
     a.n = c->nb;
     a.np = np;
     a.act = act;
@@ -545,7 +547,7 @@ int negf_bind(negf_ctx* c, const negf_system* S, int n_points, const int* points
               dev_alloc(c, &c->orb_tmp_d, total * c->nb * sizeof(double), c->bound_allocs) &&
               dev_alloc(c, &c->trans_d, n_points * sizeof(double), c->bound_allocs);
     if (ok && grid) {
-        long long nblk = ((long long)S->n_e * total * c->nb + 255) / 256;
+        long long nblk = ((long long)S->n_e * total * c->nb * c->scat_opa + 255) / 256;
         ok = dev_alloc(c, &c->scba_partial_d, nblk * 2 * sizeof(double), c->bound_allocs);
     }
     if (!ok) return NEGF_ENOMEM;
@@ -891,6 +893,7 @@ int negf_rgf_backward(negf_ctx* c, void* stream, int p0, int np, negf_c128* GR, 
     if (!c) return NEGF_EINVAL;
     if (!c->bound || !c->fwd_done || p0 != c->fwd_p0 || np != c->fwd_np) return NEGF_ESTATE;
     if (transmission && !(c->fwd_flags & NEGF_WANT_TRANSMISSION)) return NEGF_ESTATE;
+    if (full_blocks < 0 || full_blocks > 2) return NEGF_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const int n = c->nb;
     const long long nn = (long long)n * n;
@@ -966,7 +969,8 @@ int negf_rgf_backward(negf_ctx* c, void* stream, int p0, int np, negf_c128* GR, 
             e.G = Gb[cur]; e.GL = GLb[cur]; e.sG = nn;
             e.outR = reinterpret_cast<double2*>(GR); e.outL = reinterpret_cast<double2*>(GL);
             e.outG = reinterpret_cast<double2*>(GG);
-            e.full = full_blocks ? 1 : 0; e.slab_stride = slab_stride; e.slab = st; e.n = n; e.np = hiF; e.p0 = p0;
+            e.full = full_blocks; e.opa = c->scat_opa; e.slab_stride = slab_stride; e.slab = st; e.n = n;
+            e.np = hiF; e.p0 = p0;
             e.act = aF;
             e.lesser_ref = (c->prec == NEGF_MIXED) ? 1 : 0;
             e.energy = c->sys.energy; e.muR = c->sys.mu_R; e.kT = c->sys.kT;
@@ -992,7 +996,8 @@ int negf_rgf_solve(negf_ctx* c, void* stream, int p0, int np, const negf_c128* s
     int maxN = 0;
     for (int q = 0; q < np; ++q) maxN = std::max(maxN, c->desc_h[p0 + q].w);
     if (slab_stride < maxN) return NEGF_EINVAL;
-    const bool fused = c->nb <= SMALL_NMAX && c->prec == NEGF_FP64 && !c->ckpt;
+    const bool fused = c->nb <= SMALL_NMAX && c->prec == NEGF_FP64 && !c->ckpt && c->scat_opa == 1 &&
+                       full_blocks != 2;
     if (!fused) {
         const int st = negf_rgf_forward(c, stream, p0, np, sigma_L, sigma_R, scat_R, scat_L, flags);
         if (st != NEGF_OK) return st;
@@ -1056,7 +1061,7 @@ int negf_scba_selfenergy(negf_ctx* c, void* stream, const negf_c128* GR, const n
     a.GR = reinterpret_cast<const double2*>(GR);
     a.GL = reinterpret_cast<const double2*>(GL);
     a.w_k = w_k; a.D = D_ac; a.M = M_op; a.n0 = n_bose; a.shift = shift;
-    a.n_k = c->sys.n_k; a.n_e = c->sys.n_e; a.N = N; a.n = c->nb; a.slab_stride = slab_stride;
+    a.n_k = c->sys.n_k; a.n_e = c->sys.n_e; a.N = N; a.n = c->nb * c->scat_opa; a.slab_stride = slab_stride;
     a.sigR = reinterpret_cast<double2*>(sig_R);
     a.sigL = reinterpret_cast<double2*>(sig_L);
     a.partial = c->scba_partial_d;
@@ -1080,10 +1085,11 @@ int negf_scba_history(negf_ctx* c, void* stream, double* out, int max_n, int* n_
 
 int negf_observables(negf_ctx* c, void* stream, const negf_c128* GL, const double* bond_j, int slab_stride,
                      const double* w_e, const double* w_k, double g_s, int orbs_per_atom, double* n_out, double* J,
-                     double* j_E) {
+                     double* j_E, int gl_opa) {
     if (!c) return NEGF_EINVAL;
     if (!c->bound) return NEGF_ESTATE;
     if (!w_e || !w_k || orbs_per_atom < 1 || c->nb % orbs_per_atom != 0) return NEGF_EINVAL;
+    if (gl_opa < 1 || c->nb % gl_opa != 0) return NEGF_EINVAL;
     if ((n_out && !GL) || ((J || j_E) && !bond_j)) return NEGF_EINVAL;
     int maxN = 0;
     for (size_t s = 0; s + 1 < c->soff_h.size(); ++s) maxN = std::max<long long>(maxN, c->soff_h[s + 1] - c->soff_h[s]);
@@ -1091,7 +1097,7 @@ int negf_observables(negf_ctx* c, void* stream, const negf_c128* GL, const doubl
     ObsArgs a{};
     a.GL = reinterpret_cast<const double2*>(GL);
     a.bond = bond_j; a.slab_stride = slab_stride; a.w_e = w_e; a.w_k = w_k; a.g_s = g_s;
-    a.opa = orbs_per_atom; a.n = c->nb; a.n_e = c->sys.n_e; a.n_samples = c->sys.n_samples;
+    a.opa = orbs_per_atom; a.n = c->nb; a.n_e = c->sys.n_e; a.n_samples = c->sys.n_samples; a.gopa = gl_opa;
     a.total = c->soff_h.back();
     a.desc = c->desc_d; a.slab_off = c->soff_d; a.slab_sample = c->slab_sample_d;
     a.csr_off = c->csr_off_d; a.csr_pts = c->csr_pts_d; a.orb_tmp = c->orb_tmp_d;
@@ -1337,6 +1343,19 @@ int negf_cap_selfenergy(negf_ctx* c, void* stream, const double* w_slab, const i
                        c->sys.energy, c->sys.n_e, total, c->nb, w_slab, side, c->sys.mu_L, c->sys.mu_R, c->sys.kT,
                        reinterpret_cast<double2*>(scat_R), reinterpret_cast<double2*>(scat_L));
     NEGF_HIP_CHECK(hipGetLastError());
+    return NEGF_OK;
+}
+
+int negf_set_scattering_blocks(negf_ctx* c, int opa) {
+    if (!c || opa < 1 || opa > 64 || c->nb % opa != 0) return NEGF_EINVAL;
+    if (opa == c->scat_opa) return NEGF_OK;
+    if (c->bound && c->is_grid) {      // the SCBA reduction's partials grow with the entries per slab
+        const long long nblk = ((long long)c->sys.n_e * c->soff_h.back() * c->nb * opa + 255) / 256;
+        double* p = nullptr;
+        if (!dev_alloc(c, &p, nblk * 2 * sizeof(double), c->bound_allocs)) return NEGF_ENOMEM;
+        c->scba_partial_d = p;
+    }
+    c->scat_opa = opa;
     return NEGF_OK;
 }
 

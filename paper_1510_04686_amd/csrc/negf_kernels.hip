@@ -32,7 +32,10 @@ __device__ inline void sandwich_base(const SandArgs& a, double2& z, int gr, int 
         if (gr == gc) {
             z.x += E; z.y += a.eta;
             if (a.v) z.x -= a.v[gslab * n + gr];
-            if (a.scat) { double2 s = a.scat[((long long)ie * a.total + gslab) * n + gr]; z.x -= s.x; z.y -= s.y; }
+        }
+        if (a.scat && gr / a.sopa == gc / a.sopa) {
+            const double2 s = a.scat[(((long long)ie * a.total + gslab) * n + gr) * a.sopa + gc % a.sopa];
+            z.x -= s.x; z.y -= s.y;
         }
         const long long lo = ((long long)ik * a.n_e + ie) * n * n;
         if (a.slab == 0) { double2 s = a.sigL[lo + (long long)gr * n + gc]; z.x -= s.x; z.y -= s.y; }
@@ -45,9 +48,20 @@ __device__ inline void sandwich_base(const SandArgs& a, double2& z, int gr, int 
         // occupation, i f_R (Gamma_L + Gamma_R + Gamma_scat + 2 eta); the
         // remaining source drives only the non-equilibrium part of G^<.
         const double fR = a.lesser_ref ? fermi_d(E, a.muR, a.kT) : 0.0;
+        if (gr / a.sopa == gc / a.sopa) {
+            const long long base = ((long long)ie * a.total + gslab) * n;
+            if (a.scat) {
+                const double2 s = a.scat[(base + gr) * a.sopa + gc % a.sopa];
+                z.x += s.x; z.y += s.y;
+            }
+            if (a.lesser_ref && a.scat2) {
+                // + f_R (Sigma^R - Sigma^R^dagger)_rc
+                const double2 s1 = a.scat2[(base + gr) * a.sopa + gc % a.sopa];
+                const double2 s2 = a.scat2[(base + gc) * a.sopa + gr % a.sopa];
+                z.x += fR * (s1.x - s2.x); z.y += fR * (s1.y + s2.y);
+            }
+        }
         if (gr == gc) {
-            if (a.scat) { double2 s = a.scat[((long long)ie * a.total + gslab) * n + gr]; z.x += s.x; z.y += s.y; }
-            if (a.lesser_ref && a.scat2) z.y += 2.0 * fR * a.scat2[((long long)ie * a.total + gslab) * n + gr].y;
             if (a.eta_fill) z.y += 2.0 * a.eta * fermi_d(E, a.muL, a.kT);
             z.y -= 2.0 * a.eta * fR;
         }
@@ -333,7 +347,7 @@ hipError_t copy_launch(hipStream_t s, int tdi, int tdo, const void* src, long lo
 template <typename TI>
 __global__ __launch_bounds__(256) void extract_kernel(ExtArgs a) {
     const int n = a.n;
-    const long long nel = a.full ? (long long)n * n : n;
+    const long long nel = a.full == 1 ? (long long)n * n : (a.full == 2 ? (long long)n * a.opa : n);
     const long long per = (nel + 255) / 256;
     const int q = (int)(blockIdx.x / per);
     if (q >= a.np || !a.act(q)) return;
@@ -343,7 +357,13 @@ __global__ __launch_bounds__(256) void extract_kernel(ExtArgs a) {
     const TI* GL = reinterpret_cast<const TI*>(a.GL) + q * a.sG;
     const long long p = a.p0 + q;
     int r, c;
-    if (a.full) { r = (int)(i / n); c = (int)(i - (long long)r * n); } else { r = c = (int)i; }
+    if (a.full == 1) {
+        r = (int)(i / n); c = (int)(i - (long long)r * n);
+    } else if (a.full == 2) {            // entry (r, c) of r's atom block, stored at [r][c mod opa]
+        r = (int)(i / a.opa); c = (r / a.opa) * a.opa + (int)(i - (long long)r * a.opa);
+    } else {
+        r = c = (int)i;
+    }
     double2 g = cconv<double2>(G[(long long)r * n + c]);
     double2 gl = cconv<double2>(GL[(long long)r * n + c]);
     double2 gt = g;
@@ -385,7 +405,7 @@ hipError_t diag_out_launch(hipStream_t s, const double2* X, long long sX, int n,
 
 hipError_t extract_launch(hipStream_t s, int dt, const ExtArgs& a) {
     if (a.np <= 0) return hipSuccess;
-    const long long nel = a.full ? (long long)a.n * a.n : a.n;
+    const long long nel = a.full == 1 ? (long long)a.n * a.n : (a.full == 2 ? (long long)a.n * a.opa : a.n);
     dim3 grid((unsigned)((long long)a.np * ((nel + 255) / 256)));
     if (dt == DT_C128) hipLaunchKernelGGL(extract_kernel<double2>, grid, dim3(256), 0, s, a);
     else hipLaunchKernelGGL(extract_kernel<float2>, grid, dim3(256), 0, s, a);
@@ -847,7 +867,7 @@ __global__ __launch_bounds__(256) void obs_orbital_kernel(ObsArgs a) {
         for (int t = b; t < e; ++t) {
             const int p = a.csr_pts[t];
             const int ik = a.desc[p].y;
-            se += a.w_k[ik] * a.GL[((long long)p * a.slab_stride + li) * a.n + o].y;
+            se += a.w_k[ik] * a.GL[(((long long)p * a.slab_stride + li) * a.n + o) * a.gopa + o % a.gopa].y;
         }
         acc += a.w_e[ie] * se;
     }

@@ -16,7 +16,8 @@ struct SandArgs {
     int slab;                           // local slab index of the assembled block
     const double2* hdiag; long long hdiag_k;
     const double* v;                    // [total][n] or NULL
-    const double2* scat;                // [n_e][total][n] or NULL (R for mode 1, < for mode 2)
+    const double2* scat;                // [n_e][total][n][sopa] or NULL (R for mode 1, < for mode 2)
+    int sopa;                           // 1: orbital-diagonal scat; > 1: atom blocks of sopa orbitals
     long long total;
     const double2* sigL; const double2* sigR; int n_e;
     const double* energy; double eta, muL, muR, kT; int eta_fill;
@@ -31,7 +32,8 @@ struct SandArgs {
 struct ExtArgs {
     const void* G; const void* GL; long long sG;
     double2* outR; double2* outL; double2* outG;
-    int full, slab_stride, slab, n, np, p0;
+    int full, slab_stride, slab, n, np, p0;   // full: 0 orbital diagonal, 1 whole block, 2 atom blocks
+    int opa;                            // full = 2: orbitals per atom
     Active act;
     int lesser_ref;                     // GL holds the non-equilibrium part: add -f_R (G - G^dagger)
     const double* energy; double muR, kT;
@@ -108,6 +110,7 @@ struct ObsArgs {
     const double* w_e; const double* w_k;
     double g_s;
     int opa, n, n_e, n_samples;
+    int gopa;                           // GL layout: 1 orbital diagonals, > 1 atom blocks [n][gopa]
     long long total;
     const int4* desc; const long long* slab_off; const int* slab_sample;
     const int* csr_off; const int* csr_pts;

@@ -64,7 +64,7 @@ EXPORTS = [
     "negf_create", "negf_destroy", "negf_workspace_bytes", "negf_sync_status", "negf_error_string",
     "negf_bind", "negf_lead_selfenergy", "negf_lead_selfenergy_pair", "negf_rgf_forward", "negf_rgf_backward",
     "negf_scba_selfenergy", "negf_observables", "negf_rgf_adjoint", "negf_zgemm_batched", "negf_zinv_batched", "negf_mixed_stats",
-    "negf_set_mixed_threshold", "negf_mixed_point_residuals", "negf_mixed_point_scores", "negf_cap_selfenergy", "negf_gemm_timing_enable", "negf_gemm_timing", "negf_get_tuning", "negf_set_tuning", "negf_autotune",
+    "negf_set_mixed_threshold", "negf_mixed_point_residuals", "negf_mixed_point_scores", "negf_cap_selfenergy", "negf_set_scattering_blocks", "negf_gemm_timing_enable", "negf_gemm_timing", "negf_get_tuning", "negf_set_tuning", "negf_autotune",
     "negf_build_id", "negf_scba_history", "negf_rgf_solve", "negf_zinv_noalloc_bytes", "negf_zinv_batched_noalloc",
     "negf_poisson_apply", "negf_poisson_residual", "negf_poisson_work_bytes", "negf_poisson_solve",
     "negf_vec_work_bytes", "negf_vec_dots", "negf_vec_combine", "negf_vec_norms",
@@ -99,7 +99,8 @@ def lib():
         "negf_rgf_backward": (i, [vp, vp, i, i, vp, vp, vp, i, i, vp, vp]),
         "negf_rgf_solve": (i, [vp, vp, i, i, vp, vp, vp, vp, i, vp, vp, vp, i, i, vp, vp]),
         "negf_scba_selfenergy": (i, [vp, vp, vp, vp, i, vp, d, d, i, d, vp, vp, vp]),
-        "negf_observables": (i, [vp, vp, vp, vp, i, vp, vp, d, i, vp, vp, vp]),
+        "negf_observables": (i, [vp, vp, vp, vp, i, vp, vp, d, i, vp, vp, vp, i]),
+        "negf_set_scattering_blocks": (i, [vp, i]),
         "negf_scba_history": (i, [vp, vp, POINTER(d), i, POINTER(i)]),
         "negf_rgf_adjoint": (i, [vp, vp, i, i, vp, vp, i]),
         "negf_zgemm_batched": (i, [vp, vp, i, i, i, i, vp, vp, vp, i]),
@@ -285,13 +286,20 @@ def negf_scba_history(ctx, max_n=4096, stream=None):
 
 
 def negf_observables(ctx, GL, bond_j, slab_stride, w_e, w_k, g_s, orbs_per_atom, n=None, J=None, j_E=None,
-                     stream=None):
+                     stream=None, gl_opa=1):
+    """Density / current sums; GL holds orbital diagonals (gl_opa = 1) or atom
+    blocks [p][slab_stride][nb][gl_opa]."""
     code = lib().negf_observables(
         ctx.handle, _stream(stream), _ptr(GL, torch.complex128, "GL"), _ptr(bond_j, torch.float64, "bond_j"),
         int(slab_stride), _ptr(w_e, torch.float64, "w_e"), _ptr(w_k, torch.float64, "w_k"), float(g_s),
         int(orbs_per_atom), _ptr(n, torch.float64, "n"), _ptr(J, torch.float64, "J"),
-        _ptr(j_E, torch.float64, "j_E"))
+        _ptr(j_E, torch.float64, "j_E"), int(gl_opa))
     _check("negf_observables", code)
+
+
+def negf_set_scattering_blocks(ctx, opa):
+    """Orbital-diagonal (opa = 1) or atom-block (opa > 1) scattering self-energies."""
+    _check("negf_set_scattering_blocks", lib().negf_set_scattering_blocks(ctx.handle, int(opa)))
 
 
 def negf_rgf_adjoint(ctx, p0, np_, w_orb, dX, slab_stride, stream=None):

@@ -125,6 +125,7 @@ class RGFSolver:
         self.resid = torch.zeros(self.n_points, dtype=torch.float64, device=self.device) if mixed else None
         self.redo_ctx = None
         self.points_redone = 0
+        self.scat_opa = 1             # scattering self-energies: orbital diagonal (1) or atom blocks
         self._bind()
         self.sigma_L = self.sigma_R = None
         self.lead_dual = 0
@@ -261,7 +262,7 @@ class RGFSolver:
     # ------------------------------------------------------------------ RGF
     def alloc_outputs(self, full_blocks=False, want=("GR", "GL", "GG", "bond"), want_T=False):
         nb, P, S = self.wl.nb, self.n_points, self.slab_stride
-        shp = (P, S, nb, nb) if full_blocks else (P, S, nb)
+        shp = {0: (P, S, nb), 1: (P, S, nb, nb), 2: (P, S, nb, self.scat_opa)}[int(full_blocks)]
         out = {}
         for k in ("GR", "GL", "GG"):
             if k in want:
@@ -340,6 +341,7 @@ class RGFSolver:
             cap = int(max(1, min(64, self.capacity, (free // 2) // per_point)))
             self.redo_ctx = N.negf_create(nb, self.n_slab_max, cap, N.NEGF_FP64, 0)
             self.redo_cap = cap
+        N.negf_set_scattering_blocks(self.redo_ctx, self.scat_opa)
         pts = self.points[idx.cpu().numpy()]
         N.negf_bind(self.redo_ctx, wl.nb, wl.slab_offset, wl.n_k, wl.n_e, self.h_diag, self.h_up, 0, wl.up_block,
                     self.v, self.energy, wl.eta, wl.mu_L, wl.mu_R, wl.kT, self.eta_fill, pts)
@@ -370,8 +372,9 @@ class RGFSolver:
         J = None if bond is None else torch.zeros(wl.total_slabs, dtype=torch.float64, device=self.device)
         jE = (torch.zeros((wl.n_samples, wl.n_e, self.slab_stride), dtype=torch.float64, device=self.device)
               if (spectral and bond is not None) else None)
+        gl_opa = 1 if GL is None or GL.dim() == 3 else int(GL.shape[-1])   # diagonals or (atom) blocks
         N.negf_observables(self.ctx, GL, bond, self.slab_stride, self.w_e, self.w_k, g_s, wl.orbs_per_atom,
-                           n, J, jE)
+                           n, J, jE, gl_opa=gl_opa)
         return n, J, jE
 
     # ------------------------------------------------------------------ adjoint
@@ -414,11 +417,15 @@ class RGFSolver:
         return max(codes)
 
     # ------------------------------------------------------------------ SCBA
-    def scba(self, n_iter=None, graph=True):
+    def scba(self, n_iter=None, graph=True, atom_blocks=False):
         """Self-consistent Born loop (Eqs. 1-6) for a single-sample grid
         workload.  One iteration = scattering self-energy update from the last
         diagonals + a full forward/backward pass; captured once into a HIP
-        graph and replayed when ``graph`` is true."""
+        graph and replayed when ``graph`` is true.  atom_blocks: build the
+        local self-energies from the atom blocks (orbs_per_atom square) of the
+        diagonal blocks instead of the orbital diagonals; the outputs are then
+        atom blocks [P][slab][nb][orbs_per_atom] (negf_set_scattering_blocks,
+        which stays set on the solver's contexts)."""
         wl = self.wl
         assert wl.n_samples == 1
         n_iter = wl.n_scba if n_iter is None else n_iter
@@ -426,19 +433,23 @@ class RGFSolver:
             graph = False      # the mixed-precision point redo decides on the host after every pass
         if self.sigma_L is None:
             self.lead_selfenergies()
+        self.scat_opa = wl.orbs_per_atom if atom_blocks else 1
+        for c in self.ctxs + ([self.redo_ctx] if self.redo_ctx is not None else []):
+            N.negf_set_scattering_blocks(c, self.scat_opa)
+        fb = 2 if atom_blocks else 0
         Ns = wl.total_slabs
-        shp = (wl.n_e, Ns, wl.nb)
+        shp = (wl.n_e, Ns, wl.nb) + ((self.scat_opa,) if atom_blocks else ())
         self.scat_R = torch.zeros(shp, dtype=torch.complex128, device=self.device)
         self.scat_L = torch.zeros(shp, dtype=torch.complex128, device=self.device)
-        out = self.alloc_outputs(want=("GR", "GL", "bond"))
+        out = self.alloc_outputs(full_blocks=fb, want=("GR", "GL", "bond"))
         N.negf_scba_history(self.ctx, 0)          # clear the device residual list
         # iteration 0: ballistic pass (Sigma_scat = 0)
-        self.run_batches(out, scat_R=self.scat_R, scat_L=self.scat_L)
+        self.run_batches(out, full_blocks=fb, scat_R=self.scat_R, scat_L=self.scat_L)
 
         def one_iteration(stream=None):
             N.negf_scba_selfenergy(self.ctx, out["GR"], out["GL"], self.slab_stride, self.w_k, wl.D_ac, wl.M_op,
                                    wl.shift, wl.n_bose, self.scat_R, self.scat_L, None, stream=stream)
-            self.run_batches(out, scat_R=self.scat_R, scat_L=self.scat_L, stream=stream)
+            self.run_batches(out, full_blocks=fb, scat_R=self.scat_R, scat_L=self.scat_L, stream=stream)
 
         if n_iter <= 1 or not graph:
             for _ in range(n_iter - 1):

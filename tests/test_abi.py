@@ -58,7 +58,8 @@ def test_calls_reject_null_context(lib):
     assert lib.negf_lead_selfenergy_pair(None, None, 1, None, None, None, None, None, 1, None, 0.0, 1e-14, 10,
                                          None, None, None, None, None) == -1
     assert lib.negf_scba_selfenergy(None, None, None, None, 1, None, 0, 0, 0, 0, None, None, None) == -1
-    assert lib.negf_observables(None, None, None, None, 1, None, None, 2.0, 1, None, None, None) == -1
+    assert lib.negf_observables(None, None, None, None, 1, None, None, 2.0, 1, None, None, None, 1) == -1
+    assert lib.negf_set_scattering_blocks(None, 10) == -1
     assert lib.negf_zgemm_batched(None, None, 4, 1, 0, 0, None, None, None, 0) == -1
     assert lib.negf_zinv_batched(None, None, 4, 1, None, None, 0) == -1
     assert lib.negf_set_mixed_threshold(None, ctypes.c_double(1e-2)) == -1
