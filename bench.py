@@ -40,6 +40,40 @@ WORKLOAD_DESC = {
 }
 
 
+def poisson_record(args, wl, solver):
+    """Newton steps of the NEGF-Poisson loop (Eq. 9) on the workload's own
+    device: silicon (eps_r 11.7) on a 0.2715 nm atom grid, insulating faces,
+    contacts held at the mean starting potential of the first / last slab,
+    donors N_D = n(V0) + 1e-3 per atom (a small excess, so the root lies near
+    the starting potential).  Times every part of each step."""
+    import numpy as np
+    import torch
+    from paper_1510_04686_amd.runtime import NewtonPoisson
+    nz, ny = {"C5": (12, 10), "C2": (10, 4), "C3": (12, 2)}.get(args.workload, (1, wl.atoms_per_slab))
+    opa = wl.orbs_per_atom
+    v0 = (np.zeros((wl.total_slabs, wl.atoms_per_slab)) if wl.v_onsite is None
+          else wl.v_onsite.reshape(wl.total_slabs, -1, opa)[:, :, 0])
+    solver.set_potential(torch.from_numpy(np.repeat(v0, opa, axis=1)).cuda())
+    n0 = solver.density().cpu().numpy()
+    beta = 18.0951 / (11.7 * 0.2715)
+    loop = NewtonPoisson(solver, nz, ny, beta, n0 + 1e-3, v_left=float(v0[0].mean()),
+                         v_right=float(v0[-1].mean()), jacobian=args.poisson_jacobian, krylov_dim=20,
+                         krylov_tol=1e-3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    V, hist = loop.solve(v0, tol=1e-9, max_newton=args.poisson,
+                         log=lambda m: print(f"[bench] poisson {m}", file=sys.stderr, flush=True))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = dict(loop.stats)
+    return {"newton_steps": st["newton"], "krylov_iterations": st["krylov"], "cg_iterations": st["cg"],
+            "jacobian": args.poisson_jacobian, "equilibrium": bool(wl.mu_L == wl.mu_R),
+            "seconds": dt, "seconds_per_newton_step": dt / max(st["newton"], 1),
+            "density_seconds": st["density_s"], "jacobian_seconds": st["jacobian_s"],
+            "max_residual_history": hist, "atoms": int(wl.total_slabs * wl.atoms_per_slab),
+            "max_potential_change_eV": float(np.max(np.abs(V.cpu().numpy() - v0)))}
+
+
 GEMM_SOURCES = ["negf_gemm.hip", "negf_mfma.hpp", "negf_common.hpp", "negf_internal.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_traffic_C2.json")
 
@@ -106,6 +140,16 @@ def main():
     ap.add_argument("--redo-frac", type=float, default=0.05,
                     help="mixed precision: also redo this share of the points with the highest redo score "
                          "(residual x largest weighted |Im G^<_jj|) in FP64")
+    ap.add_argument("--atom-blocks", action="store_true",
+                    help="C3: local scattering self-energies from the atom blocks of G (else orbital diagonals)")
+    ap.add_argument("--cap-slabs", type=int, default=0,
+                    help="C2/C4: absorbing-potential contacts of this many disordered slabs per side "
+                         "instead of Sancho-Rubio leads")
+    ap.add_argument("--poisson", type=int, default=0, metavar="K",
+                    help="C5 (or any single-sample workload): after the timed steps, at most K Newton steps of "
+                         "the NEGF-Poisson loop (Eq. 9) from the workload's potential, reported in a 'poisson' record")
+    ap.add_argument("--poisson-jacobian", default="adjoint", choices=["adjoint", "fd"])
+    ap.add_argument("--equilibrium", action="store_true", help="set mu_R = mu_L (one Fermi level)")
     ap.add_argument("--lanes", type=int, default=1,
                     help="batches in flight at once, each on its own context and stream")
     ap.add_argument("--store", default="full", choices=["full", "checkpoint"],
@@ -141,10 +185,17 @@ def main():
         kw["n_e"] = args.n_e
     if args.workload == "C4" and args.samples:
         kw["n_samples"] = args.samples
+    if args.cap_slabs:
+        if args.workload not in ("C2", "C4"):
+            sys.exit("--cap-slabs applies to C2 and C4")
+        kw["cap_slabs"] = args.cap_slabs
     wl = make_workload(args.workload, **kw)
+    if args.equilibrium:
+        import dataclasses
+        wl = dataclasses.replace(wl, mu_R=wl.mu_L)
     print(f"[bench] workload {args.workload}: nb={wl.nb} samples={wl.n_samples} slabs={wl.total_slabs} "
           f"n_k={wl.n_k} n_e={wl.n_e} precision={args.precision}", file=sys.stderr, flush=True)
-    adj_seg = -1 if args.workload == "C5" else 0
+    adj_seg = -1 if (args.workload == "C5" or (args.poisson and args.poisson_jacobian == "adjoint")) else 0
     solver = RGFSolver(wl, precision=args.precision, capacity=args.capacity, adjoint_segment=adj_seg,
                        tune="auto" if args.tune == "auto" else None, lanes=args.lanes, point_redo=args.point_redo,
                        store=args.store, redo_frac=args.redo_frac or None)
@@ -168,7 +219,7 @@ def main():
         solver.lead_selfenergies()
         ranges = [(ik, 0, wl.n_e) for ik in range(wl.n_k)]
         if args.workload == "C3":
-            o, hist = solver.scba(n_iter=n_iter, graph=True)
+            o, hist = solver.scba(n_iter=n_iter, graph=True, atom_blocks=args.atom_blocks)
             return (*solver.observables(o["GL"], o["bond"]), solver.n_points, ranges)
         if args.workload == "C5":
             return solver.density(), None, None, solver.n_points, ranges
@@ -255,6 +306,8 @@ def main():
                    "samples": wl.n_samples, "n_e": wl.n_e, "n_k": wl.n_k,
                    "batch_capacity": solver.capacity, "lanes": solver.lanes, "precision": args.precision,
                    "store": args.store,
+                   "contacts": (f"absorbing potential, {args.cap_slabs} disordered slabs per side"
+                                if args.cap_slabs else "Sancho-Rubio leads"),
                    "parallelism": "single GPU, batched (sample,k,E) points"},
         "model_tflops": (rgf_f + lead_f) / dt / 1e12,
         "model_flops_per_step": {"rgf": rgf_f / args.steps, "leads": lead_f / args.steps},
@@ -279,6 +332,7 @@ def main():
     }
     if args.workload == "C3":
         res["config"]["scba_iterations"] = n_iter
+        res["config"]["sigma_scat"] = "atom blocks" if args.atom_blocks else "orbital diagonal"
         res["roofline"]["note"] = "GEMM events are not recorded inside the captured SCBA graph"
     if args.precision == "mixed":
         stats = [N.negf_mixed_stats(c) for c in solver.ctxs]
@@ -342,6 +396,8 @@ def main():
         res["mixed"]["speedup_vs_fp64"] = t64 / (dt / args.steps)
         res["mixed"]["target_rel_err"] = 1e-4
         res["mixed"]["target_met"] = bool(max(errs) <= 1e-4 and max(jerrs) <= 1e-4)
+    if args.poisson > 0:
+        res["poisson"] = poisson_record(args, wl, solver)
     if not args.no_cpu_baseline and args.cpu_points > 0:
         res["cpu_baseline"] = cpu_baseline(wl, args.cpu_points)
         res["gpu_over_cpu"] = res["value"] / res["cpu_baseline"]["value"]

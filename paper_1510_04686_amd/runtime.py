@@ -531,6 +531,7 @@ class NewtonPoisson:
         self.s, self.wl = solver, wl
         self.mode, self.fd_step = jacobian, float(fd_step)
         self._V = None
+        self._log = None
         self.grid = N.poisson_grid(wl.total_slabs, n_z, n_y, z_gate, v_left, v_right, v_gate)
         self.n = wl.total_slabs * wl.atoms_per_slab
         dev = solver.device
@@ -646,6 +647,8 @@ class NewtonPoisson:
             g[j] = cs[j] * g[j]
             k = j + 1
             self.stats["krylov"] += 1
+            if self._log:
+                self._log(f"  krylov {k}: residual ratio {abs(g[j + 1]) / b0:.2e}")
             if abs(g[j + 1]) <= self.ktol * b0 or wn == 0.0:
                 break
             self.Q[j + 1].copy_(self.w)
@@ -663,6 +666,7 @@ class NewtonPoisson:
                             dtype=torch.float64, device=self.s.device).reshape(-1).clone()
         dV = torch.empty_like(V)
         rhs = torch.empty_like(V)
+        self._log = log
         hist = []
         for it in range(max_newton + 1):
             F, _ = self.residual(V)

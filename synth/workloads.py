@@ -389,15 +389,17 @@ def scba_params(kT: float = KT_300K, hw: float = 0.060, de: float = 0.005):
 
 def make_workload(name: str, n_slab: Optional[int] = None, n_e: Optional[int] = None,
                   n_k: Optional[int] = None, n_z: Optional[int] = None, n_y: Optional[int] = None,
-                  n_samples: Optional[int] = None, samples=None) -> Workload:
-    """The named workload; keyword overrides shrink it for tests (same recipe)."""
+                  n_samples: Optional[int] = None, samples=None, cap_slabs: int = 0) -> Workload:
+    """The named workload; keyword overrides shrink it for tests (same recipe).
+    cap_slabs (C2, C4): disordered absorbing-potential contacts of that many
+    slabs per side instead of the ordered leads."""
     seed = SEEDS[name]
     if name == "C1":
         return strip_workload(n_slab=n_slab or 20, n_e=n_e or 256, seed=seed)
     if name == "C2":
         ne = n_e or 512
         return cross_section_workload("C2", n_z or 10, n_y or 4, [n_slab or 70], n_k or 8,
-                                      np.linspace(-2.0, 2.0, ne), seed)
+                                      np.linspace(-2.0, 2.0, ne), seed, cap_slabs=cap_slabs)
     if name == "C3":
         ne = n_e or 1024
         energy = -2.56 + 0.005 * np.arange(ne)
@@ -410,7 +412,7 @@ def make_workload(name: str, n_slab: Optional[int] = None, n_e: Optional[int] = 
             counts = np.maximum(2, np.round(counts * n_slab / 70.0)).astype(int)
         ne = n_e or 256
         return cross_section_workload("C4", n_z or 10, n_y or 4, [int(c) for c in counts], n_k or 1,
-                                      np.linspace(-2.0, 2.0, ne), seed, samples=samples)
+                                      np.linspace(-2.0, 2.0, ne), seed, samples=samples, cap_slabs=cap_slabs)
     if name == "C5":
         ne = n_e or 16
         return cross_section_workload("C5", n_z or 12, n_y or 10, [n_slab or 200], n_k or 1,
