@@ -207,17 +207,35 @@ def main():
     # C2: one step is one batch (the 512 energies of one k-point); the others run
     # the whole workload per step
     per_batch = args.workload == "C2" and args.precision == "fp64" and args.lanes == 1
-    lead_steps = []        # (ik, e0, e1) lead ranges computed in each timed step
+    lead_steps = []        # (ik, e0, e1) lead ranges decimated in each timed step
+    # C2 steps: a batch, or a batch together with its mirror batch (the one at -k),
+    # whose lead tables are the transposes of the first's (RGFSolver.mirror)
+    groups, used = [], set()
+    for b in range(len(batches)):
+        if b in used:
+            continue
+        g = [b]
+        used.add(b)
+        ks = {ik for ik, _, _ in solver.lead_ranges(*batches[b])}
+        for b2 in range(b + 1, len(batches)):
+            ks2 = {ik for ik, _, _ in solver.lead_ranges(*batches[b2])}
+            if b2 not in used and any(solver.mirror.get(k2) in ks for k2 in ks2):
+                g.append(b2)
+                used.add(b2)
+                break
+        groups.append(g)
 
     def step(j):
         if per_batch:
-            p0, np_ = batches[j % len(batches)]
-            ranges = solver.lead_selfenergies_for(p0, np_)
-            solver.run_batch(out, p0, np_)
+            grp = groups[j % len(groups)]
+            ranges = [r for b in grp for r in solver.lead_ranges(*batches[b])]
+            dec = solver.lead_selfenergies_for_ranges(ranges)
+            for b in grp:
+                solver.run_batch(out, *batches[b])
             n, J, jE = solver.observables(out["GL"], out["bond"])
-            return n, J, jE, np_, ranges
+            return n, J, jE, sum(batches[b][1] for b in grp), dec
         solver.lead_selfenergies()
-        ranges = [(ik, 0, wl.n_e) for ik in range(wl.n_k)]
+        ranges = list(solver.last_lead_ranges)
         if args.workload == "C3":
             o, hist = solver.scba(n_iter=n_iter, graph=True, atom_blocks=args.atom_blocks)
             return (*solver.observables(o["GL"], o["bond"]), solver.n_points, ranges)
@@ -266,8 +284,9 @@ def main():
     # shared decimation) plus 3 U per lead for the surface inverse and tau g tau^dagger
     for k, ranges in enumerate(lead_steps):
         if per_batch:
-            p0, np_ = batches[(args.warmup + k) % len(batches)]
-            slabs = float(np.sum(counts[solver.points[p0:p0 + np_, 0]]))
+            grp = groups[(args.warmup + k) % len(groups)]
+            slabs = float(sum(np.sum(counts[solver.points[p0:p0 + np_, 0]])
+                              for p0, np_ in (batches[b] for b in grp)))
         else:
             slabs = float(np.sum(counts)) * wl.n_k * wl.n_e
         rgf_f += 7.0 * U * slabs * n_iter
@@ -299,9 +318,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOAD_DESC[args.workload]}",
                    "points_per_step": points // max(args.steps * n_iter, 1),
-                   "step": ("one batch of bound points (one k-point's 512 energies): its leads, forward + "
-                            "backward sweeps, and the reductions over the point set; steps cycle over the "
-                            f"{len(batches)} batches" if per_batch else "the whole workload"),
+                   "step": ("one batch of bound points (one k-point's 512 energies), or two batches at k "
+                            "and -k: their leads (decimated once for a mirror pair, the -k tables by "
+                            "transposition), forward + backward sweeps, and the reductions over the point "
+                            f"set; steps cycle over the {len(groups)} groups of the {len(batches)} batches"
+                            if per_batch else "the whole workload"),
+                   "lead_mirrors": {str(k): v for k, v in solver.mirror.items()},
                    "points_per_pass": solver.n_points, "block": wl.nb, "slabs": int(wl.total_slabs),
                    "samples": wl.n_samples, "n_e": wl.n_e, "n_k": wl.n_k,
                    "batch_capacity": solver.capacity, "lanes": solver.lanes, "precision": args.precision,

@@ -376,6 +376,16 @@ int negf_set_mixed_threshold(negf_ctx* ctx, double thr);
  * forward sweep yet), NEGF_ESHAPE (n larger than the sweep). */
 int negf_mixed_point_residuals(negf_ctx* ctx, void* stream, int n, double* out);
 
+/* Batched transpose, dst[m] = src[m]^T for m < count (n x n complex128, matrix
+ * m at src + m * src_stride, dst + m * dst_stride elements; DEVICE buffers that
+ * must not overlap).  Its use here: each lead is in equilibrium and, where its
+ * couplings are real and h00(-k) = h00(k)^T, its surface Green's function and
+ * self-energy obey Sigma(-k) = Sigma(k)^T, so the lead tables of a k-point's
+ * mirror need no decimation of their own.  No context; allocates nothing.
+ * Errors: NEGF_EINVAL (sizes, NULL, overlap). */
+int negf_transpose_batched(void* stream, int n, int count, const negf_c128* src, long long src_stride,
+                           negf_c128* dst, long long dst_stride);
+
 /* Absorbing-potential contacts (the paper treats random-alloy leads with a
  * complex absorbing potential, paragraph after Eq. 6): the contact regions are
  * slabs of the bound device itself, each carrying an imaginary onsite potential

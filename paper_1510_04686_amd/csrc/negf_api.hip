@@ -346,6 +346,28 @@ __global__ __launch_bounds__(256) void cap_kernel(const double* energy, int n_e,
     sL[i] = make_double2(0.0, 2.0 * W * f);
 }
 
+// dst[m] = src[m]^T for a batch of n x n complex matrices: 32 x 32 tiles staged
+// through LDS so that both the reads and the writes run along rows.
+__global__ __launch_bounds__(256) void transpose_kernel(const double2* src, long long ss, double2* dst, long long sd,
+                                                        int n) {
+    __shared__ double2 t[32][33];
+    const int tiles = (n + 31) / 32;
+    const int m = blockIdx.y;
+    const int r0 = (blockIdx.x / tiles) * 32, c0 = (blockIdx.x % tiles) * 32;
+    const double2* S = src + (long long)m * ss;
+    double2* D = dst + (long long)m * sd;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;     // 32 x 8 threads
+    for (int y = ty; y < 32; y += 8) {
+        const int r = r0 + y, c = c0 + tx;
+        if (r < n && c < n) t[y][tx] = S[(long long)r * n + c];
+    }
+    __syncthreads();
+    for (int y = ty; y < 32; y += 8) {
+        const int r = c0 + y, c = r0 + tx;                       // element (c, r) of S
+        if (r < n && c < n) D[(long long)r * n + c] = t[tx][y];
+    }
+}
+
 // Mixed precision: per-point redo score = (largest block refinement residual of
 // the point) x (its energy and k weights) x (largest |Im G^<_jj| over its
 // orbitals), i.e. the residual times the point's largest contribution to the
@@ -1329,6 +1351,22 @@ int negf_mixed_point_scores(negf_ctx* c, void* stream, const negf_c128* GL, int 
     if (slab_stride < maxN) return NEGF_EINVAL;
     hipLaunchKernelGGL(mixed_score_kernel, dim3(c->n_points), dim3(256), 0, (hipStream_t)stream,
                        reinterpret_cast<const double2*>(GL), slab_stride, c->nb, c->desc_d, w_e, w_k, resid, score);
+    NEGF_HIP_CHECK(hipGetLastError());
+    return NEGF_OK;
+}
+
+int negf_transpose_batched(void* stream, int n, int count, const negf_c128* src, long long src_stride,
+                           negf_c128* dst, long long dst_stride) {
+    if (n < 1 || count < 1 || count > 65535 || !src || !dst) return NEGF_EINVAL;
+    const long long nn = (long long)n * n;
+    if (src_stride < nn || dst_stride < nn) return NEGF_EINVAL;
+    const char *s0 = reinterpret_cast<const char*>(src), *d0 = reinterpret_cast<const char*>(dst);
+    const long long sb = ((count - 1) * src_stride + nn) * 16, db = ((count - 1) * dst_stride + nn) * 16;
+    if (s0 < d0 + db && d0 < s0 + sb) return NEGF_EINVAL;       // overlapping buffers
+    const int tiles = (n + 31) / 32;
+    hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)(tiles * tiles), (unsigned)count), dim3(256), 0,
+                       (hipStream_t)stream, reinterpret_cast<const double2*>(src), src_stride,
+                       reinterpret_cast<double2*>(dst), dst_stride, n);
     NEGF_HIP_CHECK(hipGetLastError());
     return NEGF_OK;
 }

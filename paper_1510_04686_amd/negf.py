@@ -64,7 +64,7 @@ EXPORTS = [
     "negf_create", "negf_destroy", "negf_workspace_bytes", "negf_sync_status", "negf_error_string",
     "negf_bind", "negf_lead_selfenergy", "negf_lead_selfenergy_pair", "negf_rgf_forward", "negf_rgf_backward",
     "negf_scba_selfenergy", "negf_observables", "negf_rgf_adjoint", "negf_zgemm_batched", "negf_zinv_batched", "negf_mixed_stats",
-    "negf_set_mixed_threshold", "negf_mixed_point_residuals", "negf_mixed_point_scores", "negf_cap_selfenergy", "negf_set_scattering_blocks", "negf_gemm_timing_enable", "negf_gemm_timing", "negf_get_tuning", "negf_set_tuning", "negf_autotune",
+    "negf_set_mixed_threshold", "negf_mixed_point_residuals", "negf_mixed_point_scores", "negf_cap_selfenergy", "negf_set_scattering_blocks", "negf_transpose_batched", "negf_gemm_timing_enable", "negf_gemm_timing", "negf_get_tuning", "negf_set_tuning", "negf_autotune",
     "negf_build_id", "negf_scba_history", "negf_rgf_solve", "negf_zinv_noalloc_bytes", "negf_zinv_batched_noalloc",
     "negf_poisson_apply", "negf_poisson_residual", "negf_poisson_work_bytes", "negf_poisson_solve",
     "negf_vec_work_bytes", "negf_vec_dots", "negf_vec_combine", "negf_vec_norms",
@@ -101,6 +101,7 @@ def lib():
         "negf_scba_selfenergy": (i, [vp, vp, vp, vp, i, vp, d, d, i, d, vp, vp, vp]),
         "negf_observables": (i, [vp, vp, vp, vp, i, vp, vp, d, i, vp, vp, vp, i]),
         "negf_set_scattering_blocks": (i, [vp, i]),
+        "negf_transpose_batched": (i, [vp, i, i, vp, ll, vp, ll]),
         "negf_scba_history": (i, [vp, vp, POINTER(d), i, POINTER(i)]),
         "negf_rgf_adjoint": (i, [vp, vp, i, i, vp, vp, i]),
         "negf_zgemm_batched": (i, [vp, vp, i, i, i, i, vp, vp, vp, i]),
@@ -295,6 +296,17 @@ def negf_observables(ctx, GL, bond_j, slab_stride, w_e, w_k, g_s, orbs_per_atom,
         int(orbs_per_atom), _ptr(n, torch.float64, "n"), _ptr(J, torch.float64, "J"),
         _ptr(j_E, torch.float64, "j_E"), int(gl_opa))
     _check("negf_observables", code)
+
+
+def negf_transpose_batched(src, dst, stream=None):
+    """dst[m] = src[m]^T for [count][n][n] complex128 device tensors (distinct buffers)."""
+    n = src.shape[-1]
+    count = src.numel() // (n * n)
+    if src.shape != dst.shape or src.shape[-2] != n:
+        raise ValueError("src and dst must be [..., n, n] of one shape")
+    _check("negf_transpose_batched",
+           lib().negf_transpose_batched(_stream(stream), int(n), int(count), _ptr(src, torch.complex128, "src"),
+                                        n * n, _ptr(dst, torch.complex128, "dst"), n * n))
 
 
 def negf_set_scattering_blocks(ctx, opa):

@@ -129,6 +129,8 @@ class RGFSolver:
         self._bind()
         self.sigma_L = self.sigma_R = None
         self.lead_dual = 0
+        self.mirror = self._lead_mirrors()
+        self.last_lead_ranges = []
 
     def _tune(self, tune, precision):
         if tune is None:
@@ -197,6 +199,32 @@ class RGFSolver:
             out.append((int(ik), int(es.min()), int(es.max()) + 1))
         return out
 
+    def _lead_mirrors(self):
+        """{ik: ik_src} for the k-points whose lead tables are the transposes of
+        an earlier k-point's.  Each lead is a reservoir in equilibrium; with real
+        couplings (h01, tau) and h00(-k) = h00(k)^T its surface Green's function
+        solves the transposed equation at -k, so Sigma(-k) = Sigma(k)^T for both
+        leads and the mirror needs no decimation.  Checked on the inputs: the k
+        values must be mirrors modulo 2 pi and h00 equal to the transpose to
+        within a few rounding units; otherwise every k-point is decimated."""
+        wl = self.wl
+        if self.cap or wl.n_k < 2:
+            return {}
+        for x in (wl.lead_h01_L, wl.lead_tau_L, wl.lead_h01_R, wl.lead_tau_R):
+            if np.iscomplexobj(x) and np.any(np.imag(x) != 0):
+                return {}
+        scale = max(float(np.max(np.abs(wl.lead_h00))), 1e-300)
+        two_pi = 2.0 * math.pi
+        out = {}
+        for j in range(wl.n_k):
+            for i in range(j):
+                d = (float(wl.kpts[i]) + float(wl.kpts[j])) % two_pi
+                if (min(d, two_pi - d) < 1e-12 and i not in out and
+                        float(np.max(np.abs(wl.lead_h00[j] - wl.lead_h00[i].T))) <= 8 * 2.0 ** -53 * scale):
+                    out[j] = i
+                    break
+        return out
+
     def _cap_contacts(self):
         """Zero lead tables and the absorbing contacts' self-energies
         (negf_cap_selfenergy), once: they depend on neither k nor the batch."""
@@ -221,16 +249,26 @@ class RGFSolver:
 
     def lead_selfenergies_for(self, p0, np_, tol=1e-14, max_iter=100):
         """Lead self-energies of only the (k, E) points that the batch [p0, p0 + np_)
-        reads, written into their slots of the full tables (one shared
-        decimation call per k-point of the batch).  Returns the (ik, e0, e1)
-        ranges computed."""
+        reads, written into their slots of the full tables.  Returns the
+        (ik, e0, e1) ranges decimated."""
+        return self.lead_selfenergies_for_ranges(self.lead_ranges(p0, np_), tol, max_iter)
+
+    def lead_selfenergies_for_ranges(self, ranges, tol=1e-14, max_iter=100):
+        """Lead self-energies of the (ik, e0, e1) ranges: one shared decimation
+        call per range whose k-point has no mirror among the decimated ones, the
+        mirrored ranges by transposing their source's tables (negf_transpose_batched).
+        Returns the ranges decimated."""
         if self.cap:
             self._cap_contacts()
             return []
         self._alloc_lead_tables()
-        ranges = self.lead_ranges(p0, np_)
-        status, dual = 0, 1
+        dec = []
         for ik, e0, e1 in ranges:
+            r = (self.mirror.get(ik, ik), e0, e1)
+            if r not in dec:
+                dec.append(r)
+        status, dual = 0, 1
+        for ik, e0, e1 in dec:
             k = slice(ik, ik + 1)
             st, du = N.negf_lead_selfenergy_pair(
                 self.ctx, self.lead_h00[k], self.lead_h01_L[k], self.lead_tau_L[k], self.lead_h01_R[k],
@@ -238,8 +276,18 @@ class RGFSolver:
                 self.sigma_L[ik, e0:e1], self.sigma_R[ik, e0:e1], self.iters_L[ik, e0:e1],
                 self.iters_R[ik, e0:e1])
             status, dual = max(status, st), min(dual, du)
+        for ik, e0, e1 in ranges:
+            if ik in self.mirror:
+                self._mirror_tables(ik, self.mirror[ik], e0, e1)
         self.lead_status, self.lead_dual = status, dual
-        return ranges
+        self.last_lead_ranges = dec
+        return dec
+
+    def _mirror_tables(self, ik, src, e0, e1):
+        N.negf_transpose_batched(self.sigma_L[src, e0:e1], self.sigma_L[ik, e0:e1])
+        N.negf_transpose_batched(self.sigma_R[src, e0:e1], self.sigma_R[ik, e0:e1])
+        self.iters_L[ik, e0:e1].copy_(self.iters_L[src, e0:e1])
+        self.iters_R[ik, e0:e1].copy_(self.iters_R[src, e0:e1])
 
     def lead_selfenergies(self, tol=1e-14, max_iter=100, shared_decimation=True):
         if self.cap:
@@ -248,9 +296,24 @@ class RGFSolver:
         self._alloc_lead_tables()
         wl = self.wl
         if shared_decimation:
-            self.lead_status, self.lead_dual = N.negf_lead_selfenergy_pair(
-                self.ctx, self.lead_h00, self.lead_h01_L, self.lead_tau_L, self.lead_h01_R, self.lead_tau_R,
-                self.energy, wl.eta, tol, max_iter, self.sigma_L, self.sigma_R, self.iters_L, self.iters_R)
+            # decimate the k-points without a mirror, in contiguous runs, then transpose
+            todo = [ik for ik in range(wl.n_k) if ik not in self.mirror]
+            runs, status, dual = [], 0, 1
+            for ik in todo:
+                if runs and runs[-1][1] == ik:
+                    runs[-1][1] = ik + 1
+                else:
+                    runs.append([ik, ik + 1])
+            for a, b in runs:
+                st, du = N.negf_lead_selfenergy_pair(
+                    self.ctx, self.lead_h00[a:b], self.lead_h01_L[a:b], self.lead_tau_L[a:b],
+                    self.lead_h01_R[a:b], self.lead_tau_R[a:b], self.energy, wl.eta, tol, max_iter,
+                    self.sigma_L[a:b], self.sigma_R[a:b], self.iters_L[a:b], self.iters_R[a:b])
+                status, dual = max(status, st), min(dual, du)
+            for ik, src in self.mirror.items():
+                self._mirror_tables(ik, src, 0, wl.n_e)
+            self.lead_status, self.lead_dual = status, dual
+            self.last_lead_ranges = [(ik, 0, wl.n_e) for ik in todo]
             return self.sigma_L, self.sigma_R
         cL = N.negf_lead_selfenergy(self.ctx, self.lead_h00, self.lead_h01_L, self.lead_tau_L, self.energy, wl.eta,
                                     tol, max_iter, self.sigma_L, self.iters_L)

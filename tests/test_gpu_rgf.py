@@ -355,3 +355,41 @@ def test_abi_rejects_empty_and_out_of_range_point_ranges():
     ref, tols = _ref_and_tol(wl, [tuple(p) for p in s.points])
     for p, r in enumerate(ref):
         _check_point(out, p, r, 3, tol=tols[p])
+
+
+def test_transpose_batched_exact():
+    from paper_1510_04686_amd import negf as N
+    for n, cnt in [(1, 3), (31, 2), (33, 5), (400, 3)]:
+        a = torch.randn(cnt, n, n, dtype=torch.complex128, device="cuda")
+        b = torch.empty_like(a)
+        N.negf_transpose_batched(a, b)
+        assert torch.equal(b, a.transpose(1, 2))
+
+
+def test_lead_mirror_tables_and_rgf_at_minus_k():
+    """Four k-points: the k = 3 pi / 2 lead tables are the transposes of the
+    k = pi / 2 ones (no decimation of their own).  They match a direct
+    decimation at the lead tolerance, and the RGF outputs at every k match the
+    oracle, which decimates every k-point."""
+    from paper_1510_04686_amd.runtime import RGFSolver
+    wl = make_workload("C2", n_slab=4, n_e=3, n_k=4, n_z=1, n_y=2)
+    s = RGFSolver(wl)
+    assert s.mirror == {3: 1}
+    s.lead_selfenergies()
+    assert s.last_lead_ranges == [(0, 0, wl.n_e), (1, 0, wl.n_e), (2, 0, wl.n_e)]
+    mir_L, mir_R = s.sigma_L.clone(), s.sigma_R.clone()
+    s.mirror = {}
+    s.lead_selfenergies()
+    torch.cuda.synchronize()
+    for a, b in ((mir_L, s.sigma_L), (mir_R, s.sigma_R)):
+        a3, b3 = a[3].cpu().numpy(), b[3].cpu().numpy()
+        assert np.max(np.abs(a3 - b3)) <= 1e-10 * np.max(np.abs(b3))
+    s.mirror = {3: 1}
+    out = s.solve()
+    torch.cuda.synchronize()
+    assert s.status() == 0
+    pts = [tuple(int(x) for x in p) for p in s.points]
+    sel = [i for i, p in enumerate(pts) if p[1] in (1, 3)]
+    ref, tols = P.reference(wl, [pts[i] for i in sel])
+    for i, r, t in zip(sel, ref, tols):
+        P.check_point(out, i, pts[i], r, wl.total_slabs, t)

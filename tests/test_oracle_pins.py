@@ -748,3 +748,24 @@ def test_scba_atom_blocks_invariant_under_orbital_rotations_of_each_atom():
     d0, _ = obs(wl, False)
     d1, _ = obs(wr, False)
     assert np.max(np.abs(d1 - d0)) > 1e-6 * np.max(np.abs(d0))
+
+
+def test_lead_selfenergy_mirror_k_is_transpose():
+    """The cross-section leads (real couplings, h00(-k) = h00(k)^T): the surface
+    Green's function at -k solves the transposed equation, so Sigma(-k) =
+    Sigma(k)^T for both leads; complex couplings break it."""
+    import dataclasses
+    wl = make_workload("C2", n_slab=3, n_e=3, n_k=4, n_z=1, n_y=2)
+    tab = O.lead_tables(wl)
+    for ie in range(wl.n_e):
+        for a in range(2):
+            S1, S3 = tab[(1, ie)][a], tab[(3, ie)][a]
+            assert np.max(np.abs(S3 - S1.T)) < 1e-12 * np.max(np.abs(S1))
+    # a complex (not gauge) change of the couplings: no longer real
+    R = 0.05j * np.random.default_rng(3).normal(size=wl.lead_h01_R.shape)
+    h01 = wl.lead_h01_R + R
+    wc = dataclasses.replace(wl, lead_h01_R=h01, lead_tau_R=h01, lead_h01_L=h01.conj().T,
+                             lead_tau_L=h01.conj().T)
+    tc = O.lead_tables(wc, es=[1])
+    S1, S3 = tc[(1, 1)][1], tc[(3, 1)][1]
+    assert np.max(np.abs(S3 - S1.T)) > 1e-6 * np.max(np.abs(S1))
