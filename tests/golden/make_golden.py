@@ -25,7 +25,8 @@ inputs so a test can tell when the generator has changed since:
 * c4_density.npz -- two alloy samples of the random-alloy ensemble (block 400,
   their own slab counts, all 256 energies): the electron density per atom
   (Eq. 7) and the bond current per slab (Eq. 8) of each sample, with their
-  drift over the variants of tests/parity.py.  The reference of the
+  drift over the variants of tests/parity.py, and per point the drift and
+  largest magnitude of its G^< diagonals.  The reference of the
   mixed-precision accuracy figures.
 
 The full case takes tens of minutes and ~20 GB of host memory; the C4 case
@@ -180,6 +181,8 @@ def c4_case(workers=4):
     chunks = [pts[i::16] for i in range(16)]
     variants = [("ref", None, None), ("alt", "alt", None)] + [(f"perturb{k}", None, k) for k in range(P.N_PERTURB)]
     res = {}
+    ref_gl = None
+    pdrift = np.zeros(len(pts))
     with ProcessPoolExecutor(workers) as ex:
         for name, variant, seed in variants:
             GL, bond = [None] * len(pts), [None] * len(pts)
@@ -189,11 +192,20 @@ def c4_case(workers=4):
                     GL[ci + 16 * j], bond[ci + 16 * j] = g, b
             n, J, _ = O.observables(wl, pts, GL, bond)
             res[name] = (n, J)
+            if ref_gl is None:
+                ref_gl = GL
+            else:                # per-point drift of the G^< diagonals
+                pdrift = np.maximum(pdrift, [P.rel(a, b) for a, b in zip(GL, ref_gl)])
             print(f"  c4 {name} done ({time.time() - t0:.0f} s)", file=sys.stderr, flush=True)
     n, J = res.pop("ref")
     out["n"], out["J"] = n, J
     out["drift_n"] = np.array(max(P.rel(v[0], n) for v in res.values()))
     out["drift_J"] = np.array(max(P.rel(v[1], J) for v in res.values()))
+    # per point: the drift of its G^< diagonals and their largest magnitude, so that
+    # a test can bound the density by the per-point tolerances, weighted as Eq. 7 sums them
+    out["points"] = np.array(pts)
+    out["point_drift_GL"] = pdrift
+    out["point_max_GL"] = np.array([float(np.max(np.abs(g))) for g in ref_gl])
     np.savez_compressed(os.path.join(HERE, "c4_density.npz"), **out)
     print(f"c4_density.npz written ({time.time() - t0:.0f} s)", file=sys.stderr)
 
