@@ -385,6 +385,13 @@ def test_lead_mirror_tables_and_rgf_at_minus_k():
         a3, b3 = a[3].cpu().numpy(), b[3].cpu().numpy()
         assert np.max(np.abs(a3 - b3)) <= 1e-10 * np.max(np.abs(b3))
     s.mirror = {3: 1}
+    # the per-range form (one batch at -k alone): decimates k = pi / 2, transposes into k = 3 pi / 2
+    s.sigma_L.zero_()
+    s.sigma_R.zero_()
+    assert s.lead_selfenergies_for_ranges([(3, 0, wl.n_e)]) == [(1, 0, wl.n_e)]
+    for a_, b_ in ((s.sigma_L[3], mir_L[3]), (s.sigma_R[3], mir_R[3])):
+        assert float((a_ - b_).abs().max()) <= 1e-12 * float(b_.abs().max())
+    s.lead_selfenergies()
     out = s.solve()
     torch.cuda.synchronize()
     assert s.status() == 0
