@@ -500,13 +500,27 @@ int negf_poisson_residual(void* stream, const negf_poisson_grid* grid, const dou
 /* Device bytes of the `work` argument of negf_poisson_solve (-1: bad grid). */
 long long negf_poisson_work_bytes(const negf_poisson_grid* grid);
 
-/* x = L0^-1 rhs by conjugate gradients from x = 0, until ||r|| <= tol ||rhs||
- * or max_iter iterations (checked every 16).  Writes the iteration count and
- * the final relative residual (host outputs; synchronises `stream`).  `work`:
- * negf_poisson_work_bytes bytes of device memory, owned by the caller.
- * Errors: NEGF_EINVAL, NEGF_EHIP. */
-int negf_poisson_solve(void* stream, const negf_poisson_grid* grid, const double* rhs, double* x, double tol,
-                       int max_iter, void* work, int* iters, double* rel_res);
+/* x = (L0 + diag(shift))^-1 rhs by conjugate gradients from x = 0, until
+ * ||r|| <= tol ||rhs|| or max_iter iterations (checked every 16).  shift:
+ * DEVICE [atoms] diagonal (e.g. beta times minus the local part
+ * of dn/dV, the preconditioner of the Newton step; negative entries count as
+ * zero, so the operator stays positive definite), or NULL for L0 alone.
+ * Writes the iteration count and the final relative residual (host outputs;
+ * synchronises `stream`).  `work`: negf_poisson_work_bytes bytes of device
+ * memory, owned by the caller.  Errors: NEGF_EINVAL, NEGF_EHIP. */
+int negf_poisson_solve(void* stream, const negf_poisson_grid* grid, const double* shift, const double* rhs,
+                       double* x, double tol, int max_iter, void* work, int* iters, double* rel_res);
+
+/* The local part of the density Jacobian: for every atom a,
+ *   d_a = g_s sum_p w_e w_k (1/2pi) sum_{o in a} Im(G^R_oo G^<_oo + G^<_oo conj(G^R_oo)),
+ * the o' = o terms of dn_a/dV_a (the full Jacobian also has the products of
+ * G_oo' and G^<_o'o within the atom and between atoms).  GR, GL: orbital
+ * diagonals [p][slab_stride][nb] of the bound points (negf_rgf_backward);
+ * d_out [total_slabs][nb / orbs_per_atom] (DEVICE).  Summed in the fixed
+ * order of negf_observables.  Errors: NEGF_ESTATE, NEGF_EINVAL. */
+int negf_density_jacobian_local(negf_ctx* ctx, void* stream, const negf_c128* GR, const negf_c128* GL,
+                                int slab_stride, const double* w_e, const double* w_k, double g_s,
+                                int orbs_per_atom, double* d_out);
 
 /* Vector kernels of the Newton step's Krylov solver (device arrays; X holds m
  * vectors of length n, row j at X + j * ld).

@@ -34,5 +34,6 @@ from .poisson import (  # noqa: F401
     poisson_boundary,
     density_atoms,
     density_jacobian,
+    density_jacobian_local,
     newton_poisson,
 )

@@ -134,6 +134,24 @@ def density_jacobian(wl, v_atom, points, leads, eta_fill=None):
     return D
 
 
+def density_jacobian_local(wl, v_atom, points, leads, eta_fill=None):
+    """The orbital-diagonal part of dn_a/dV_a per atom (the o' = o terms of
+    ``density_jacobian``'s diagonal), from the orbital diagonals of G^R and G^<:
+      d_a = sum_points c_p sum_{o in a} Im(G_oo G^<_oo + G^<_oo conj(G_oo)).
+    Pinned by: equal to the diagonal of ``density_jacobian`` for one-orbital
+    atoms."""
+    nat, opa = wl.atoms_per_slab, wl.orbs_per_atom
+    v_orb = np.repeat(np.asarray(v_atom, dtype=np.float64), opa, axis=1)
+    w = dataclasses.replace(wl, v_onsite=v_orb)
+    res = solve_points(w, points, leads=leads, diag_only=True, eta_fill=eta_fill)
+    d = np.zeros((wl.total_slabs, nat))
+    for (s, ik, ie), r in zip(points, res):
+        g, gl = r["GR"], r["GL"]
+        c = wl.g_s * wl.w_e[ie] * wl.w_k[ik] / (2 * np.pi)
+        d += c * np.imag(g * gl + gl * np.conj(g)).reshape(wl.total_slabs, nat, opa).sum(axis=2)
+    return d
+
+
 @dataclasses.dataclass
 class PoissonGrid:
     nz: int

@@ -1384,6 +1384,29 @@ int negf_cap_selfenergy(negf_ctx* c, void* stream, const double* w_slab, const i
     return NEGF_OK;
 }
 
+int negf_density_jacobian_local(negf_ctx* c, void* stream, const negf_c128* GR, const negf_c128* GL,
+                                int slab_stride, const double* w_e, const double* w_k, double g_s,
+                                int orbs_per_atom, double* d_out) {
+    if (!c) return NEGF_EINVAL;
+    if (!c->bound) return NEGF_ESTATE;
+    if (!GR || !GL || !w_e || !w_k || !d_out || orbs_per_atom < 1 || c->nb % orbs_per_atom != 0)
+        return NEGF_EINVAL;
+    int maxN = 0;
+    for (size_t s = 0; s + 1 < c->soff_h.size(); ++s) maxN = std::max<long long>(maxN, c->soff_h[s + 1] - c->soff_h[s]);
+    if (slab_stride < maxN) return NEGF_EINVAL;
+    ObsArgs a{};
+    a.GL = reinterpret_cast<const double2*>(GL);
+    a.GR = reinterpret_cast<const double2*>(GR);
+    a.slab_stride = slab_stride; a.w_e = w_e; a.w_k = w_k; a.g_s = g_s;
+    a.opa = orbs_per_atom; a.n = c->nb; a.n_e = c->sys.n_e; a.n_samples = c->sys.n_samples; a.gopa = 1;
+    a.total = c->soff_h.back();
+    a.desc = c->desc_d; a.slab_off = c->soff_d; a.slab_sample = c->slab_sample_d;
+    a.csr_off = c->csr_off_d; a.csr_pts = c->csr_pts_d; a.orb_tmp = c->orb_tmp_d;
+    a.n_out = d_out;
+    NEGF_HIP_CHECK(observables_launch((hipStream_t)stream, a));
+    return NEGF_OK;
+}
+
 int negf_set_scattering_blocks(negf_ctx* c, int opa) {
     if (!c || opa < 1 || opa > 64 || c->nb % opa != 0) return NEGF_EINVAL;
     if (opa == c->scat_opa) return NEGF_OK;

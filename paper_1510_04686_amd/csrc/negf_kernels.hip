@@ -867,7 +867,14 @@ __global__ __launch_bounds__(256) void obs_orbital_kernel(ObsArgs a) {
         for (int t = b; t < e; ++t) {
             const int p = a.csr_pts[t];
             const int ik = a.desc[p].y;
-            se += a.w_k[ik] * a.GL[(((long long)p * a.slab_stride + li) * a.n + o) * a.gopa + o % a.gopa].y;
+            const long long ix = (((long long)p * a.slab_stride + li) * a.n + o) * a.gopa + o % a.gopa;
+            const double2 gl = a.GL[ix];
+            double v = gl.y;
+            if (a.GR) {                  // Im(g gl + gl conj(g)) = 2 Re(g) Im(gl)
+                const double2 g = a.GR[ix];
+                v = 2.0 * g.x * gl.y;
+            }
+            se += a.w_k[ik] * v;
         }
         acc += a.w_e[ie] * se;
     }

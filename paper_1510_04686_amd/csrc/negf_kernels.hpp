@@ -111,6 +111,8 @@ struct ObsArgs {
     double g_s;
     int opa, n, n_e, n_samples;
     int gopa;                           // GL layout: 1 orbital diagonals, > 1 atom blocks [n][gopa]
+    const double2* GR;                  // non-NULL: sum Im(G^R_oo G^<_oo + G^<_oo conj(G^R_oo)) instead of
+                                        // Im G^<_oo (the local part of dn/dV; orbital diagonals only)
     long long total;
     const int4* desc; const long long* slab_off; const int* slab_sample;
     const int* csr_off; const int* csr_pts;

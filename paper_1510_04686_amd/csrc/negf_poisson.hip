@@ -78,13 +78,14 @@ __device__ inline double block_sum(double v, double* red) {
     return red[0];
 }
 
-// Ap = L0 p and the workgroup's partial of p . Ap
-__global__ __launch_bounds__(PB) void cg_apply_kernel(Grid g, const double* p, double* Ap, double* part,
-                                                      long long n) {
+// Ap = (L0 + diag(shift)) p and the workgroup's partial of p . Ap
+__global__ __launch_bounds__(PB) void cg_apply_kernel(Grid g, const double* p, const double* shift, double* Ap,
+                                                      double* part, long long n) {
     __shared__ double red[PB];
     double acc = 0.0;
     for (long long a = (long long)blockIdx.x * PB + threadIdx.x; a < n; a += (long long)gridDim.x * PB) {
-        const double q = stencil(g, p, a, false);
+        double q = stencil(g, p, a, false);
+        if (shift) q = fma(fmax(shift[a], 0.0), p[a], q);     // negative entries count as zero
         Ap[a] = q;
         acc = fma(p[a], q, acc);
     }
@@ -287,8 +288,8 @@ long long negf_poisson_work_bytes(const negf_poisson_grid* g) {
     return (3 * n + RED_MAX + 8) * (long long)sizeof(double);
 }
 
-int negf_poisson_solve(void* stream, const negf_poisson_grid* g, const double* rhs, double* x, double tol,
-                       int max_iter, void* work, int* iters, double* rel_res) {
+int negf_poisson_solve(void* stream, const negf_poisson_grid* g, const double* shift, const double* rhs,
+                       double* x, double tol, int max_iter, void* work, int* iters, double* rel_res) {
     if (!grid_ok(g) || !rhs || !x || !work || !(tol >= 0.0) || max_iter < 1) return NEGF_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const long long n = atoms(g);
@@ -312,7 +313,7 @@ int negf_poisson_solve(void* stream, const negf_poisson_grid* g, const double* r
     while (r0 > 0.0 && std::sqrt(rr) > tol * r0 && it < max_iter) {
         const int k = std::min(CHECK, max_iter - it);
         for (int q = 0; q < k; ++q) {
-            hipLaunchKernelGGL(cg_apply_kernel, dim3(nb), dim3(PB), 0, s, gr, p, Ap, part, n);
+            hipLaunchKernelGGL(cg_apply_kernel, dim3(nb), dim3(PB), 0, s, gr, p, shift, Ap, part, n);
             hipLaunchKernelGGL(cg_alpha_kernel, dim3(1), dim3(PB), 0, s, part, nb, sc);
             hipLaunchKernelGGL(cg_update_kernel, dim3(nb), dim3(PB), 0, s, x, r, p, Ap, sc, part, n);
             hipLaunchKernelGGL(cg_beta_kernel, dim3(1), dim3(PB), 0, s, part, nb, sc);

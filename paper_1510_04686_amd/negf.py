@@ -64,7 +64,7 @@ EXPORTS = [
     "negf_create", "negf_destroy", "negf_workspace_bytes", "negf_sync_status", "negf_error_string",
     "negf_bind", "negf_lead_selfenergy", "negf_lead_selfenergy_pair", "negf_rgf_forward", "negf_rgf_backward",
     "negf_scba_selfenergy", "negf_observables", "negf_rgf_adjoint", "negf_zgemm_batched", "negf_zinv_batched", "negf_mixed_stats",
-    "negf_set_mixed_threshold", "negf_mixed_point_residuals", "negf_mixed_point_scores", "negf_cap_selfenergy", "negf_set_scattering_blocks", "negf_transpose_batched", "negf_gemm_timing_enable", "negf_gemm_timing", "negf_get_tuning", "negf_set_tuning", "negf_autotune",
+    "negf_set_mixed_threshold", "negf_mixed_point_residuals", "negf_mixed_point_scores", "negf_cap_selfenergy", "negf_set_scattering_blocks", "negf_transpose_batched", "negf_density_jacobian_local", "negf_gemm_timing_enable", "negf_gemm_timing", "negf_get_tuning", "negf_set_tuning", "negf_autotune",
     "negf_build_id", "negf_scba_history", "negf_rgf_solve", "negf_zinv_noalloc_bytes", "negf_zinv_batched_noalloc",
     "negf_poisson_apply", "negf_poisson_residual", "negf_poisson_work_bytes", "negf_poisson_solve",
     "negf_vec_work_bytes", "negf_vec_dots", "negf_vec_combine", "negf_vec_norms",
@@ -121,7 +121,8 @@ def lib():
         "negf_poisson_apply": (i, [vp, POINTER(negf_poisson_grid), vp, i, vp]),
         "negf_poisson_residual": (i, [vp, POINTER(negf_poisson_grid), vp, vp, vp, d, vp]),
         "negf_poisson_work_bytes": (ll, [POINTER(negf_poisson_grid)]),
-        "negf_poisson_solve": (i, [vp, POINTER(negf_poisson_grid), vp, vp, d, i, vp, POINTER(i), POINTER(d)]),
+        "negf_poisson_solve": (i, [vp, POINTER(negf_poisson_grid), vp, vp, vp, d, i, vp, POINTER(i), POINTER(d)]),
+        "negf_density_jacobian_local": (i, [vp, vp, vp, vp, i, vp, vp, d, i, vp]),
         "negf_vec_work_bytes": (ll, [ll, i]),
         "negf_vec_dots": (i, [vp, ll, i, vp, ll, vp, vp, vp]),
         "negf_vec_combine": (i, [vp, ll, i, vp, ll, vp, d, vp]),
@@ -439,17 +440,28 @@ def negf_poisson_work_bytes(grid):
     return int(lib().negf_poisson_work_bytes(ctypes.byref(grid)))
 
 
-def negf_poisson_solve(grid, rhs, x, work, tol=1e-12, max_iter=10000, stream=None):
-    """x = L0^-1 rhs (conjugate gradients); returns (iterations, relative residual)."""
+def negf_poisson_solve(grid, rhs, x, work, tol=1e-12, max_iter=10000, stream=None, shift=None):
+    """x = (L0 + diag(shift))^-1 rhs (conjugate gradients); returns (iterations,
+    relative residual)."""
     n = _atoms(grid)
     if work.numel() * work.element_size() < negf_poisson_work_bytes(grid):
         raise ValueError("work too small")
     it, rr = c_int(0), c_double(0.0)
     _check("negf_poisson_solve",
-           lib().negf_poisson_solve(_stream(stream), ctypes.byref(grid), _vec(rhs, n, "rhs"), _vec(x, n, "x"),
-                                    float(tol), int(max_iter), _ptr(work, None, "work"), ctypes.byref(it),
-                                    ctypes.byref(rr)))
+           lib().negf_poisson_solve(_stream(stream), ctypes.byref(grid),
+                                    None if shift is None else _vec(shift, n, "shift"), _vec(rhs, n, "rhs"),
+                                    _vec(x, n, "x"), float(tol), int(max_iter), _ptr(work, None, "work"),
+                                    ctypes.byref(it), ctypes.byref(rr)))
     return it.value, rr.value
+
+
+def negf_density_jacobian_local(ctx, GR, GL, slab_stride, w_e, w_k, g_s, orbs_per_atom, d_out, stream=None):
+    """Per atom, the orbital-diagonal part of dn_a/dV_a into d_out [total_slabs][atoms]."""
+    _check("negf_density_jacobian_local",
+           lib().negf_density_jacobian_local(ctx.handle, _stream(stream), _ptr(GR, torch.complex128, "GR"),
+                                             _ptr(GL, torch.complex128, "GL"), int(slab_stride),
+                                             _ptr(w_e, torch.float64, "w_e"), _ptr(w_k, torch.float64, "w_k"),
+                                             float(g_s), int(orbs_per_atom), _ptr(d_out, torch.float64, "d_out")))
 
 
 def negf_vec_work_bytes(n, m):

@@ -577,13 +577,19 @@ class NewtonPoisson:
       jacobian="fd": the central difference (n(V + h z) - n(V - h z)) / 2h,
         two forward densities per iteration, exact to O(h^2) with or without
         bias (h z at most fd_step eV on any atom).
-    A step whose largest change exceeds max_step (eV) is scaled down to it.
+    Preconditioner: preconditioner="local" (default) solves with
+    L0 + diag(s), s = -beta d, d the orbital-diagonal part of dn_a/dV_a
+    (negf_density_jacobian_local, from the G^R and G^< diagonals of the same
+    pass; entries of s below zero count as zero): where beta dn/dV outweighs L
+    (quantum capacitance) L0 alone leaves GMRES almost stalled; "poisson" uses
+    L0 alone.  A step whose largest change exceeds max_step (eV) is scaled down
+    to it, and halved (up to three times) while max |F| does not decrease.
     Every vector operation runs in the library's kernels; the host keeps the
     small Hessenberg least-squares problem of GMRES."""
 
     def __init__(self, solver, n_z, n_y, beta, n_d, z_gate=False, v_left=0.0, v_right=0.0, v_gate=0.0,
                  max_step=0.1, krylov_dim=20, krylov_tol=1e-3, cg_tol=1e-13, jacobian="adjoint",
-                 fd_step=1e-5):
+                 fd_step=1e-5, preconditioner="local"):
         wl = solver.wl
         if wl.n_samples != 1:
             raise ValueError("the NEGF-Poisson loop runs one device (one sample)")
@@ -591,6 +597,9 @@ class NewtonPoisson:
             raise ValueError("atoms per slab must equal n_z * n_y")
         if jacobian not in ("adjoint", "fd"):
             raise ValueError("jacobian must be 'adjoint' or 'fd'")
+        if preconditioner not in ("local", "poisson"):
+            raise ValueError("preconditioner must be 'local' or 'poisson'")
+        self.local = preconditioner == "local"
         self.s, self.wl = solver, wl
         self.mode, self.fd_step = jacobian, float(fd_step)
         self._V = None
@@ -615,6 +624,8 @@ class NewtonPoisson:
         self.nrm = torch.empty(2, **f64)
         self.stats = {"newton": 0, "krylov": 0, "cg": 0, "density_s": 0.0, "jacobian_s": 0.0}
         self.vp = torch.empty(self.n, **f64)
+        self.dloc = torch.zeros(self.n, **f64)      # local part of dn/dV
+        self.shift = torch.zeros(self.n, **f64)     # -beta dloc (the preconditioner's diagonal)
 
     # -- small helpers (device kernels; one host read each where noted)
     def _norms(self, x):
@@ -637,9 +648,19 @@ class NewtonPoisson:
         import time
         t = time.perf_counter()
         self._set_v(V)
-        self._V = V
-        n = self.s.density().reshape(-1).contiguous()
-        torch.cuda.synchronize(self.s.device)
+        self._V = V.clone()
+        s, wl = self.s, self.wl
+        if self.local:
+            out = s.alloc_outputs(want=("GR", "GL"))
+            s.run_batches(out)
+            n = s.observables(out["GL"], None)[0].reshape(-1).contiguous()
+            N.negf_density_jacobian_local(s.ctx, out["GR"], out["GL"], s.slab_stride, s.w_e, s.w_k, wl.g_s,
+                                          wl.orbs_per_atom, self.dloc.view(wl.total_slabs, -1))
+            self._combine(self.dloc.view(1, -1), [-self.beta], 0.0, self.shift)
+            del out
+        else:
+            n = s.density().reshape(-1).contiguous()
+        torch.cuda.synchronize(s.device)
         self.stats["density_s"] += time.perf_counter() - t
         N.negf_poisson_residual(self.grid, V, n, self.nd, self.beta, self.F)
         return self.F, n
@@ -668,7 +689,8 @@ class NewtonPoisson:
         self.stats["jacobian_s"] += time.perf_counter() - t
 
     def _precond(self, q, z):
-        it, _ = N.negf_poisson_solve(self.grid, q, z, self.pwork, tol=self.cg_tol, max_iter=20 * self.n + 100)
+        it, _ = N.negf_poisson_solve(self.grid, q, z, self.pwork, tol=self.cg_tol, max_iter=20 * self.n + 100,
+                                     shift=self.shift if self.local else None)
         self.stats["cg"] += it
 
     def _gmres(self, rhs, out):
@@ -731,9 +753,9 @@ class NewtonPoisson:
         rhs = torch.empty_like(V)
         self._log = log
         hist = []
+        F, _ = self.residual(V)
+        _, fmax = self._norms(F)
         for it in range(max_newton + 1):
-            F, _ = self.residual(V)
-            _, fmax = self._norms(F)
             hist.append(fmax)
             if log:
                 log(f"newton {it}: max|F| = {fmax:.3e}")
@@ -744,6 +766,17 @@ class NewtonPoisson:
             self._gmres(rhs, dV)
             _, dmax = self._norms(dV)
             scale = min(1.0, self.max_step / max(dmax, 1e-300))
-            self._combine(dV.view(1, -1), [scale], 1.0, V)
+            base = V.clone()
+            for bt in range(4):                            # backtracking on max |F|
+                V.copy_(base)
+                self._combine(dV.view(1, -1), [scale], 1.0, V)
+                F, _ = self.residual(V)
+                _, ft = self._norms(F)
+                if ft < fmax or bt == 3:
+                    break
+                scale *= 0.5
+                if log:
+                    log(f"  step halved to {scale:.3e}")
+            fmax = ft
             self.stats["newton"] += 1
         return V.view(self.wl.total_slabs, -1), hist

@@ -53,6 +53,12 @@ def test_poisson_operator_and_solve_match_oracle(shape, gate):
     _say(f"  CG {it} iterations, relative residual {rr:.1e}")
     assert rr <= 1e-13
     assert np.max(np.abs(x.cpu().numpy() - xs)) <= 1e-11 * np.max(np.abs(xs))
+    # with a diagonal shift (negative entries count as zero)
+    sh = rng.uniform(-0.5, 3.0, size=n)
+    it, rr = N.negf_poisson_solve(g, _cuda(rhs), x, work, tol=1e-13, shift=_cuda(sh))
+    xs = np.linalg.solve(L0 + np.diag(np.maximum(sh, 0.0)), rhs)
+    assert rr <= 1e-13
+    assert np.max(np.abs(x.cpu().numpy() - xs)) <= 1e-11 * np.max(np.abs(xs))
 
 
 def test_krylov_vector_kernels():
@@ -76,14 +82,38 @@ def test_krylov_vector_kernels():
         assert abs(o[0] - y @ y) <= 1e-12 * (y @ y) and o[1] == np.max(np.abs(y))
 
 
+@pytest.mark.parametrize("kind", ["strip", "section"])
+def test_density_jacobian_local_matches_oracle(kind):
+    from paper_1510_04686_amd import negf as N
+    from paper_1510_04686_amd.runtime import RGFSolver
+    from synth import strip_workload
+    if kind == "strip":
+        wl = dataclasses.replace(strip_workload(n_slab=4, n_e=6, e_lo=-3.0, e_hi=3.0), eta=1e-2)
+    else:
+        wl = _tiny(n_slab=3, n_e=8)
+    rng = np.random.default_rng(6)
+    v = rng.uniform(0.0, 0.1, size=(wl.total_slabs, wl.atoms_per_slab))
+    pts = [(0, 0, e) for e in range(wl.n_e)]
+    ref = O.density_jacobian_local(wl, v, pts, O.lead_tables(wl))
+    s = RGFSolver(wl)
+    s.set_potential(_cuda(np.repeat(v, wl.orbs_per_atom, axis=1)))
+    out = s.solve(want=("GR", "GL"))
+    d = torch.zeros((wl.total_slabs, wl.atoms_per_slab), dtype=torch.float64, device="cuda")
+    N.negf_density_jacobian_local(s.ctx, out["GR"], out["GL"], s.slab_stride, s.w_e, s.w_k, wl.g_s,
+                                  wl.orbs_per_atom, d)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(d.cpu().numpy() - ref)) <= 1e-10 * np.max(np.abs(ref))
+
+
 def _tiny(n_slab=4, n_z=1, n_y=2, n_e=48):
     wl = make_workload("C2", n_slab=n_slab, n_e=n_e, n_k=1, n_z=n_z, n_y=n_y)
     return dataclasses.replace(wl, eta=0.05, v_onsite=None)
 
 
-@pytest.mark.parametrize("case,jac", [("chain", "adjoint"), ("section_gated", "fd"),
-                                      ("section_equilibrium", "adjoint")])
-def test_newton_poisson_matches_oracle(case, jac):
+@pytest.mark.parametrize("case,jac,pre", [("chain", "adjoint", "local"), ("chain", "adjoint", "poisson"),
+                                          ("section_gated", "fd", "local"),
+                                          ("section_equilibrium", "adjoint", "local")])
+def test_newton_poisson_matches_oracle(case, jac, pre):
     """The damped Newton loop on the GPU (RGF density, its Jacobian through the
     adjoint or central differences, GMRES preconditioned by the Poisson CG) and
     the oracle's (dense Jacobian) reach the same potential; the GPU's final
@@ -115,7 +145,7 @@ def test_newton_poisson_matches_oracle(case, jac):
         s.set_eta_fill(True)
     s.lead_selfenergies()
     loop = NewtonPoisson(s, nz, ny, beta, nd, z_gate=gate, v_left=0.0, v_right=-0.05, v_gate=0.03,
-                         krylov_tol=1e-6, jacobian=jac)
+                         krylov_tol=1e-6, jacobian=jac, preconditioner=pre)
     V, hist = loop.solve(np.zeros(n0.shape), tol=1e-11, max_newton=60, log=_say)
     assert s.status() == 0
     _say(f"  GPU: {loop.stats}")

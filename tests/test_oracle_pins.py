@@ -769,3 +769,14 @@ def test_lead_selfenergy_mirror_k_is_transpose():
     tc = O.lead_tables(wc, es=[1])
     S1, S3 = tc[(1, 1)][1], tc[(3, 1)][1]
     assert np.max(np.abs(S3 - S1.T)) > 1e-6 * np.max(np.abs(S1))
+
+
+def test_density_jacobian_local_is_the_diagonal_for_one_orbital_atoms():
+    """For one-orbital atoms the o' = o part is the whole diagonal of dn/dV."""
+    wl = strip_workload(n_slab=4, n_e=6, e_lo=-3.0, e_hi=3.0, eta=1e-2)
+    pts = [(0, 0, e) for e in range(wl.n_e)]
+    leads = O.lead_tables(wl)
+    v = np.random.default_rng(4).uniform(0.0, 0.1, size=(wl.total_slabs, wl.atoms_per_slab))
+    D = O.density_jacobian(wl, v, pts, leads)
+    d = O.density_jacobian_local(wl, v, pts, leads)
+    assert np.max(np.abs(d.reshape(-1) - np.diag(D))) < 1e-12 * np.max(np.abs(D))
