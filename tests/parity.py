@@ -33,7 +33,7 @@ import numpy as np
 
 import oracle as O
 
-TOL = 1e-10          # relative FP64 parity bound (the benchmark spec)
+TOL = 1e-10          # relative FP64 parity bound
 FACTOR = 10.0        # x the measured drift, for points that cannot meet TOL in FP64
 N_PERTURB = 3
 U64 = 2.0 ** -53     # unit roundoff of FP64
