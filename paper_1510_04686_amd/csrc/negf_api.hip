@@ -20,6 +20,7 @@ constexpr int DUAL_NBLK = 64;   // blocks of the h01_L = h01_R^dagger check
 constexpr int NBMAX_INV = 32;   // widest Gauss-Jordan panel
 constexpr int EV_POOL = 2048;
 constexpr int SCBA_HMAX = 4096; // SCBA residual history entries kept on the device
+constexpr int SR_CHECK = 4;         // decimation iterations between host reads of the active count
 
 struct TimedLaunch {
     hipEvent_t a, b;
@@ -673,9 +674,17 @@ static int lead_sr(negf_ctx* c, hipStream_t s, int n_k, const negf_c128* h00, co
             std::swap(be, be2);
             hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, s, c->d_count, 0, 1);
             NEGF_HIP_CHECK(sr_launch_check(s, a, al, be, it));
-            NEGF_HIP_CHECK(hipMemcpyAsync(c->h_pinned, c->d_count, sizeof(int), hipMemcpyDeviceToHost, s));
-            NEGF_HIP_CHECK(hipStreamSynchronize(s));
-            active = c->h_pinned[0];
+            // The host reads the active count every SR_CHECK iterations only: a point
+            // that has converged is frozen (its workgroups exit at once and its flag
+            // stays set), so the iterations run past the last convergence change
+            // nothing, and the loop needs a quarter of the host synchronisations.
+            // With GEMM timing on, every iteration's count is read: the timed launches
+            // are credited with the products of the points still active.
+            if (c->timing || it % SR_CHECK == 0 || it == max_iter) {
+                NEGF_HIP_CHECK(hipMemcpyAsync(c->h_pinned, c->d_count, sizeof(int), hipMemcpyDeviceToHost, s));
+                NEGF_HIP_CHECK(hipStreamSynchronize(s));
+                active = c->h_pinned[0];
+            }
         }
         if (active > 0) noconv = true;
         // g_s = (z - eps_s)^-1 ; Sigma = tau g_s tau^dagger  (then the same for the dual surface)
