@@ -58,7 +58,7 @@ def poisson_record(args, wl, solver):
     beta = 18.0951 / (11.7 * 0.2715)
     loop = NewtonPoisson(solver, nz, ny, beta, n0 + 1e-3, v_left=float(v0[0].mean()),
                          v_right=float(v0[-1].mean()), jacobian=args.poisson_jacobian, krylov_dim=20,
-                         krylov_tol=1e-3)
+                         krylov_tol=1e-4)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     V, hist = loop.solve(v0, tol=1e-9, max_newton=args.poisson,
@@ -68,6 +68,7 @@ def poisson_record(args, wl, solver):
     st = dict(loop.stats)
     return {"newton_steps": st["newton"], "krylov_iterations": st["krylov"], "cg_iterations": st["cg"],
             "jacobian": args.poisson_jacobian, "equilibrium": bool(wl.mu_L == wl.mu_R),
+            "preconditioner": "local", "eta": wl.eta,
             "seconds": dt, "seconds_per_newton_step": dt / max(st["newton"], 1),
             "density_seconds": st["density_s"], "jacobian_seconds": st["jacobian_s"],
             "max_residual_history": hist, "atoms": int(wl.total_slabs * wl.atoms_per_slab),
@@ -149,7 +150,10 @@ def main():
                     help="C5 (or any single-sample workload): after the timed steps, at most K Newton steps of "
                          "the NEGF-Poisson loop (Eq. 9) from the workload's potential, reported in a 'poisson' record")
     ap.add_argument("--poisson-jacobian", default="adjoint", choices=["adjoint", "fd"])
-    ap.add_argument("--equilibrium", action="store_true", help="set mu_R = mu_L (one Fermi level)")
+    ap.add_argument("--equilibrium", action="store_true",
+                    help="set mu_R = mu_L and fill the device's eta sink at that level (one Fermi level)")
+    ap.add_argument("--n-k", type=int, default=None, help="shrink the k grid (not for reported runs)")
+    ap.add_argument("--eta", type=float, default=None, help="override the broadening eta (eV)")
     ap.add_argument("--lanes", type=int, default=1,
                     help="batches in flight at once, each on its own context and stream")
     ap.add_argument("--store", default="full", choices=["full", "checkpoint"],
@@ -183,6 +187,8 @@ def main():
     kw = {}
     if args.n_e:
         kw["n_e"] = args.n_e
+    if args.n_k:
+        kw["n_k"] = args.n_k
     if args.workload == "C4" and args.samples:
         kw["n_samples"] = args.samples
     if args.cap_slabs:
@@ -190,15 +196,20 @@ def main():
             sys.exit("--cap-slabs applies to C2 and C4")
         kw["cap_slabs"] = args.cap_slabs
     wl = make_workload(args.workload, **kw)
-    if args.equilibrium:
+    if args.equilibrium or args.eta is not None:
         import dataclasses
-        wl = dataclasses.replace(wl, mu_R=wl.mu_L)
+        if args.equilibrium:
+            wl = dataclasses.replace(wl, mu_R=wl.mu_L)
+        if args.eta is not None:
+            wl = dataclasses.replace(wl, eta=args.eta)
     print(f"[bench] workload {args.workload}: nb={wl.nb} samples={wl.n_samples} slabs={wl.total_slabs} "
           f"n_k={wl.n_k} n_e={wl.n_e} precision={args.precision}", file=sys.stderr, flush=True)
     adj_seg = -1 if (args.workload == "C5" or (args.poisson and args.poisson_jacobian == "adjoint")) else 0
     solver = RGFSolver(wl, precision=args.precision, capacity=args.capacity, adjoint_segment=adj_seg,
                        tune="auto" if args.tune == "auto" else None, lanes=args.lanes, point_redo=args.point_redo,
                        store=args.store, redo_frac=args.redo_frac or None)
+    if args.equilibrium:
+        solver.set_eta_fill(True)
     print(f"[bench] capacity={solver.capacity} points/batch, workspace "
           f"{sum(N.negf_workspace_bytes(c) for c in solver.ctxs) / 2**30:.1f} GiB", file=sys.stderr, flush=True)
     n_iter = (args.scba_iters or wl.n_scba) if args.workload == "C3" else 1
