@@ -521,6 +521,14 @@ def observables(wl, points, GLd, bond, g_s=None):
 # Differentiation: VJP of the density with respect to the onsite potential
 # ---------------------------------------------------------------------------
 
+def _cap_terms(wl, ie, a0, a1):
+    """Absorbing-contact self-energies of the slabs [a0, a1) at energy ie, or None."""
+    if getattr(wl, "cap_w", None) is None:
+        return None, None
+    cR, cL = cap_selfenergy(wl)
+    return cR[ie, a0:a1], cL[ie, a0:a1]
+
+
 def density_objective(wl, w_atom, v_orb, points, leads):
     """f(V) = sum_a w_a n_a(V) for the given onsite potential (per orbital)."""
     nat, opa = wl.atoms_per_slab, wl.orbs_per_atom
@@ -530,8 +538,9 @@ def density_objective(wl, w_atom, v_orb, points, leads):
         hd, hu, _ = wl.sample_blocks(int(s), int(ik))
         E = float(wl.energy[ie])
         sL, sR = leads[(int(ik), int(ie))][:2]
+        scR, scL = _cap_terms(wl, ie, a0, a1)
         r = rgf(hd, hu, E, wl.eta, sL, sR, float(fermi(E, wl.mu_L, wl.kT)),
-                float(fermi(E, wl.mu_R, wl.kT)), v=[v_orb[i] for i in range(a0, a1)])
+                float(fermi(E, wl.mu_R, wl.kT)), v=[v_orb[i] for i in range(a0, a1)], scatR=scR, scatL=scL)
         im = np.imag(np.diagonal(r["GL"], axis1=1, axis2=2)).reshape(a1 - a0, nat, opa).sum(axis=2)
         f += wl.g_s * wl.w_e[ie] * wl.w_k[ik] / (2 * np.pi) * float(np.sum(w_atom[a0:a1] * im))
     return f
@@ -553,8 +562,10 @@ def dense_grad(wl, w_atom, v_orb, points, leads):
         hd, hu, _ = wl.sample_blocks(int(s), int(ik))
         E = float(wl.energy[ie])
         sL, sR = leads[(int(ik), int(ie))][:2]
+        scR, scL = _cap_terms(wl, ie, a0, a1)
         r = dense(hd, hu, E, wl.eta, sL, sR, float(fermi(E, wl.mu_L, wl.kT)),
-                  float(fermi(E, wl.mu_R, wl.kT)), v=[v_orb[i] for i in range(a0, a1)], full=True)
+                  float(fermi(E, wl.mu_R, wl.kT)), v=[v_orb[i] for i in range(a0, a1)], scatR=scR, scatL=scL,
+                  full=True)
         wdiag = np.repeat(np.asarray(w_atom[a0:a1]).reshape(-1), opa)
         X = r["Gl"] @ (wdiag[:, None] * r["G"])
         c = wl.g_s * wl.w_e[ie] * wl.w_k[ik] / (2 * np.pi)

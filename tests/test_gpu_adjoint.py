@@ -134,3 +134,24 @@ def test_checkpointed_stores_equal_full_stores(segment, precision):
         res[store] = r
     for k in res["full"]:
         assert np.array_equal(res["full"][k], res["checkpoint"][k]), k
+
+
+@pytest.mark.parametrize("store", ["full", "checkpoint"])
+def test_adjoint_with_absorbing_contacts_matches_dense_gradient(store):
+    """Disordered absorbing-potential contacts: the adjoint's recomputed forward
+    slabs carry the contact self-energies too (two ragged samples, two batches)."""
+    from synth.workloads import cross_section_workload
+    _say(f"adjoint with absorbing contacts, store={store}")
+    wl = cross_section_workload("cap", 1, 2, [3, 2], 1, np.linspace(-0.5, 0.5, 2), 17, cap_slabs=3, cap_w=0.5,
+                                eta=1e-3)
+    rng = np.random.default_rng(10)
+    wl.v_onsite = rng.uniform(0, 0.1, size=(wl.total_slabs, wl.nb))
+    w = rng.normal(size=(wl.total_slabs, wl.atoms_per_slab))
+    s = _solver(wl, capacity=2, adjoint_segment=2, store=store)
+    s.density()
+    g = s.density_vjp(torch.from_numpy(w)).cpu().numpy()
+    torch.cuda.synchronize()
+    assert s.status() == 0
+    pts = [tuple(p) for p in s.points]
+    ref = O.dense_grad(wl, w, wl.v_onsite, pts, O.lead_tables(wl))
+    assert _rel(g, ref) < 1e-10

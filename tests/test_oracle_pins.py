@@ -780,3 +780,22 @@ def test_density_jacobian_local_is_the_diagonal_for_one_orbital_atoms():
     D = O.density_jacobian(wl, v, pts, leads)
     d = O.density_jacobian_local(wl, v, pts, leads)
     assert np.max(np.abs(d.reshape(-1) - np.diag(D))) < 1e-12 * np.max(np.abs(D))
+
+
+def test_dense_grad_with_absorbing_contacts_matches_finite_differences():
+    from synth.workloads import cross_section_workload
+    wl = cross_section_workload("cap", 1, 2, [3], 1, np.linspace(-0.5, 0.5, 2), 17, cap_slabs=3, cap_w=0.5,
+                                eta=1e-3)
+    pts = [(0, 0, ie) for ie in range(wl.n_e)]
+    leads = O.lead_tables(wl)
+    rng = np.random.default_rng(6)
+    w = rng.normal(size=(wl.total_slabs, wl.atoms_per_slab))
+    v = rng.uniform(0, 0.1, size=(wl.total_slabs, wl.nb))
+    g = O.dense_grad(wl, w, v, pts, leads)
+    h = 1e-5
+    for (s, a) in [(0, 0), (3, 1), (5, 0), (8, 1)]:
+        vp, vm = v.copy(), v.copy()
+        vp[s, a * 10:(a + 1) * 10] += h
+        vm[s, a * 10:(a + 1) * 10] -= h
+        fd = (O.density_objective(wl, w, vp, pts, leads) - O.density_objective(wl, w, vm, pts, leads)) / (2 * h)
+        assert abs(fd - g[s, a]) < 1e-6 * np.max(np.abs(g)) + 1e-12
