@@ -239,13 +239,28 @@ class RGFSolver:
         return self.sigma_L, self.sigma_R
 
     def _scat(self, scat_R, scat_L):
+        """The self-energies the forward sweep adds to the diagonal blocks: the
+        caller's scattering terms, plus the absorbing contacts' on a workload
+        that has them (summed into buffers of the solver by negf_vec_combine,
+        so that this also runs inside a captured graph)."""
         if not self.cap:
             return scat_R, scat_L
-        if scat_R is not None or scat_L is not None:
-            raise NotImplementedError("scattering self-energies on top of absorbing contacts")
         if self.cap_R is None:
             self._cap_contacts()
-        return self.cap_R, self.cap_L
+        if scat_R is None and scat_L is None:
+            return self.cap_R, self.cap_L
+        if scat_R is None or scat_L is None or scat_R.shape != self.cap_R.shape:
+            raise ValueError("with absorbing contacts, scattering self-energies must be orbital-diagonal "
+                             "[n_e][total_slabs][nb] and given for both R and <")
+        if getattr(self, "_tot_R", None) is None:
+            self._tot_R = torch.empty_like(self.cap_R)
+            self._tot_L = torch.empty_like(self.cap_L)
+            self._one = torch.ones(1, dtype=torch.float64, device=self.device)
+        for src, cap, tot in ((scat_R, self.cap_R, self._tot_R), (scat_L, self.cap_L, self._tot_L)):
+            t = torch.view_as_real(tot).view(1, -1)
+            N.negf_vec_combine(torch.view_as_real(src).reshape(1, -1), 1, self._one, 0.0, t.view(-1))
+            N.negf_vec_combine(torch.view_as_real(cap).reshape(1, -1), 1, self._one, 1.0, t.view(-1))
+        return self._tot_R, self._tot_L
 
     def lead_selfenergies_for(self, p0, np_, tol=1e-14, max_iter=100):
         """Lead self-energies of only the (k, E) points that the batch [p0, p0 + np_)

@@ -86,3 +86,30 @@ def test_cap_contacts_match_exact_leads_on_gpu():
     _say(f"  exact leads {j0}, absorbing contacts {j1}")
     assert np.all(np.abs(j0) > 1.0)
     assert np.max(np.abs(j1 - j0) / np.abs(j0)) < 2e-3
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_scba_with_absorbing_contacts_matches_oracle(graph):
+    """Phonon scattering (acoustic + optical) in a device whose disordered
+    contacts are absorbing regions: the Born loop adds its self-energies to the
+    contacts' on the device (also inside the captured graph)."""
+    from paper_1510_04686_amd.runtime import RGFSolver
+    energy = np.linspace(-0.2, 0.2, 9)
+    hw = 2 * (energy[1] - energy[0])
+    wl = cross_section_workload("cap", 1, 2, [3], 1, energy, 23, cap_slabs=4, cap_w=0.5, eta=0.05,
+                                D_ac=0.02, M_op=0.03, hw_op=hw, shift=2, n_bose=1.0 / np.expm1(hw / 0.025852),
+                                n_scba=4)
+    ref = O.scba(wl, 4)
+    s = RGFSolver(wl)
+    out, hist = s.scba(n_iter=4, graph=graph)
+    torch.cuda.synchronize()
+    assert s.status() == 0
+    for got, want in ((s.scat_R, ref["sigR"]), (s.scat_L, ref["sigL"])):
+        err = float(np.max(np.abs(got.cpu().numpy() - want)) / np.max(np.abs(want)))
+        _say(f"  Sigma_scat rel err {err:.2e}")
+        assert err < 1e-10
+    d = lambda x: np.diagonal(x, axis1=1, axis2=2)
+    for key in ("GR", "GL"):
+        got = out[key].cpu().numpy()[:, :wl.total_slabs]
+        want = np.array([d(r[key]) for r in ref["res"]])
+        assert float(np.max(np.abs(got - want)) / np.max(np.abs(want))) < 1e-10
