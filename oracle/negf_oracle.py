@@ -521,16 +521,21 @@ def observables(wl, points, GLd, bond, g_s=None):
 # Differentiation: VJP of the density with respect to the onsite potential
 # ---------------------------------------------------------------------------
 
-def _cap_terms(wl, ie, a0, a1):
-    """Absorbing-contact self-energies of the slabs [a0, a1) at energy ie, or None."""
-    if getattr(wl, "cap_w", None) is None:
-        return None, None
-    cR, cL = cap_selfenergy(wl)
-    return cR[ie, a0:a1], cL[ie, a0:a1]
+def _cap_terms(wl, ie, a0, a1, scatR=None, scatL=None):
+    """The diagonal self-energies of the slabs [a0, a1) at energy ie: the given
+    scattering ones [n_e, total_slabs, b] plus the absorbing contacts', or None."""
+    R = None if scatR is None else scatR[ie, a0:a1]
+    L = None if scatL is None else scatL[ie, a0:a1]
+    if getattr(wl, "cap_w", None) is not None:
+        cR, cL = cap_selfenergy(wl)
+        R = cR[ie, a0:a1] if R is None else R + cR[ie, a0:a1]
+        L = cL[ie, a0:a1] if L is None else L + cL[ie, a0:a1]
+    return R, L
 
 
-def density_objective(wl, w_atom, v_orb, points, leads):
-    """f(V) = sum_a w_a n_a(V) for the given onsite potential (per orbital)."""
+def density_objective(wl, w_atom, v_orb, points, leads, scatR=None, scatL=None):
+    """f(V) = sum_a w_a n_a(V) for the given onsite potential (per orbital),
+    with fixed scattering self-energies if given."""
     nat, opa = wl.atoms_per_slab, wl.orbs_per_atom
     f = 0.0
     for s, ik, ie in points:
@@ -538,7 +543,7 @@ def density_objective(wl, w_atom, v_orb, points, leads):
         hd, hu, _ = wl.sample_blocks(int(s), int(ik))
         E = float(wl.energy[ie])
         sL, sR = leads[(int(ik), int(ie))][:2]
-        scR, scL = _cap_terms(wl, ie, a0, a1)
+        scR, scL = _cap_terms(wl, ie, a0, a1, scatR, scatL)
         r = rgf(hd, hu, E, wl.eta, sL, sR, float(fermi(E, wl.mu_L, wl.kT)),
                 float(fermi(E, wl.mu_R, wl.kT)), v=[v_orb[i] for i in range(a0, a1)], scatR=scR, scatL=scL)
         im = np.imag(np.diagonal(r["GL"], axis1=1, axis2=2)).reshape(a1 - a0, nat, opa).sum(axis=2)
@@ -546,7 +551,7 @@ def density_objective(wl, w_atom, v_orb, points, leads):
     return f
 
 
-def dense_grad(wl, w_atom, v_orb, points, leads):
+def dense_grad(wl, w_atom, v_orb, points, leads, scatR=None, scatL=None):
     """Gradient of f(V) = sum_a w_a n_a with respect to the per-atom potential.
 
     From dG^R = G^R dV G^R and dG^< = G^R dV G^< + G^< dV G^A:
@@ -562,7 +567,7 @@ def dense_grad(wl, w_atom, v_orb, points, leads):
         hd, hu, _ = wl.sample_blocks(int(s), int(ik))
         E = float(wl.energy[ie])
         sL, sR = leads[(int(ik), int(ie))][:2]
-        scR, scL = _cap_terms(wl, ie, a0, a1)
+        scR, scL = _cap_terms(wl, ie, a0, a1, scatR, scatL)
         r = dense(hd, hu, E, wl.eta, sL, sR, float(fermi(E, wl.mu_L, wl.kT)),
                   float(fermi(E, wl.mu_R, wl.kT)), v=[v_orb[i] for i in range(a0, a1)], scatR=scR, scatL=scL,
                   full=True)

@@ -456,17 +456,21 @@ class RGFSolver:
         return n, J, jE
 
     # ------------------------------------------------------------------ adjoint
-    def density(self):
-        """Electron density per atom (Eq. 7) for the current potential."""
+    def density(self, scat_R=None, scat_L=None):
+        """Electron density per atom (Eq. 7) for the current potential (with the
+        given orbital-diagonal scattering self-energies, if any)."""
         if self.sigma_L is None:
             self.lead_selfenergies()
         out = self.alloc_outputs(want=("GL",))
-        self.run_batches(out)
+        self.run_batches(out, scat_R=scat_R, scat_L=scat_L)
         n, _, _ = self.observables(out["GL"], None)
         return n
 
-    def density_vjp(self, w_atom):
-        """grad_V (per atom) of sum_a w_a n_a through the adjoint RGF."""
+    def density_vjp(self, w_atom, scat_R=None, scat_L=None):
+        """grad_V (per atom) of sum_a w_a n_a through the adjoint RGF, at the
+        potential of the last forward pass and with the scattering
+        self-energies it used (held fixed: their own dependence on V, through
+        the Born loop, is not differentiated)."""
         wl = self.wl
         w_orb = w_atom.to(device=self.device, dtype=torch.float64).reshape(wl.total_slabs, -1)
         w_orb = w_orb.repeat_interleave(wl.orbs_per_atom, dim=1).contiguous()
@@ -478,7 +482,7 @@ class RGFSolver:
             batches.insert(0, self._last_fwd)
         for p0, np_ in batches:
             if self._last_fwd != (p0, np_):
-                N.negf_rgf_forward(self.ctx, p0, np_, self.sigma_L, self.sigma_R, *self._scat(None, None))
+                N.negf_rgf_forward(self.ctx, p0, np_, self.sigma_L, self.sigma_R, *self._scat(scat_R, scat_L))
                 self._last_fwd = (p0, np_)
             N.negf_rgf_adjoint(self.ctx, p0, np_, w_orb, dX, self.slab_stride)
         g, _, _ = self.observables(dX, None)

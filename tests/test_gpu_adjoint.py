@@ -155,3 +155,25 @@ def test_adjoint_with_absorbing_contacts_matches_dense_gradient(store):
     pts = [tuple(p) for p in s.points]
     ref = O.dense_grad(wl, w, wl.v_onsite, pts, O.lead_tables(wl))
     assert _rel(g, ref) < 1e-10
+
+
+@pytest.mark.parametrize("store", ["full", "checkpoint"])
+def test_adjoint_with_fixed_scattering_matches_dense_gradient(store):
+    """dn/dV at fixed scattering self-energies (a frozen Born-loop state): the
+    forward pass and the adjoint's recomputed slabs both carry them."""
+    _say(f"adjoint with fixed Sigma_scat, store={store}")
+    wl = _tiny(seed=11, n_e=3)
+    rng = np.random.default_rng(13)
+    shp = (wl.n_e, wl.total_slabs, wl.nb)
+    sR = 0.02 * rng.normal(size=shp) - 0.03j * rng.uniform(size=shp)
+    sL = 0.02j * rng.uniform(size=shp)
+    w = rng.normal(size=(wl.total_slabs, wl.atoms_per_slab))
+    s = _solver(wl, capacity=2, adjoint_segment=2, store=store)
+    tR, tL = torch.from_numpy(sR).cuda(), torch.from_numpy(sL).cuda()
+    s.density(tR, tL)
+    g = s.density_vjp(torch.from_numpy(w), tR, tL).cpu().numpy()
+    torch.cuda.synchronize()
+    assert s.status() == 0
+    pts = [tuple(p) for p in s.points]
+    ref = O.dense_grad(wl, w, wl.v_onsite, pts, O.lead_tables(wl), sR, sL)
+    assert _rel(g, ref) < 1e-10

@@ -799,3 +799,26 @@ def test_dense_grad_with_absorbing_contacts_matches_finite_differences():
         vm[s, a * 10:(a + 1) * 10] -= h
         fd = (O.density_objective(wl, w, vp, pts, leads) - O.density_objective(wl, w, vm, pts, leads)) / (2 * h)
         assert abs(fd - g[s, a]) < 1e-6 * np.max(np.abs(g)) + 1e-12
+
+
+def test_dense_grad_with_fixed_scattering_matches_finite_differences():
+    wl = make_workload("C5", n_slab=3, n_e=2, n_z=1, n_y=2)
+    wl.eta = 1e-3
+    pts = [(0, 0, ie) for ie in range(wl.n_e)]
+    leads = O.lead_tables(wl)
+    rng = np.random.default_rng(12)
+    shp = (wl.n_e, wl.total_slabs, wl.nb)
+    sR = 0.02 * rng.normal(size=shp) - 0.03j * rng.uniform(size=shp)
+    sL = 0.02j * rng.uniform(size=shp)
+    w = rng.normal(size=(wl.total_slabs, wl.atoms_per_slab))
+    v = wl.v_onsite.copy()
+    g = O.dense_grad(wl, w, v, pts, leads, sR, sL)
+    assert np.max(np.abs(g - O.dense_grad(wl, w, v, pts, leads))) > 1e-6 * np.max(np.abs(g))
+    h = 1e-5
+    for (s, a) in [(0, 0), (1, 1), (2, 0)]:
+        vp, vm = v.copy(), v.copy()
+        vp[s, a * 10:(a + 1) * 10] += h
+        vm[s, a * 10:(a + 1) * 10] -= h
+        fd = (O.density_objective(wl, w, vp, pts, leads, sR, sL)
+              - O.density_objective(wl, w, vm, pts, leads, sR, sL)) / (2 * h)
+        assert abs(fd - g[s, a]) < 1e-6 * np.max(np.abs(g)) + 1e-12
