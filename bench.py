@@ -248,7 +248,9 @@ def main():
         solver.lead_selfenergies()
         ranges = list(solver.last_lead_ranges)
         if args.workload == "C3":
-            o, hist = solver.scba(n_iter=n_iter, graph=True, atom_blocks=args.atom_blocks)
+            o, hist = solver.scba(n_iter=n_iter, graph=True, atom_blocks=args.atom_blocks,
+                                  progress=lambda i, n: print(f"[bench]   SCBA iteration {i}/{n} done",
+                                                              file=sys.stderr, flush=True))
             return (*solver.observables(o["GL"], o["bond"]), solver.n_points, ranges)
         if args.workload == "C5":
             return solver.density(), None, None, solver.n_points, ranges

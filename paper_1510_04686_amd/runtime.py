@@ -499,7 +499,7 @@ class RGFSolver:
         return max(codes)
 
     # ------------------------------------------------------------------ SCBA
-    def scba(self, n_iter=None, graph=True, atom_blocks=False):
+    def scba(self, n_iter=None, graph=True, atom_blocks=False, progress=None):
         """Self-consistent Born loop (Eqs. 1-6) for a single-sample grid
         workload.  One iteration = scattering self-energy update from the last
         diagonals + a full forward/backward pass; captured once into a HIP
@@ -507,7 +507,9 @@ class RGFSolver:
         local self-energies from the atom blocks (orbs_per_atom square) of the
         diagonal blocks instead of the orbital diagonals; the outputs are then
         atom blocks [P][slab][nb][orbs_per_atom] (negf_set_scattering_blocks,
-        which stays set on the solver's contexts)."""
+        which stays set on the solver's contexts).  progress(i, n): called after
+        iteration i, after waiting for it (one host synchronisation per
+        iteration; without it the replays run with no host read)."""
         wl = self.wl
         assert wl.n_samples == 1
         n_iter = wl.n_scba if n_iter is None else n_iter
@@ -534,8 +536,11 @@ class RGFSolver:
             self.run_batches(out, full_blocks=fb, scat_R=self.scat_R, scat_L=self.scat_L, stream=stream)
 
         if n_iter <= 1 or not graph:
-            for _ in range(n_iter - 1):
+            for i in range(n_iter - 1):
                 one_iteration()
+                if progress:
+                    torch.cuda.synchronize(self.device)
+                    progress(i + 2, n_iter)
         else:
             g = torch.cuda.CUDAGraph()
             s = torch.cuda.Stream()
@@ -546,8 +551,11 @@ class RGFSolver:
                 one_iteration(stream=s)
             torch.cuda.current_stream().wait_stream(s)
             # the residuals stay on the device: no host read between replays
-            for _ in range(n_iter - 1):
+            for i in range(n_iter - 1):
                 g.replay()
+                if progress:
+                    torch.cuda.synchronize(self.device)
+                    progress(i + 2, n_iter)
         # last update: Sigma_n from the n-th solve (the solve itself is not redone)
         N.negf_scba_selfenergy(self.ctx, out["GR"], out["GL"], self.slab_stride, self.w_k, wl.D_ac, wl.M_op,
                                wl.shift, wl.n_bose, self.scat_R, self.scat_L, None)
