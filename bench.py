@@ -6,16 +6,23 @@ Prints ONE JSON line.
 
 Workloads (default C2, the block-400 headline):
   C2  one step = one batch of bound points (512 points: the 512 energies of one
-      k-point): that batch's lead self-energies (Sancho-Rubio, FP64), its
-      forward + backward RGF sweeps, and the density / current reductions over
-      the point set.  Steps cycle through the 8 batches (k-points) of the
-      4096-point workload, so 8 steps make one full pass.
+      k-point), or the two batches at k and -k, whose lead tables come from one
+      decimation (the -k tables by transposition): their lead self-energies
+      (Sancho-Rubio, FP64), forward + backward RGF sweeps, and the density /
+      current reductions over the point set.  Steps cycle through the 5 groups
+      of the 8 batches (k-points) of the 4096-point workload, so 5 steps make
+      one full pass.
   C1  one step = the whole 256-point workload (one batch)
   C4  one step = leads + every batch of the alloy ensemble + reductions
   C3  one step = leads + the SCBA loop (iteration replayed from a HIP graph)
   C5  one step = leads + forward density; the adjoint dn/dV (VJP) is timed
       after the steps and reported as a cost ratio
 Inputs are resident in HBM before the timed region starts.
+
+    python bench.py --kernel-sweep 384,400,448 [--sweep-dtype f64|f32]
+
+times the batched GEMM and block inverse alone at those block sizes (one JSON
+line per size) instead of the step.
 """
 from __future__ import annotations
 
@@ -124,6 +131,52 @@ def cpu_baseline(wl, max_points=16, budget_s=15.0, seed=0):
                       f"decimations, {dt:.1f} s on the host"}
 
 
+def kernel_sweep(sizes, dtype_name, reps=10):
+    """Rates of the two dense kernels alone: the batched complex GEMM (C = A B,
+    counted as 8 n^3 real flops per product) and the batched block inverse
+    (counted as 8 n^3 per inverse, the Gauss-Jordan count), at each block size,
+    with a batch that fills the chip; HIP events on the launch stream."""
+    import torch
+    from paper_1510_04686_amd import negf as N
+    dt = torch.complex128 if dtype_name == "f64" else torch.complex64
+    rows = []
+    for n in sizes:
+        batch = 512 if n <= 512 else (128 if n <= 800 else (64 if n <= 1200 else 32))
+        ctx = N.negf_create(n, 1, batch, N.NEGF_FP64 if dtype_name == "f64" else N.NEGF_MIXED)
+        g = torch.Generator(device="cuda").manual_seed(n)
+        A = torch.randn((batch, n, n), dtype=dt, device="cuda", generator=g)
+        B = torch.randn((batch, n, n), dtype=dt, device="cuda", generator=g)
+        C = torch.empty_like(A)
+        s = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        rec = {"n": n, "batch": batch, "dtype": dtype_name}
+        for name, call in (("gemm", lambda: N.negf_zgemm_batched(ctx, A, B, C, stream=s)),
+                           ("inverse", lambda: N.negf_zinv_batched(ctx, A.clone(), C, stream=s))):
+            call()
+            torch.cuda.synchronize()
+            ms = 0.0
+            for _ in range(reps):
+                if name == "inverse":
+                    W = A.clone()
+                    e0.record(s)
+                    N.negf_zinv_batched(ctx, W, C, stream=s)
+                    e1.record(s)
+                else:
+                    e0.record(s)
+                    call()
+                    e1.record(s)
+                torch.cuda.synchronize()
+                ms += e0.elapsed_time(e1)
+            ms /= reps
+            rec[name + "_ms"] = ms
+            rec[name + "_tflops"] = 8.0 * n ** 3 * batch / ms / 1e9
+        print(json.dumps(rec), flush=True)
+        rows.append(rec)
+        del A, B, C, ctx
+        torch.cuda.empty_cache()
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -161,6 +214,9 @@ def main():
     ap.add_argument("--tune", default="auto", choices=["auto", "default"],
                     help="kernel shapes: measured on this GPU before timing (auto) or the library defaults")
     ap.add_argument("--cpu-points", type=int, default=16, help="oracle points at most (about 15 s of host time)")
+    ap.add_argument("--kernel-sweep", default="", metavar="N1,N2,...",
+                    help="instead of the step: time the batched GEMM and block inverse alone at these block sizes")
+    ap.add_argument("--sweep-dtype", default="f64", choices=["f64", "f32"])
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -176,6 +232,9 @@ def main():
     from synth import make_workload
 
     N.lib()   # fail loudly if the HIP library is missing
+    if args.kernel_sweep:
+        kernel_sweep([int(x) for x in args.kernel_sweep.split(",")], args.sweep_dtype)
+        return
     if args.copy_calibration > 0:
         nbytes = args.copy_calibration << 20
         src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
