@@ -499,7 +499,7 @@ class RGFSolver:
         return max(codes)
 
     # ------------------------------------------------------------------ SCBA
-    def scba(self, n_iter=None, graph=True, atom_blocks=False, progress=None):
+    def scba(self, n_iter=None, graph=True, atom_blocks=False, progress=None, tol=None):
         """Self-consistent Born loop (Eqs. 1-6) for a single-sample grid
         workload.  One iteration = scattering self-energy update from the last
         diagonals + a full forward/backward pass; captured once into a HIP
@@ -509,7 +509,12 @@ class RGFSolver:
         atom blocks [P][slab][nb][orbs_per_atom] (negf_set_scattering_blocks,
         which stays set on the solver's contexts).  progress(i, n): called after
         iteration i, after waiting for it (one host synchronisation per
-        iteration; without it the replays run with no host read)."""
+        iteration; without it the replays run with no host read).
+        tol: stop at the first update whose residual ||dSigma|| / ||Sigma|| is
+        below tol (at most n_iter updates): the update and the solve are then
+        two graphs (or eager calls) with one residual read between them, and
+        the outputs are the last solve's with the self-energy of that update,
+        as after a fixed count."""
         wl = self.wl
         assert wl.n_samples == 1
         n_iter = wl.n_scba if n_iter is None else n_iter
@@ -530,10 +535,45 @@ class RGFSolver:
         # iteration 0: ballistic pass (Sigma_scat = 0)
         self.run_batches(out, full_blocks=fb, scat_R=self.scat_R, scat_L=self.scat_L)
 
-        def one_iteration(stream=None):
+        def update(stream=None):
             N.negf_scba_selfenergy(self.ctx, out["GR"], out["GL"], self.slab_stride, self.w_k, wl.D_ac, wl.M_op,
                                    wl.shift, wl.n_bose, self.scat_R, self.scat_L, None, stream=stream)
+
+        def solve(stream=None):
             self.run_batches(out, full_blocks=fb, scat_R=self.scat_R, scat_L=self.scat_L, stream=stream)
+
+        def one_iteration(stream=None):
+            update(stream)
+            solve(stream)
+
+        def capture(fn):
+            g = torch.cuda.CUDAGraph()
+            s = torch.cuda.Stream()
+            s.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(s):
+                torch.cuda.synchronize()
+            with torch.cuda.graph(g, stream=s):
+                fn(stream=s)
+            torch.cuda.current_stream().wait_stream(s)
+            return g
+
+        if tol is not None:
+            run_u, run_s = update, solve
+            if graph:
+                gu, gs = capture(update), capture(solve)
+                run_u, run_s = (lambda: gu.replay()), (lambda: gs.replay())
+            hist = []
+            for i in range(max(n_iter, 1)):
+                run_u()
+                hist += N.negf_scba_history(self.ctx, 1)      # waits for the update
+                if hist[-1] < tol or i == max(n_iter, 1) - 1:
+                    break
+                run_s()
+                if progress:
+                    torch.cuda.synchronize(self.device)
+                    progress(i + 2, n_iter)
+            self.scba_out = out
+            return out, hist
 
         if n_iter <= 1 or not graph:
             for i in range(n_iter - 1):
@@ -542,14 +582,7 @@ class RGFSolver:
                     torch.cuda.synchronize(self.device)
                     progress(i + 2, n_iter)
         else:
-            g = torch.cuda.CUDAGraph()
-            s = torch.cuda.Stream()
-            s.wait_stream(torch.cuda.current_stream())
-            with torch.cuda.stream(s):
-                torch.cuda.synchronize()
-            with torch.cuda.graph(g, stream=s):
-                one_iteration(stream=s)
-            torch.cuda.current_stream().wait_stream(s)
+            g = capture(one_iteration)
             # the residuals stay on the device: no host read between replays
             for i in range(n_iter - 1):
                 g.replay()

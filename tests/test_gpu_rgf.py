@@ -266,6 +266,41 @@ def test_scba_matches_oracle(graph):
     assert np.allclose(hist, ref["hist"], rtol=1e-8, atol=1e-14)
 
 
+@pytest.mark.parametrize("graph", [True, False])
+def test_scba_to_tolerance_matches_oracle(graph):
+    """The Born loop run to a residual tolerance (at most 10 updates) stops at
+    the oracle's update: with the tolerance between the third and fourth
+    residuals of a fixed 4-update oracle run, it makes exactly 4 updates and
+    returns that run's self-energies, diagonals and residuals (the update and
+    the solve as two graphs with one residual read between them)."""
+    _say(f"scba to tolerance, graph={graph}")
+    wl = make_workload("C3", n_slab=4, n_e=40, n_k=2, n_z=2, n_y=1)
+    wl.D_ac, wl.M_op = 0.02, 0.03
+    wl.eta = 1e-3
+    ref = O.scba(wl, 4)
+    h = ref["hist"]
+    assert h[0] > h[1] > h[2] > h[3] > 0
+    tol = float(np.sqrt(h[2] * h[3]))
+    s = _solver(wl, capacity=23)
+    out, hist = s.scba(n_iter=10, graph=graph, tol=tol)
+    torch.cuda.synchronize()
+    assert s.status() == 0
+    assert len(hist) == 4, hist
+    assert np.allclose(hist, h, rtol=1e-8, atol=1e-14)
+    assert _rel(s.scat_R.cpu().numpy(), ref["sigR"]) < TOL
+    assert _rel(s.scat_L.cpu().numpy(), ref["sigL"]) < TOL
+    GR = out["GR"].cpu().numpy().reshape(wl.n_k, wl.n_e, -1, wl.nb)
+    GL = out["GL"].cpu().numpy().reshape(wl.n_k, wl.n_e, -1, wl.nb)
+    assert _rel(GR, ref["GRd"]) < TOL
+    assert _rel(GL, ref["GLd"]) < TOL
+    # a tolerance no update reaches: all n_iter updates, as the fixed count
+    out2, hist2 = s.scba(n_iter=3, graph=graph, tol=1e-30)
+    ref3 = O.scba(wl, 3)
+    torch.cuda.synchronize()
+    assert len(hist2) == 3 and np.allclose(hist2, ref3["hist"], rtol=1e-8, atol=1e-14)
+    assert _rel(s.scat_R.cpu().numpy(), ref3["sigR"]) < TOL
+
+
 @pytest.mark.parametrize("graph", [False, True])
 def test_two_lanes_match_one_lane(graph):
     """Batches spread over two contexts and streams give the results of one
