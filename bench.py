@@ -131,6 +131,40 @@ def cpu_baseline(wl, max_points=16, budget_s=15.0, seed=0):
                       f"decimations, {dt:.1f} s on the host"}
 
 
+def inverse_record(N, solver, nb, reps=5):
+    """The batched block inverse alone (the recursion's other dense kernel) on
+    the step's context: its tuned shapes, its batch capacity, block nb; random
+    complex blocks with nb on the diagonal; HIP events on the launch stream,
+    median of `reps` launches.  Run after the timed region (it overwrites the
+    workspace)."""
+    import numpy as np
+    import torch
+    cap = solver.capacity
+    g = torch.Generator(device="cuda").manual_seed(nb)
+    A = torch.randn((cap, nb, nb), dtype=torch.complex128, device="cuda", generator=g)
+    A += nb * torch.eye(nb, dtype=torch.complex128, device="cuda")
+    W, C = torch.empty_like(A), torch.empty_like(A)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ms = []
+    for r in range(reps + 1):
+        W.copy_(A)
+        e0.record(s)
+        N.negf_zinv_batched(solver.ctx, W, C, stream=s)
+        e1.record(s)
+        torch.cuda.synchronize()
+        if r:
+            ms.append(e0.elapsed_time(e1))
+    t = float(np.median(ms))
+    tf = 8.0 * nb ** 3 * cap / (t * 1e-3) / 1e12
+    del A, W, C
+    torch.cuda.empty_cache()
+    return {"kernel": "batched block inverse (negf::gj_panel + negf::gj_update)", "block": nb, "batch": cap,
+            "ms": t, "achieved": tf, "peak": 78.6, "unit": "TFLOP/s", "frac": tf / 78.6,
+            "flops": "8 b^3 per inverse (the Gauss-Jordan count, algorithmic)",
+            "note": "standalone on the step's context and shapes, after the timed region"}
+
+
 def kernel_sweep(sizes, dtype_name, reps=10):
     """Rates of the two dense kernels alone: the batched complex GEMM (C = A B,
     counted as 8 n^3 real flops per product) and the batched block inverse
@@ -457,6 +491,8 @@ def main():
                           "store": args.store, "checkpoint_segment": int(np.ceil(np.sqrt(wl.total_slabs))),
                           "workspace_bytes_per_point": ws / solver.capacity,
                           "grad_norm": float(torch.linalg.norm(g))}
+    if args.precision == "fp64" and wl.nb >= 64:
+        res["inverse"] = inverse_record(N, solver, wl.nb)
     if args.workload in ("C2", "C4") and args.precision == "mixed":
         # per-sample density and current error of the mixed path against the FP64
         # GPU path (outside the timed region)
